@@ -1,0 +1,241 @@
+/*
+ * tfstat — transient F-statistic maps on AMD MI355X (gfx950).
+ *
+ * C ABI of the library.  The method is the atoms-based transient
+ * F-statistic of Keitel & Ashton (arXiv:1805.05652):
+ *
+ *   - Section 2 (eq. winrect, eq. winexp) defines the rectangular window
+ *     (1 on [t0, t0 + tau]) and the exponential window
+ *     (exp(-(t - t0)/tau) on [t0, t0 + 3 tau]);
+ *   - section 2 (eq. F_FaFb) gives F from the windowed antenna sums A, B, C,
+ *     their determinant D = A B - C^2 and the windowed data sums F_a, F_b;
+ *   - section 2 (eq. Fmn) defines the transient map F_mn over a grid of start
+ *     times t0_m and durations tau_n;
+ *   - section 3 states the inputs: per-SFT vectors a^2, b^2, ab (real) and
+ *     F_a, F_b (complex), a window type and a {t0, tau} grid;
+ *   - the footnote of appendix A names the marginalised Bayes factor over
+ *     the map, whose exponent is F (eq. F_OSG).
+ *
+ * Conventions (where the paper leaves the details open):
+ *   - A window holds the SFTs whose START time t_j satisfies
+ *     t0 <= t_j < t0 + tau (rect) or t0 <= t_j < t0 + 3 tau (exp); the
+ *     decision is made in integer seconds.
+ *   - A, B, C use weights w^2 and F_a, F_b use weights w.
+ *   - Windows past the end of the data are truncated (appendix A), never
+ *     renormalised; the full n_t0 x n_tau map is still produced.
+ *   - A cell with D <= 1e-10 * A * B (empty, single-SFT or rank-one window)
+ *     has 2F = 0.
+ *   - logB = ln( (1/(n_t0 n_tau)) * sum_mn exp(F_mn) ), with F = 2F/2 and a
+ *     flat prior over the grid cells; degenerate cells count with F = 0.
+ *   - The argmax is the first maximum of 2F in row-major (m, n) order.
+ *
+ * Memory and threading:
+ *   - Host pointers passed in are borrowed for the duration of the call.
+ *   - Device memory for atoms and workspaces is sub-allocated from the arena
+ *     the caller hands to tfstat_ctx_create; the library itself calls no
+ *     device allocator.  The arena and the stream must outlive the context.
+ *   - tfstat_fmap and tfstat_logB are synchronous on the context's stream.
+ *   - tfstat_submit / tfstat_poll / tfstat_cancel are thread-safe; other
+ *     calls on one context must not run concurrently with each other.
+ *   - Results are deterministic for a given (atoms, window, precision).
+ *
+ * Errors: every function returns a tfstat_status; 0 is success.  On error no
+ * output is written and tfstat_last_error() describes the failure (the
+ * message is thread-local and valid until the next call on that thread).
+ */
+#ifndef TFSTAT_H
+#define TFSTAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TFSTAT_OK = 0,
+    TFSTAT_E_INVAL = -1,      /* bad argument (null pointer, bad enum, size) */
+    TFSTAT_E_GRID = -2,       /* timestamps off the slot grid, bad t0/tau grid */
+    TFSTAT_E_NOMEM = -3,      /* the arena cannot hold the request */
+    TFSTAT_E_DEVICE = -4,     /* a HIP runtime call failed */
+    TFSTAT_E_BUSY = -5,       /* serving queue full */
+    TFSTAT_E_NOTFOUND = -6,   /* unknown atoms id or ticket */
+    TFSTAT_E_CANCELLED = -7   /* the ticket was cancelled */
+} tfstat_status;
+
+typedef enum {
+    TFSTAT_WIN_RECT = 0,      /* eq. winrect */
+    TFSTAT_WIN_EXP = 1        /* eq. winexp, cut off at 3 tau */
+} tfstat_window_type;
+
+/*
+ * Arithmetic of the windowed sums.  A, B, C, D and F are FP64 in every mode.
+ *   FP64   : F_a, F_b sums in FP64.
+ *   FP32   : F_a, F_b sums in FP32 (the paper's single precision).
+ *   BF16X3 : F_a, F_b sums on bf16 matrix cores with split hi + lo operands
+ *            (three products) and FP32 accumulation; exponential windows of
+ *            several bins only, other requests fall back to FP32.
+ * Rectangular windows use FP64 prefix sums in every mode.
+ */
+typedef enum {
+    TFSTAT_PREC_FP64 = 0,
+    TFSTAT_PREC_FP32 = 1,
+    TFSTAT_PREC_BF16X3 = 2
+} tfstat_precision;
+
+/*
+ * Search grid (eq. Fmn; section 3 allows gaps and resolutions other than
+ * T_sft).  All times are integer seconds.  The start times are
+ * t0_list[m] when t0_list is non-null, else t0_min + m * dt0 (dt0 >= 1);
+ * likewise for tau.  Both sequences must be strictly increasing and every
+ * tau must be >= 1; otherwise TFSTAT_E_GRID.
+ */
+typedef struct {
+    int32_t type;             /* tfstat_window_type */
+    int32_t n_t0;             /* >= 1 */
+    int32_t n_tau;            /* >= 1 */
+    int32_t reserved;         /* must be 0 */
+    int64_t t0_min, dt0;
+    int64_t tau_min, dtau;
+    const int64_t *t0_list;   /* optional, [n_t0] host memory */
+    const int64_t *tau_list;  /* optional, [n_tau] host memory */
+} tfstat_window;
+
+/*
+ * Atoms of one candidate (section 2: {a_j, b_j, F_aj, F_bj} per SFT j,
+ * shipped as a^2, b^2, ab and complex F_a, F_b per section 3).  All host
+ * memory.  Timestamps are SFT start times, strictly increasing, each equal
+ * to timestamps[0] + k * t_sft for an integer k (SFTs on a common slot grid;
+ * gaps allowed), else TFSTAT_E_GRID.  The antenna atoms are shared by all
+ * frequency bins; fa and fb hold [n_bins][n_sft][2] interleaved (re, im).
+ */
+typedef struct {
+    int32_t n_sft;            /* >= 1 */
+    int32_t n_bins;           /* >= 1 */
+    int64_t t_sft;            /* SFT length in seconds, >= 1 */
+    const int64_t *timestamps;
+    const double *a2, *b2, *ab;
+    const double *fa, *fb;
+} tfstat_atoms_desc;
+
+/* Per-bin result of one map (appendix A footnote; eq. Fmn). */
+typedef struct {
+    double max2F;             /* largest 2F over the map */
+    double logB;              /* marginalised log Bayes factor, see above */
+    int64_t t0, tau;          /* grid values at the argmax */
+    int32_t m, n;             /* argmax indices */
+} tfstat_bin_result;
+
+typedef struct tfstat_ctx tfstat_ctx;
+typedef uint64_t tfstat_atoms_id;
+typedef uint64_t tfstat_ticket;
+
+/*
+ * Creates a context on HIP device `device`.  `arena_dev` is device memory of
+ * `arena_bytes` bytes (e.g. a torch tensor's storage), 256-byte aligned,
+ * which the context sub-allocates; `hip_stream` is a hipStream_t (may be
+ * null for the null stream) on which every synchronous call runs.
+ * Errors: E_INVAL (null out, unaligned arena, arena under 1 MiB),
+ * E_DEVICE (bad device).
+ */
+int tfstat_ctx_create(int device, void *arena_dev, size_t arena_bytes,
+                      void *hip_stream, tfstat_ctx **out);
+
+/* Waits for in-flight work, then releases host resources.  Atoms ids die. */
+int tfstat_ctx_destroy(tfstat_ctx *ctx);
+
+/*
+ * Copies one candidate's atoms to the device and keeps them resident (as
+ * zero-filled slots on the T_sft grid) until tfstat_atoms_free.
+ * Errors: E_INVAL, E_GRID (see tfstat_atoms_desc), E_NOMEM, E_DEVICE.
+ */
+int tfstat_atoms_upload(tfstat_ctx *ctx, const tfstat_atoms_desc *desc,
+                        tfstat_atoms_id *out);
+
+/* Releases resident atoms.  E_NOTFOUND for an unknown id, E_BUSY while a
+ * submitted request still uses them. */
+int tfstat_atoms_free(tfstat_ctx *ctx, tfstat_atoms_id id);
+
+/* Number of slots K and bins of resident atoms. */
+int tfstat_atoms_info(tfstat_ctx *ctx, tfstat_atoms_id id, int32_t *n_slots,
+                      int32_t *n_bins);
+
+/*
+ * Computes the transient F-statistic map of every bin of the atoms over the
+ * window grid (eq. Fmn with eq. F_FaFb) and its per-bin results.
+ *   twoF_dev  optional device pointer, float [n_bins][n_t0][n_tau]
+ *             row-major, receives 2F; pass null to skip the map.
+ *   res_host  host array of n_bins results.
+ * Synchronous on the context stream.
+ * Errors: E_INVAL, E_GRID, E_NOTFOUND, E_NOMEM (workspace), E_DEVICE.
+ */
+int tfstat_fmap(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win,
+                int32_t precision, float *twoF_dev, tfstat_bin_result *res_host);
+
+/*
+ * Marginalised log Bayes factor of existing 2F maps (appendix A footnote):
+ * logB = ln((1/(n_t0 n_tau)) sum exp(2F/2)), max-shifted, for each of
+ * n_maps maps of twoF_dev (device, float [n_maps][n_t0][n_tau]).
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE.
+ */
+int tfstat_logB(tfstat_ctx *ctx, const float *twoF_dev, int32_t n_maps,
+                int32_t n_t0, int32_t n_tau, double *logB_host);
+
+/*
+ * Serving: queues a map request over resident atoms and returns a ticket at
+ * once.  Requests run concurrently on the device as workspace memory and
+ * worker slots allow (admission by arena footprint); each result equals the
+ * one tfstat_fmap gives for the same arguments.  No map is materialised.
+ * Errors: E_INVAL, E_GRID, E_NOTFOUND, E_NOMEM (could never fit),
+ * E_BUSY (queue full).
+ */
+int tfstat_submit(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win,
+                  int32_t precision, tfstat_ticket *out);
+
+/*
+ * Non-blocking completion check.  *done is set to 1 and res_host (n_bins
+ * results) is written when the request finished; the ticket is then
+ * retired.  Returns the request's own error if it failed, E_CANCELLED for a
+ * cancelled ticket, E_NOTFOUND for an unknown or retired ticket.
+ */
+int tfstat_poll(tfstat_ctx *ctx, tfstat_ticket t, tfstat_bin_result *res_host,
+                int *done);
+
+/* Cancels a queued request (a running one completes, its result dropped). */
+int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t);
+
+/*
+ * Per-kernel timing.  When enabled, the context brackets each kernel launch
+ * with HIP events on its stream; tfstat_profile_read returns, for kernel
+ * class `kind` (see tfstat_kernel_kind), the number of launches and their
+ * summed device time in milliseconds since the last reset.
+ */
+typedef enum {
+    TFSTAT_K_UPLOAD = 0,      /* slot planes from uploaded atoms */
+    TFSTAT_K_WEIGHTS = 1,     /* exponential weight tables */
+    TFSTAT_K_EXP = 2,         /* exponential-window sums + finalize (VALU) */
+    TFSTAT_K_SCAN = 3,        /* rectangular prefix sums */
+    TFSTAT_K_RECT = 4,        /* rectangular cells + finalize */
+    TFSTAT_K_MERGE = 5,       /* per-bin reduction merge */
+    TFSTAT_K_MFMA = 6,        /* exponential F_a, F_b on matrix cores */
+    TFSTAT_K_ABC = 7,         /* exponential A, B, C (FP64) */
+    TFSTAT_K_COUNT = 8
+} tfstat_kernel_kind;
+
+int tfstat_profile_enable(tfstat_ctx *ctx, int on);
+int tfstat_profile_read(tfstat_ctx *ctx, int32_t kind, int64_t *launches,
+                        double *total_ms);
+int tfstat_profile_reset(tfstat_ctx *ctx);
+
+/* Thread-local message for the last failing call on this thread. */
+const char *tfstat_last_error(void);
+
+/* Library version string. */
+const char *tfstat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFSTAT_H */

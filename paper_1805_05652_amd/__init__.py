@@ -1,0 +1,209 @@
+"""tfstat: transient F-statistic maps on AMD MI355X.
+
+Thin Python binding of the C ABI in include/tfstat.h (libtfstat.so).  Every
+step of the map (slot planes, weight tables, windowed sums, D, 2F,
+reductions) runs in the library's HIP kernels; this module only converts
+arguments.  PyTorch supplies the device arena and the stream.
+
+Method: Keitel & Ashton, arXiv:1805.05652 (section 2: windows and F from
+windowed atom sums; section 3: the atoms-plus-grid inputs and the two window
+kernels; appendix A footnote: the marginalised Bayes factor).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import TfstatError  # noqa: F401
+
+PRECISIONS = {"fp64": _abi.PREC_FP64, "fp32": _abi.PREC_FP32, "bf16x3": _abi.PREC_BF16X3}
+WINDOWS = {"rect": _abi.WIN_RECT, "exp": _abi.WIN_EXP}
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+class _WindowArgs:
+    """Keeps the window struct and its backing arrays alive for a call."""
+
+    def __init__(self, kind, t0, tau, t0_regular=None, tau_regular=None):
+        self.t0 = np.ascontiguousarray(t0, dtype=np.int64)
+        self.tau = np.ascontiguousarray(tau, dtype=np.int64)
+        w = _abi.Window()
+        w.type = WINDOWS[kind] if isinstance(kind, str) else int(kind)
+        w.n_t0 = int(self.t0.shape[0])
+        w.n_tau = int(self.tau.shape[0])
+        w.reserved = 0
+        if t0_regular is not None:
+            w.t0_min, w.dt0 = int(t0_regular[0]), int(t0_regular[1])
+            w.t0_list = None
+        else:
+            w.t0_list = self.t0.ctypes.data
+        if tau_regular is not None:
+            w.tau_min, w.dtau = int(tau_regular[0]), int(tau_regular[1])
+            w.tau_list = None
+        else:
+            w.tau_list = self.tau.ctypes.data
+        self.struct = w
+
+    @classmethod
+    def from_window(cls, win):
+        return cls(win.kind, win.t0, win.tau, getattr(win, "t0_regular", None),
+                   getattr(win, "tau_regular", None))
+
+
+def _results(arr) -> List[dict]:
+    return [dict(max2F=r.max2F, logB=r.logB, t0=int(r.t0), tau=int(r.tau), m=int(r.m), n=int(r.n))
+            for r in arr]
+
+
+class Context:
+    """A library context on one GPU with a device arena owned by a torch tensor."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 1 << 30, stream=None):
+        import torch
+        self._lib = _abi.load()
+        self.device = int(device)
+        self._torch = torch
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda:%d" % self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = ctypes.c_void_p()
+        _abi.check(self._lib.tfstat_ctx_create(self.device, ctypes.c_void_p(self.arena.data_ptr()),
+                                               int(arena_bytes), ctypes.c_void_p(self.stream.cuda_stream),
+                                               ctypes.byref(self._ctx)))
+        self._bins = {}
+
+    # -- lifetime ---------------------------------------------------------------
+    def close(self):
+        if self._ctx:
+            _abi.check(self._lib.tfstat_ctx_destroy(self._ctx))
+            self._ctx = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- atoms -------------------------------------------------------------------
+    def upload(self, timestamps, a2, b2, ab, fa, fb, t_sft: int = 1800) -> int:
+        ts = np.ascontiguousarray(timestamps, dtype=np.int64)
+        a2 = np.ascontiguousarray(a2, dtype=np.float64)
+        b2 = np.ascontiguousarray(b2, dtype=np.float64)
+        ab = np.ascontiguousarray(ab, dtype=np.float64)
+        fa = np.ascontiguousarray(fa, dtype=np.float64)
+        fb = np.ascontiguousarray(fb, dtype=np.float64)
+        if fa.ndim == 2:
+            fa = fa[None]
+            fb = fb[None]
+        n = int(ts.shape[0])
+        if a2.shape != (n,) or b2.shape != (n,) or ab.shape != (n,) or fa.shape[1:] != (n, 2) \
+                or fb.shape != fa.shape:
+            raise ValueError("atom arrays have inconsistent shapes")
+        d = _abi.AtomsDesc()
+        d.n_sft = n
+        d.n_bins = int(fa.shape[0])
+        d.t_sft = int(t_sft)
+        d.timestamps = ts.ctypes.data
+        d.a2, d.b2, d.ab = a2.ctypes.data, b2.ctypes.data, ab.ctypes.data
+        d.fa, d.fb = fa.ctypes.data, fb.ctypes.data
+        out = ctypes.c_uint64()
+        _abi.check(self._lib.tfstat_atoms_upload(self._ctx, ctypes.byref(d), ctypes.byref(out)))
+        self._bins[out.value] = d.n_bins
+        return out.value
+
+    def upload_atoms(self, atoms) -> int:
+        """Uploads a tfsynth.Atoms object."""
+        return self.upload(atoms.timestamps, atoms.a2, atoms.b2, atoms.ab, atoms.fa, atoms.fb,
+                           atoms.t_sft)
+
+    def free(self, atoms_id: int):
+        _abi.check(self._lib.tfstat_atoms_free(self._ctx, ctypes.c_uint64(atoms_id)))
+        self._bins.pop(atoms_id, None)
+
+    def atoms_info(self, atoms_id: int):
+        k = ctypes.c_int32()
+        b = ctypes.c_int32()
+        _abi.check(self._lib.tfstat_atoms_info(self._ctx, ctypes.c_uint64(atoms_id), ctypes.byref(k),
+                                               ctypes.byref(b)))
+        return k.value, b.value
+
+    # -- maps --------------------------------------------------------------------
+    def fmap(self, atoms_id: int, win, precision="fp32", want_map: bool = False,
+             out=None):
+        """Map of every bin over `win` (a tfsynth.Window-like object).
+
+        Returns (per-bin result dicts, 2F map tensor [bins, n_t0, n_tau] or
+        None).  `out` may be a preallocated float32 CUDA tensor for the map.
+        """
+        wa = _WindowArgs.from_window(win)
+        nb = self._bins[atoms_id]
+        res = (_abi.BinResult * nb)()
+        twoF = out
+        if want_map and twoF is None:
+            twoF = self._torch.empty((nb, wa.struct.n_t0, wa.struct.n_tau), dtype=self._torch.float32,
+                                     device="cuda:%d" % self.device)
+        if twoF is not None:
+            if twoF.dtype != self._torch.float32 or not twoF.is_contiguous() or \
+                    twoF.numel() != nb * wa.struct.n_t0 * wa.struct.n_tau:
+                raise ValueError("out must be a contiguous float32 tensor of bins*n_t0*n_tau")
+            ptr = ctypes.c_void_p(twoF.data_ptr())
+        else:
+            ptr = None
+        _abi.check(self._lib.tfstat_fmap(self._ctx, ctypes.c_uint64(atoms_id), ctypes.byref(wa.struct),
+                                         _prec(precision), ptr, res))
+        return _results(res), twoF
+
+    def logB(self, twoF) -> np.ndarray:
+        """logB of each map of a float32 CUDA tensor [n_maps, n_t0, n_tau]."""
+        t = twoF if twoF.dim() == 3 else twoF[None]
+        if t.dtype != self._torch.float32 or not t.is_contiguous():
+            raise ValueError("twoF must be a contiguous float32 tensor")
+        out = np.empty(t.shape[0], dtype=np.float64)
+        _abi.check(self._lib.tfstat_logB(self._ctx, ctypes.c_void_p(t.data_ptr()), int(t.shape[0]),
+                                         int(t.shape[1]), int(t.shape[2]), out.ctypes.data))
+        return out
+
+    # -- serving -------------------------------------------------------------------
+    def submit(self, atoms_id: int, win, precision="fp32") -> int:
+        wa = _WindowArgs.from_window(win)
+        t = ctypes.c_uint64()
+        _abi.check(self._lib.tfstat_submit(self._ctx, ctypes.c_uint64(atoms_id), ctypes.byref(wa.struct),
+                                           _prec(precision), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, n_bins: int) -> Optional[List[dict]]:
+        """Results if the ticket finished (the ticket is then retired), else None."""
+        res = (_abi.BinResult * n_bins)()
+        done = ctypes.c_int()
+        _abi.check(self._lib.tfstat_poll(self._ctx, ctypes.c_uint64(ticket), res, ctypes.byref(done)))
+        return _results(res) if done.value else None
+
+    def cancel(self, ticket: int):
+        _abi.check(self._lib.tfstat_cancel(self._ctx, ctypes.c_uint64(ticket)))
+
+    # -- profiling -----------------------------------------------------------------
+    def profile(self, on: bool = True):
+        _abi.check(self._lib.tfstat_profile_enable(self._ctx, 1 if on else 0))
+
+    def profile_reset(self):
+        _abi.check(self._lib.tfstat_profile_reset(self._ctx))
+
+    def profile_read(self) -> dict:
+        out = {}
+        for k, name in enumerate(_abi.KERNEL_NAMES):
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            _abi.check(self._lib.tfstat_profile_read(self._ctx, k, ctypes.byref(n), ctypes.byref(ms)))
+            out[name] = (n.value, ms.value)
+        return out
+
+
+def version() -> str:
+    return _abi.load().tfstat_version().decode()

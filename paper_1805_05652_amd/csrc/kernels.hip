@@ -1,0 +1,645 @@
+// HIP kernels of the transient F-statistic map for gfx950 (MI355X).
+//
+// Method: Keitel & Ashton, arXiv:1805.05652, section 2 (windows eq. winrect
+// and eq. winexp, F from windowed atom sums eq. F_FaFb, the map eq. Fmn) and
+// section 3 (running-sum reuse for rectangular windows, per-cell sums for
+// exponential windows, D and F evaluated in the kernel).  The marginalised
+// Bayes factor (appendix A footnote) is reduced from per-tile partials.
+//
+// Layout of resident atoms (slot grid, zero-filled gaps, row K all zeros):
+//   abc [K+1][4]          FP64 a^2, b^2, ab, 0
+//   x64 [K+1][bins][4]    FP64 Re Fa, Im Fa, Re Fb, Im Fb
+//   x32 [K+1][bins][4]    FP32 copy of x64
+#include "tfstat_device.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace tfs {
+
+namespace {
+
+constexpr int kLanes = 64;
+constexpr int kWaves = 4;
+constexpr int kThreads = kLanes * kWaves;
+constexpr int kDC = 256;          // band slots staged per round
+constexpr int kSpreadMax = 256;   // max k0 spread of a 64-row tile for LDS staging
+constexpr int kStage = kSpreadMax + kDC;
+
+// ---------------------------------------------------------------------------
+// Reduction state: (F max, sum exp(F - fmax), first index of the max).
+// ---------------------------------------------------------------------------
+struct Red {
+    double f;
+    double s;
+    long long i;
+};
+
+__device__ inline Red red_empty() { return Red{-INFINITY, 0.0, 0x7fffffffffffffffLL}; }
+
+__device__ inline Red red_combine(const Red &a, const Red &b) {
+    Red r;
+    r.f = fmax(a.f, b.f);
+    if (r.f == -INFINITY) return red_empty();
+    const double sa = (a.f == -INFINITY) ? 0.0 : a.s * exp(a.f - r.f);
+    const double sb = (b.f == -INFINITY) ? 0.0 : b.s * exp(b.f - r.f);
+    r.s = sa + sb;
+    r.i = (a.f > b.f) ? a.i : (b.f > a.f) ? b.i : (a.i < b.i ? a.i : b.i);
+    return r;
+}
+
+__device__ inline Red red_wave(Red v) {
+#pragma unroll
+    for (int o = 1; o < kLanes; o <<= 1) {
+        Red w;
+        w.f = __shfl_xor(v.f, o, kLanes);
+        w.s = __shfl_xor(v.s, o, kLanes);
+        w.i = __shfl_xor(v.i, o, kLanes);
+        v = red_combine(v, w);
+    }
+    return v;
+}
+
+// 2F of one cell from windowed sums (eq. F_FaFb), FP64, with the
+// degenerate-window rule.
+__device__ inline double twoF_cell(double A, double B, double C, double far_,
+                                   double fai, double fbr, double fbi) {
+    const double D = A * B - C * C;
+    if (D <= kDegenerateRtol * A * B) return 0.0;
+    const double num = B * (far_ * far_ + fai * fai) + A * (fbr * fbr + fbi * fbi)
+                       - 2.0 * C * (far_ * fbr + fai * fbi);
+    return 2.0 * (num / D);
+}
+
+template <typename T>
+struct Q4 {
+    T x, y, z, w;
+};
+
+__device__ inline Q4<float> load_q4(const float *p) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    return Q4<float>{v.x, v.y, v.z, v.w};
+}
+__device__ inline Q4<double> load_q4(const double *p) {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    return Q4<double>{a.x, a.y, b.x, b.y};
+}
+
+template <typename XT>
+__device__ inline const XT *xplane(const AtomsView &at);
+template <>
+__device__ inline const float *xplane<float>(const AtomsView &at) { return at.x32; }
+template <>
+__device__ inline const double *xplane<double>(const AtomsView &at) { return at.x64; }
+
+template <typename XT>
+__device__ inline const XT *wplane(const ExpValuParams &p);
+template <>
+__device__ inline const float *wplane<float>(const ExpValuParams &p) { return p.g32; }
+template <>
+__device__ inline const double *wplane<double>(const ExpValuParams &p) { return p.g64; }
+
+// ---------------------------------------------------------------------------
+// Exponential-window sums and finalize, VALU form.
+//
+// Workgroup = one (64-row t0 tile, R-column tau block) task.  Lane l owns
+// row m = tile*64 + l; the R taus of the block share every atom the lane
+// loads.  Window weights w = exp(-(delta_m + d T)/tau_n) factor into a
+// per-row scale s = exp(-delta_m/tau) and a table g_n[d] = exp(-d T/tau_n)
+// that is uniform across the wave (scalar loads).  The band d is split into
+// four contiguous quarters per staged chunk, one per wave, and the four
+// partial sums are combined through LDS in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename XT, int R, int BG>
+struct ExpSmem {
+    union {
+        struct {
+            double a2[kStage];
+            double b2[kStage];
+            double ab[kStage];
+            Q4<XT> x[BG][kStage];
+        } stage;
+        struct {
+            double abc[1][R][3][kLanes];
+            XT f[1][R][BG][4][kLanes];
+        } comb;
+    } u;
+    Red wred[kWaves][BG];
+};
+
+template <typename XT, int R, int BG>
+struct ExpAcc {
+    double A[R], B[R], C[R];
+    XT f[R][BG][4];
+
+    __device__ inline void zero() {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            A[r] = 0.0; B[r] = 0.0; C[r] = 0.0;
+#pragma unroll
+            for (int b = 0; b < BG; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[r][b][c] = XT(0);
+        }
+    }
+
+    __device__ inline void step(const XT *__restrict__ gw, const double *__restrict__ gq,
+                                double a2, double b2, double ab, const Q4<XT> *x) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double q = gq[r];
+            A[r] = fma(q, a2, A[r]);
+            B[r] = fma(q, b2, B[r]);
+            C[r] = fma(q, ab, C[r]);
+            const XT g = gw[r];
+#pragma unroll
+            for (int b = 0; b < BG; ++b) {
+                f[r][b][0] = fma(g, x[b].x, f[r][b][0]);
+                f[r][b][1] = fma(g, x[b].y, f[r][b][1]);
+                f[r][b][2] = fma(g, x[b].z, f[r][b][2]);
+                f[r][b][3] = fma(g, x[b].w, f[r][b][3]);
+            }
+        }
+    }
+
+    template <typename SM>
+    __device__ inline void store(SM &sm, int j, int lane) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            sm.u.comb.abc[j][r][0][lane] = A[r];
+            sm.u.comb.abc[j][r][1][lane] = B[r];
+            sm.u.comb.abc[j][r][2][lane] = C[r];
+#pragma unroll
+            for (int b = 0; b < BG; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sm.u.comb.f[j][r][b][c][lane] = f[r][b][c];
+        }
+    }
+
+    template <typename SM>
+    __device__ inline void add(const SM &sm, int j, int lane) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            A[r] += sm.u.comb.abc[j][r][0][lane];
+            B[r] += sm.u.comb.abc[j][r][1][lane];
+            C[r] += sm.u.comb.abc[j][r][2][lane];
+#pragma unroll
+            for (int b = 0; b < BG; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[r][b][c] += sm.u.comb.f[j][r][b][c][lane];
+        }
+    }
+};
+
+template <typename XT, int R, int BG>
+__global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
+    __shared__ ExpSmem<XT, R, BG> sm;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kLanes - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    // XCD-aware task order: workgroup b runs on XCD b % 8.  Blocks of tau
+    // (sorted largest band first) are dealt round-robin to the XCDs and all
+    // row tiles of a block stay on one XCD, so its weight table is fetched
+    // into one L2 only.
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7;
+    const int slot = bid >> 3;
+    const int q = (slot / p.n_row_tiles) * 8 + xcd;
+    if (q >= p.n_blocks) return;
+    const int row_tile = slot % p.n_row_tiles;
+    const int nb = p.blk_order[q];
+    const int tile = q * p.n_row_tiles + row_tile;
+    const int bin0 = blockIdx.y * BG;
+    const int n_bins = p.at.n_bins;
+    const int K = p.at.K;
+
+    const int m_first = row_tile * kLanes;
+    const int m_last = min(m_first + kLanes - 1, p.n_t0 - 1);
+    const bool row_ok = m_first + lane < p.n_t0;
+    const int m = min(m_first + lane, p.n_t0 - 1);
+    const RowPlan rp = p.rows[m];
+    const int k_lo = p.rows[m_first].k0;
+    const int k_hi = p.rows[m_last].k0;
+    const int spread = k_hi - k_lo;
+    const int lblk = p.lblk[nb];
+    const int dwg = min(lblk, K - k_lo);
+    const int64_t off = p.blk_off[nb];
+    const XT *__restrict__ gw_base = wplane<XT>(p) + off;
+    const double *__restrict__ gq_base = p.gsq + off;
+    const XT *__restrict__ xg = xplane<XT>(p.at);
+    const double *__restrict__ abc = p.at.abc;
+
+    ExpAcc<XT, R, BG> acc;
+    acc.zero();
+
+    if (spread <= kSpreadMax) {
+        const int my = rp.k0 - k_lo;
+        for (int d0 = 0; d0 < dwg; d0 += kDC) {
+            const int dn = min(kDC, dwg - d0);
+            const int width = spread + dn;
+            __syncthreads();
+            for (int i = tid; i < width; i += kThreads) {
+                const int k = k_lo + d0 + i;
+                const bool in = (unsigned)k < (unsigned)K;
+                double a2 = 0.0, b2 = 0.0, ab = 0.0;
+                if (in) {
+                    const double2 v = *reinterpret_cast<const double2 *>(abc + (size_t)k * 4);
+                    a2 = v.x;
+                    b2 = v.y;
+                    ab = abc[(size_t)k * 4 + 2];
+                }
+                sm.u.stage.a2[i] = a2;
+                sm.u.stage.b2[i] = b2;
+                sm.u.stage.ab[i] = ab;
+#pragma unroll
+                for (int b = 0; b < BG; ++b) {
+                    Q4<XT> x{XT(0), XT(0), XT(0), XT(0)};
+                    if (in && bin0 + b < n_bins)
+                        x = load_q4(xg + ((size_t)k * n_bins + bin0 + b) * 4);
+                    sm.u.stage.x[b][i] = x;
+                }
+            }
+            __syncthreads();
+            const int per = (dn + kWaves - 1) / kWaves;
+            const int ds = wave * per;
+            const int de = min(dn, ds + per);
+            for (int dd = ds; dd < de; ++dd) {
+                const int li = my + dd;
+                Q4<XT> x[BG];
+#pragma unroll
+                for (int b = 0; b < BG; ++b) x[b] = sm.u.stage.x[b][li];
+                const int d = d0 + dd;
+                acc.step(gw_base + (size_t)d * R, gq_base + (size_t)d * R,
+                         sm.u.stage.a2[li], sm.u.stage.b2[li], sm.u.stage.ab[li], x);
+            }
+        }
+    } else {
+        // Rows too far apart to stage one band: read through the caches.
+        const int per = (max(dwg, 0) + kWaves - 1) / kWaves;
+        const int ds = wave * per;
+        const int de = min(dwg, ds + per);
+        for (int d = ds; d < de; ++d) {
+            const int k = rp.k0 + d;
+            const int kk = ((unsigned)k < (unsigned)K) ? k : K;   // row K is zero
+            const double2 v = *reinterpret_cast<const double2 *>(abc + (size_t)kk * 4);
+            const double ab = abc[(size_t)kk * 4 + 2];
+            Q4<XT> x[BG];
+#pragma unroll
+            for (int b = 0; b < BG; ++b)
+                x[b] = (bin0 + b < n_bins) ? load_q4(xg + ((size_t)kk * n_bins + bin0 + b) * 4)
+                                           : Q4<XT>{XT(0), XT(0), XT(0), XT(0)};
+            acc.step(gw_base + (size_t)d * R, gq_base + (size_t)d * R, v.x, v.y, ab, x);
+        }
+    }
+
+    // Combine the four waves' partial sums as (((w3 + w2) + w1) + w0) through
+    // one LDS slot; the total is left in that slot.
+    __syncthreads();
+    if (wave == kWaves - 1) acc.store(sm, 0, lane);
+#pragma unroll 1
+    for (int w = kWaves - 2; w >= 0; --w) {
+        __syncthreads();
+        if (wave == w) {
+            acc.add(sm, 0, lane);
+            acc.store(sm, 0, lane);
+        }
+    }
+    __syncthreads();
+
+    // Finalize, one tau column per wave at a time: exact band end, row
+    // scale, D, 2F, map, reductions.
+    const int64_t T = p.at.t_sft;
+    Red red[BG];
+#pragma unroll
+    for (int b = 0; b < BG; ++b) red[b] = red_empty();
+#pragma unroll 1
+    for (int r = wave; r < R; r += kWaves) {
+        const int n = nb * R + r;
+        const bool ok = row_ok && n < p.n_tau;
+        const int nn = min(n, p.n_tau - 1);
+        const int64_t tau = p.tau[nn];
+        const int64_t span = 3 * tau;
+        const int64_t lmn = span > rp.delta ? (span - rp.delta + T - 1) / T : 0;
+        const int lc = p.lcol[nn];
+        double A = sm.u.comb.abc[0][r][0][lane];
+        double B = sm.u.comb.abc[0][r][1][lane];
+        double C = sm.u.comb.abc[0][r][2][lane];
+        double f[BG][4];
+#pragma unroll
+        for (int b = 0; b < BG; ++b)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) f[b][c] = (double)sm.u.comb.f[0][r][b][c][lane];
+        // The table holds the band of a row with delta = 0; a row with
+        // delta > 0 may end one slot earlier.  Remove such terms exactly as
+        // they were added.
+        for (int64_t d = lmn; d < lc; ++d) {
+            const int64_t k = (int64_t)rp.k0 + d;
+            if (k < 0 || k >= K) continue;
+            const double qd = gq_base[d * R + r];
+            const XT gd = gw_base[d * R + r];
+            A -= qd * abc[k * 4 + 0];
+            B -= qd * abc[k * 4 + 1];
+            C -= qd * abc[k * 4 + 2];
+#pragma unroll
+            for (int b = 0; b < BG; ++b) {
+                if (bin0 + b >= n_bins) continue;
+                const Q4<XT> x = load_q4(xg + ((size_t)k * n_bins + bin0 + b) * 4);
+                f[b][0] -= (double)(gd * x.x);
+                f[b][1] -= (double)(gd * x.y);
+                f[b][2] -= (double)(gd * x.z);
+                f[b][3] -= (double)(gd * x.w);
+            }
+        }
+        if (rp.delta != 0) {
+            const double s = exp(-(double)rp.delta / (double)tau);
+            const double s2 = s * s;
+            A *= s2; B *= s2; C *= s2;
+#pragma unroll
+            for (int b = 0; b < BG; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[b][c] *= s;
+        }
+#pragma unroll
+        for (int b = 0; b < BG; ++b) {
+            const int bin = bin0 + b;
+            if (!ok || bin >= n_bins) continue;
+            const double v = twoF_cell(A, B, C, f[b][0], f[b][1], f[b][2], f[b][3]);
+            if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
+            const Red cell{0.5 * v, 1.0, (long long)m * p.n_tau + n};
+            red[b] = red_combine(red[b], cell);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < BG; ++b) {
+        const Red w = red_wave(red[b]);
+        if (lane == 0) sm.wred[wave][b] = w;
+    }
+    __syncthreads();
+    if (tid < BG && bin0 + tid < n_bins) {
+        Red t = sm.wred[0][tid];
+        for (int w = 1; w < kWaves; ++w) t = red_combine(t, sm.wred[w][tid]);
+        Partial &o = p.part[(size_t)(bin0 + tid) * p.n_tiles + tile];
+        o.fmax = t.f;
+        o.s = t.s;
+        o.idx = t.i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exponential weight tables g_n[d] = exp(-d T / tau_n) for d < lcol[n],
+// blocked [block][d][R] and zero-padded to the block's longest band.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void weights_kernel(WeightParams p) {
+    const int nb = blockIdx.y;
+    const int R = p.R;
+    const int64_t cnt = (int64_t)p.lblk[nb] * R;
+    const int64_t off = p.blk_off[nb];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < cnt;
+         i += (int64_t)gridDim.x * 256) {
+        const int64_t d = i / R;
+        const int r = (int)(i - d * R);
+        const int n = nb * R + r;
+        double g = 0.0;
+        if (n < p.n_tau && d < p.lcol[n])
+            g = exp(-(double)(d * p.t_sft) / (double)p.tau[n]);
+        p.g32[off + i] = (float)g;
+        p.gsq[off + i] = g * g;
+        if (p.want64) p.g64[off + i] = g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 plane of the data atoms.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void build_x32_kernel(const double *x64, float *x32, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        x32[i] = (float)x64[i];
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix sums over slots (rectangular windows, section 3's running
+// sums turned into O(1) differences per cell).  out[0][c] = 0,
+// out[k+1][c] = out[k][c] + in[k][c].  Lane = channel, wave = slot segment.
+// ---------------------------------------------------------------------------
+constexpr int kScanWaves = 16;
+
+__global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(const double *__restrict__ in,
+                                                               int64_t stride, double *__restrict__ out,
+                                                               int32_t K, int32_t C) {
+    __shared__ double tot[kScanWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    const int seg = (K + kScanWaves - 1) / kScanWaves;
+    const int kb = min(K, wave * seg);
+    const int ke = min(K, kb + seg);
+    double sum = 0.0;
+    if (c < C)
+        for (int k = kb; k < ke; ++k) sum += in[(size_t)k * stride + c];
+    tot[wave][lane] = sum;
+    __syncthreads();
+    double run = 0.0;
+    for (int w = 0; w < wave; ++w) run += tot[w][lane];
+    if (c < C) {
+        if (wave == 0) out[c] = 0.0;
+        for (int k = kb; k < ke; ++k) {
+            run += in[(size_t)k * stride + c];
+            out[(size_t)(k + 1) * C + c] = run;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rectangular-window cells: window sums as prefix differences, finalize,
+// optional map, per-tile reduction.  Block = 4 rows x 64 taus of one bin.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void rect_kernel(RectParams p) {
+    __shared__ Red wred[kWaves];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
+    const int m = blockIdx.y * kWaves + wave;
+    const int bin = blockIdx.z;
+    const bool ok = n < p.n_tau && m < p.n_t0;
+    const int nn = min(n, p.n_tau - 1);
+    const int mm = min(m, p.n_t0 - 1);
+    const RowPlan rp = p.rows[mm];
+    const int64_t tau = p.tau[nn];
+    const int64_t T = p.t_sft;
+    const int64_t L = tau > rp.delta ? (tau - rp.delta + T - 1) / T : 0;
+    const int64_t K = p.K;
+    const int64_t lo = min(max((int64_t)rp.k0, (int64_t)0), K);
+    const int64_t hi = min(max((int64_t)rp.k0 + L, (int64_t)0), K);
+    const double *a_hi = p.pabc + hi * 4;
+    const double *a_lo = p.pabc + lo * 4;
+    const double A = a_hi[0] - a_lo[0];
+    const double B = a_hi[1] - a_lo[1];
+    const double C = a_hi[2] - a_lo[2];
+    const int64_t CW = (int64_t)p.n_bins * 4;
+    const double *x_hi = p.px + hi * CW + bin * 4;
+    const double *x_lo = p.px + lo * CW + bin * 4;
+    const double v = twoF_cell(A, B, C, x_hi[0] - x_lo[0], x_hi[1] - x_lo[1],
+                               x_hi[2] - x_lo[2], x_hi[3] - x_lo[3]);
+    Red r = red_empty();
+    if (ok) {
+        if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
+        r = Red{0.5 * v, 1.0, (long long)m * p.n_tau + n};
+    }
+    r = red_wave(r);
+    if (lane == 0) wred[wave] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Red t = wred[0];
+        for (int w = 1; w < kWaves; ++w) t = red_combine(t, wred[w]);
+        Partial &o = p.part[(size_t)bin * p.n_tiles + blockIdx.y * p.n_tiles_n + blockIdx.x];
+        o.fmax = t.f;
+        o.s = t.s;
+        o.idx = t.i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-map merge of tile partials in a fixed order -> max 2F, argmax, logB.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void merge_kernel(MergeParams p) {
+    __shared__ Red sred[256];
+    const int map = blockIdx.x;
+    const Partial *part = p.part + (size_t)map * p.n_tiles;
+    Red r = red_empty();
+    for (int t = threadIdx.x; t < p.n_tiles; t += 256) {
+        const Partial q = part[t];
+        r = red_combine(r, Red{q.fmax, q.s, q.idx});
+    }
+    sred[threadIdx.x] = r;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sred[threadIdx.x] = red_combine(sred[threadIdx.x], sred[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const Red t = sred[0];
+        BinResultDev o;
+        o.max2F = 2.0 * t.f;
+        o.logB = t.f + log(t.s) - log((double)p.n_cells);
+        o.idx = t.i;
+        p.out[map] = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile partials of an existing FP32 2F map (logB of a stored map).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void map_reduce_kernel(MapReduceParams p) {
+    __shared__ Red wred[kWaves];
+    const int map = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int64_t c0 = (int64_t)tile * p.cells_per_tile;
+    const int64_t c1 = min(p.n_cells, c0 + p.cells_per_tile);
+    const float *src = p.twoF + (size_t)map * p.n_cells;
+    Red r = red_empty();
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) {
+        const double F = 0.5 * (double)src[c];
+        if (F > r.f) {
+            r.s = (r.f == -INFINITY) ? 1.0 : r.s * exp(r.f - F) + 1.0;
+            r.f = F;
+            r.i = c;
+        } else {
+            r.s += exp(F - r.f);
+        }
+    }
+    r = red_wave(r);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wred[wave] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Red t = wred[0];
+        for (int w = 1; w < kWaves; ++w) t = red_combine(t, wred[w]);
+        Partial &o = p.part[(size_t)map * p.n_tiles + tile];
+        o.fmax = t.f;
+        o.s = t.s;
+        o.idx = t.i;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+void exp_valu_config(int prec, int n_bins, int *R, int *BG) {
+    if (prec == 0) {
+        *R = 4;
+        *BG = 1;
+    } else if (n_bins >= 4) {
+        *R = 4;
+        *BG = 4;
+    } else if (n_bins >= 2) {
+        *R = 4;
+        *BG = 2;
+    } else {
+        *R = 8;
+        *BG = 1;
+    }
+}
+
+hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, hipStream_t s) {
+    const int groups = (p.n_blocks + 7) / 8;
+    const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), (unsigned)((p.at.n_bins + BG - 1) / BG));
+    if (prec == 0 && R == 4 && BG == 1)
+        hipLaunchKernelGGL((exp_valu_kernel<double, 4, 1>), grid, dim3(kThreads), 0, s, p);
+    else if (prec == 1 && R == 8 && BG == 1)
+        hipLaunchKernelGGL((exp_valu_kernel<float, 8, 1>), grid, dim3(kThreads), 0, s, p);
+    else if (prec == 1 && R == 4 && BG == 2)
+        hipLaunchKernelGGL((exp_valu_kernel<float, 4, 2>), grid, dim3(kThreads), 0, s, p);
+    else if (prec == 1 && R == 4 && BG == 4)
+        hipLaunchKernelGGL((exp_valu_kernel<float, 4, 4>), grid, dim3(kThreads), 0, s, p);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(const WeightParams &p, int64_t max_per_block, hipStream_t s) {
+    int64_t gx = (max_per_block + 255) / 256;
+    if (gx < 1) gx = 1;
+    if (gx > 4096) gx = 4096;
+    hipLaunchKernelGGL(weights_kernel, dim3((unsigned)gx, (unsigned)p.n_blocks), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_x32(const double *x64, float *x32, int64_t n, hipStream_t s) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(build_x32_kernel, dim3((unsigned)g), dim3(256), 0, s, x64, x32, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const double *in, int64_t stride, double *out, int32_t K, int32_t C,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(scan_kernel, dim3((unsigned)((C + 63) / 64)), dim3(kScanWaves * 64), 0, s,
+                       in, stride, out, K, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_rect(const RectParams &p, hipStream_t s) {
+    const dim3 grid((unsigned)p.n_tiles_n, (unsigned)((p.n_t0 + kWaves - 1) / kWaves),
+                    (unsigned)p.n_bins);
+    hipLaunchKernelGGL(rect_kernel, grid, dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const MergeParams &p, hipStream_t s) {
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)p.n_maps), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_reduce(const MapReduceParams &p, hipStream_t s) {
+    hipLaunchKernelGGL(map_reduce_kernel, dim3((unsigned)p.n_tiles, (unsigned)p.n_maps), dim3(256),
+                       0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace tfs

@@ -1,0 +1,1045 @@
+// Host runtime and C ABI of the tfstat library: device-arena sub-allocator,
+// resident atom store, integer grid planner, job execution on HIP streams,
+// a continuous-batching request loop, and per-kernel timing.
+//
+// The problem statement follows Keitel & Ashton (arXiv:1805.05652),
+// section 3: the inputs are per-SFT atoms plus a window type and a {t0, tau}
+// grid; the output is the transient map F_mn (eq. Fmn) and, per the
+// appendix A footnote, its marginalised Bayes factor.
+#include "../../include/tfstat.h"
+#include "tfstat_device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+struct Failure {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void raise(int code, const std::string &msg) { throw Failure{code, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) raise(TFSTAT_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int64_t floor_div(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
+
+// ---------------------------------------------------------------------------
+// First-fit sub-allocator over the caller's device arena (host bookkeeping
+// only; no device allocation).  256-byte granularity, coalescing frees.
+// ---------------------------------------------------------------------------
+class Arena {
+  public:
+    void init(void *base, size_t size) {
+        base_ = static_cast<char *>(base);
+        size_ = size;
+        free_.clear();
+        used_.clear();
+        free_[0] = size;
+        in_use_ = 0;
+    }
+    void *alloc(size_t bytes) {
+        bytes = round_up(std::max<size_t>(bytes, 1), 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, sz = it->second;
+            free_.erase(it);
+            if (sz > bytes) free_[off + bytes] = sz - bytes;
+            used_[off] = bytes;
+            in_use_ += bytes;
+            return base_ + off;
+        }
+        return nullptr;
+    }
+    void release(void *p) {
+        if (!p) return;
+        const size_t off = static_cast<char *>(p) - base_;
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t sz = u->second;
+        used_.erase(u);
+        in_use_ -= sz;
+        size_t start = off;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && next->first == off + sz) {
+            sz += next->second;
+            free_.erase(next);
+        }
+        auto it = free_.lower_bound(off);
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == off) {
+                start = prev->first;
+                sz += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = sz;
+    }
+    size_t capacity() const { return size_; }
+    size_t in_use() const { return in_use_; }
+    size_t largest_free() const {
+        size_t m = 0;
+        for (auto &kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+
+  private:
+    char *base_ = nullptr;
+    size_t size_ = 0;
+    size_t in_use_ = 0;
+    std::map<size_t, size_t> free_;
+    std::unordered_map<size_t, size_t> used_;
+};
+
+// Pool of pinned host buffers (staging of tables and results).
+class PinnedPool {
+  public:
+    ~PinnedPool() {
+        for (auto &kv : free_) (void)hipHostFree(kv.second);
+    }
+    void *get(size_t bytes, size_t *got) {
+        size_t want = 4096;
+        while (want < bytes) want <<= 1;
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            auto it = free_.lower_bound(want);
+            if (it != free_.end()) {
+                void *p = it->second;
+                *got = it->first;
+                free_.erase(it);
+                return p;
+            }
+        }
+        void *p = nullptr;
+        hip_check(hipHostMalloc(&p, want, hipHostMallocDefault), "hipHostMalloc");
+        *got = want;
+        return p;
+    }
+    void put(void *p, size_t size) {
+        if (!p) return;
+        std::lock_guard<std::mutex> g(mu_);
+        free_.emplace(size, p);
+    }
+
+  private:
+    std::mutex mu_;
+    std::multimap<size_t, void *> free_;
+};
+
+struct AtomsSet {
+    int32_t K = 0, n_bins = 0, n_sft = 0;
+    int64_t T0 = 0, t_sft = 0;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    double *abc = nullptr;
+    double *x64 = nullptr;
+    float *x32 = nullptr;
+    int busy = 0;
+    tfs::AtomsView view() const {
+        tfs::AtomsView v;
+        v.K = K;
+        v.n_bins = n_bins;
+        v.t_sft = t_sft;
+        v.abc = abc;
+        v.x64 = x64;
+        v.x32 = x32;
+        return v;
+    }
+};
+
+struct WindowOwned {
+    int32_t type = 0;
+    std::vector<int64_t> t0, tau;
+};
+
+WindowOwned copy_window(const tfstat_window *w) {
+    if (!w) raise(TFSTAT_E_INVAL, "window is null");
+    if (w->type != TFSTAT_WIN_RECT && w->type != TFSTAT_WIN_EXP)
+        raise(TFSTAT_E_INVAL, "unknown window type");
+    if (w->reserved != 0) raise(TFSTAT_E_INVAL, "window.reserved must be 0");
+    if (w->n_t0 < 1 || w->n_tau < 1) raise(TFSTAT_E_GRID, "n_t0 and n_tau must be >= 1");
+    WindowOwned o;
+    o.type = w->type;
+    o.t0.resize(w->n_t0);
+    o.tau.resize(w->n_tau);
+    if (w->t0_list) {
+        std::memcpy(o.t0.data(), w->t0_list, sizeof(int64_t) * w->n_t0);
+    } else {
+        if (w->dt0 < 1) raise(TFSTAT_E_GRID, "dt0 must be >= 1");
+        for (int32_t i = 0; i < w->n_t0; ++i) o.t0[i] = w->t0_min + (int64_t)i * w->dt0;
+    }
+    if (w->tau_list) {
+        std::memcpy(o.tau.data(), w->tau_list, sizeof(int64_t) * w->n_tau);
+    } else {
+        if (w->dtau < 1) raise(TFSTAT_E_GRID, "dtau must be >= 1");
+        for (int32_t i = 0; i < w->n_tau; ++i) o.tau[i] = w->tau_min + (int64_t)i * w->dtau;
+    }
+    for (size_t i = 1; i < o.t0.size(); ++i)
+        if (o.t0[i] <= o.t0[i - 1]) raise(TFSTAT_E_GRID, "t0 grid must be strictly increasing");
+    for (size_t i = 0; i < o.tau.size(); ++i) {
+        if (o.tau[i] < 1) raise(TFSTAT_E_GRID, "tau values must be >= 1");
+        if (o.tau[i] > ((int64_t)1 << 58)) raise(TFSTAT_E_GRID, "tau too large");
+        if (i && o.tau[i] <= o.tau[i - 1]) raise(TFSTAT_E_GRID, "tau grid must be strictly increasing");
+    }
+    return o;
+}
+
+enum { NK = TFSTAT_K_COUNT };
+
+// ---------------------------------------------------------------------------
+// One map computation: plan (host, integer), workspace, launches, results.
+// ---------------------------------------------------------------------------
+struct Job {
+    AtomsSet *at = nullptr;
+    WindowOwned win;
+    int prec = TFSTAT_PREC_FP32;
+    float *twoF = nullptr;
+
+    // plan
+    std::vector<tfs::RowPlan> rows;
+    std::vector<int32_t> lcol, lblk, order;
+    std::vector<int64_t> blk_off;
+    int R = 0, BG = 0, NB = 0, n_row_tiles = 0, n_tiles = 0, n_tiles_n = 0;
+    int64_t wtot = 0, max_blk = 0;
+
+    // memory
+    size_t ws_bytes = 0;
+    void *ws = nullptr;
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
+    size_t off_rows = 0, off_tau = 0, off_lcol = 0, off_lblk = 0, off_boff = 0, off_order = 0,
+           tables_bytes = 0;
+    size_t off_g32 = 0, off_gsq = 0, off_g64 = 0, off_pabc = 0, off_px = 0, off_part = 0,
+           off_res = 0;
+
+    // timing
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timed;
+    hipEvent_t done = nullptr;
+};
+
+void plan_job(Job &j) {
+    const AtomsSet &at = *j.at;
+    const int64_t T = at.t_sft;
+    const int n_t0 = (int)j.win.t0.size();
+    const int n_tau = (int)j.win.tau.size();
+    j.rows.resize(n_t0);
+    int64_t k0_min = INT64_MAX;
+    for (int m = 0; m < n_t0; ++m) {
+        const int64_t diff = j.win.t0[m] - at.T0;
+        if (diff > ((int64_t)1 << 58) || diff < -((int64_t)1 << 58))
+            raise(TFSTAT_E_GRID, "t0 too far from the data");
+        int64_t k0 = ceil_div(diff, T);
+        const int64_t delta = at.T0 + k0 * T - j.win.t0[m];
+        if (k0 > at.K) k0 = at.K;
+        if (k0 < -((int64_t)1 << 30)) raise(TFSTAT_E_GRID, "t0 too far before the data");
+        j.rows[m].k0 = (int32_t)k0;
+        j.rows[m].delta = (int32_t)delta;
+        k0_min = std::min(k0_min, k0);
+    }
+    const bool is_exp = j.win.type == TFSTAT_WIN_EXP;
+    j.lcol.assign(n_tau, 0);
+    const int64_t cap = std::max<int64_t>(0, (int64_t)at.K - k0_min);
+    for (int n = 0; n < n_tau; ++n) {
+        const int64_t span = is_exp ? 3 * j.win.tau[n] : j.win.tau[n];
+        j.lcol[n] = (int32_t)std::min(ceil_div(span, T), cap);
+    }
+    j.n_row_tiles = (n_t0 + 63) / 64;
+    if (is_exp) {
+        const int prec = (j.prec == TFSTAT_PREC_FP64) ? 0 : 1;
+        tfs::exp_valu_config(prec, at.n_bins, &j.R, &j.BG);
+        j.NB = (n_tau + j.R - 1) / j.R;
+        j.lblk.assign(j.NB, 0);
+        j.blk_off.assign(j.NB, 0);
+        int64_t acc = 0;
+        j.max_blk = 0;
+        for (int b = 0; b < j.NB; ++b) {
+            int32_t mx = 0;
+            for (int r = 0; r < j.R && b * j.R + r < n_tau; ++r) mx = std::max(mx, j.lcol[b * j.R + r]);
+            j.lblk[b] = mx;
+            j.blk_off[b] = acc;
+            acc += (int64_t)mx * j.R;
+            j.max_blk = std::max<int64_t>(j.max_blk, (int64_t)mx * j.R);
+        }
+        j.wtot = acc;
+        j.order.resize(j.NB);
+        for (int b = 0; b < j.NB; ++b) j.order[b] = b;
+        std::stable_sort(j.order.begin(), j.order.end(),
+                         [&](int a, int b) { return j.lblk[a] > j.lblk[b]; });
+        j.n_tiles = j.NB * j.n_row_tiles;
+    } else {
+        j.n_tiles_n = (n_tau + 63) / 64;
+        j.n_tiles = j.n_tiles_n * ((n_t0 + 3) / 4);
+    }
+
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at_ = o;
+        o = round_up(o + bytes, 256);
+        return at_;
+    };
+    j.off_rows = take(sizeof(tfs::RowPlan) * n_t0);
+    j.off_tau = take(sizeof(int64_t) * n_tau);
+    j.off_lcol = take(sizeof(int32_t) * n_tau);
+    if (is_exp) {
+        j.off_lblk = take(sizeof(int32_t) * j.NB);
+        j.off_boff = take(sizeof(int64_t) * j.NB);
+        j.off_order = take(sizeof(int32_t) * j.NB);
+    }
+    j.tables_bytes = o;
+    if (is_exp) {
+        j.off_g32 = take(sizeof(float) * std::max<int64_t>(j.wtot, 1));
+        j.off_gsq = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
+        if (j.prec == TFSTAT_PREC_FP64) j.off_g64 = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
+    } else {
+        j.off_pabc = take(sizeof(double) * 4 * ((size_t)at.K + 1));
+        j.off_px = take(sizeof(double) * 4 * (size_t)at.n_bins * ((size_t)at.K + 1));
+    }
+    j.off_part = take(sizeof(tfs::Partial) * (size_t)j.n_tiles * at.n_bins);
+    j.off_res = take(sizeof(tfs::BinResultDev) * at.n_bins);
+    j.ws_bytes = o;
+}
+
+struct EventPool {
+    std::mutex mu;
+    std::vector<hipEvent_t> free_;
+    hipEvent_t get() {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (!free_.empty()) {
+                hipEvent_t e = free_.back();
+                free_.pop_back();
+                return e;
+            }
+        }
+        hipEvent_t e;
+        hip_check(hipEventCreate(&e), "hipEventCreate");
+        return e;
+    }
+    void put(hipEvent_t e) {
+        std::lock_guard<std::mutex> g(mu);
+        free_.push_back(e);
+    }
+    ~EventPool() {
+        for (auto e : free_) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct tfstat_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Arena arena;
+    std::mutex mu;   // guards arena, atoms, tickets, stats
+    std::unordered_map<uint64_t, std::unique_ptr<AtomsSet>> atoms;
+    uint64_t next_atoms = 1;
+    PinnedPool pinned;
+    EventPool events;
+    std::atomic<int> profile{0};
+    int64_t k_launches[NK] = {0};
+    double k_ms[NK] = {0};
+
+    // serving
+    struct Ticket {
+        uint64_t atoms_id = 0;
+        std::unique_ptr<Job> job;
+        enum { QUEUED, RUNNING, DONE, FAILED, CANCELLED } state = QUEUED;
+        bool cancel_requested = false;
+        int err = 0;
+        std::string msg;
+        std::vector<tfstat_bin_result> res;
+        int slot = -1;
+    };
+    static constexpr int kSlots = 4;
+    static constexpr size_t kMaxQueue = 1 << 16;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    std::deque<uint64_t> queue;
+    uint64_t next_ticket = 1;
+    hipStream_t slots[kSlots] = {nullptr};
+    uint64_t slot_ticket[kSlots] = {0};
+    std::thread worker;
+    std::condition_variable cv;
+    bool stop = false;
+    bool worker_started = false;
+};
+
+namespace {
+
+void record_kernel(tfstat_ctx *ctx, Job &j, int kind, hipStream_t s, bool begin) {
+    if (!ctx->profile.load()) return;
+    if (begin) {
+        hipEvent_t a = ctx->events.get();
+        hip_check(hipEventRecord(a, s), "hipEventRecord");
+        j.timed.push_back({kind, {a, nullptr}});
+    } else {
+        hipEvent_t b = ctx->events.get();
+        hip_check(hipEventRecord(b, s), "hipEventRecord");
+        j.timed.back().second.second = b;
+    }
+}
+
+void collect_timing(tfstat_ctx *ctx, Job &j) {
+    for (auto &t : j.timed) {
+        float ms = 0.f;
+        if (t.second.second && hipEventElapsedTime(&ms, t.second.first, t.second.second) == hipSuccess) {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->k_launches[t.first] += 1;
+            ctx->k_ms[t.first] += ms;
+        }
+        ctx->events.put(t.second.first);
+        if (t.second.second) ctx->events.put(t.second.second);
+    }
+    j.timed.clear();
+}
+
+// Allocates the workspace from the arena; false when it does not fit now.
+bool alloc_job(tfstat_ctx *ctx, Job &j) {
+    j.ws = ctx->arena.alloc(j.ws_bytes);
+    return j.ws != nullptr;
+}
+
+void release_job(tfstat_ctx *ctx, Job &j) {
+    if (j.ws) ctx->arena.release(j.ws);
+    j.ws = nullptr;
+    if (j.pin) ctx->pinned.put(j.pin, j.pin_bytes);
+    j.pin = nullptr;
+}
+
+template <typename T>
+T *ws_ptr(Job &j, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(j.ws) + off);
+}
+
+// Enqueues every step of the map on stream s (tables upload, kernels,
+// results download into pinned memory).  The workspace must be allocated.
+void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
+    const AtomsSet &at = *j.at;
+    const int n_t0 = (int)j.win.t0.size();
+    const int n_tau = (int)j.win.tau.size();
+    const bool is_exp = j.win.type == TFSTAT_WIN_EXP;
+    const size_t res_bytes = sizeof(tfs::BinResultDev) * at.n_bins;
+    if (!j.pin) j.pin = ctx->pinned.get(std::max(j.tables_bytes, res_bytes), &j.pin_bytes);
+    char *h = static_cast<char *>(j.pin);
+    std::memcpy(h + j.off_rows, j.rows.data(), sizeof(tfs::RowPlan) * n_t0);
+    std::memcpy(h + j.off_tau, j.win.tau.data(), sizeof(int64_t) * n_tau);
+    std::memcpy(h + j.off_lcol, j.lcol.data(), sizeof(int32_t) * n_tau);
+    if (is_exp) {
+        std::memcpy(h + j.off_lblk, j.lblk.data(), sizeof(int32_t) * j.NB);
+        std::memcpy(h + j.off_boff, j.blk_off.data(), sizeof(int64_t) * j.NB);
+        std::memcpy(h + j.off_order, j.order.data(), sizeof(int32_t) * j.NB);
+    }
+    hip_check(hipMemcpyAsync(j.ws, h, j.tables_bytes, hipMemcpyHostToDevice, s), "upload tables");
+
+    const auto *rows = ws_ptr<tfs::RowPlan>(j, j.off_rows);
+    const auto *tau = ws_ptr<int64_t>(j, j.off_tau);
+    const auto *lcol = ws_ptr<int32_t>(j, j.off_lcol);
+    auto *part = ws_ptr<tfs::Partial>(j, j.off_part);
+    auto *res = ws_ptr<tfs::BinResultDev>(j, j.off_res);
+
+    if (is_exp) {
+        tfs::WeightParams wp{};
+        wp.n_tau = n_tau;
+        wp.n_blocks = j.NB;
+        wp.R = j.R;
+        wp.want64 = j.prec == TFSTAT_PREC_FP64;
+        wp.t_sft = at.t_sft;
+        wp.tau = tau;
+        wp.lcol = lcol;
+        wp.lblk = ws_ptr<int32_t>(j, j.off_lblk);
+        wp.blk_off = ws_ptr<int64_t>(j, j.off_boff);
+        wp.g32 = ws_ptr<float>(j, j.off_g32);
+        wp.gsq = ws_ptr<double>(j, j.off_gsq);
+        wp.g64 = wp.want64 ? ws_ptr<double>(j, j.off_g64) : nullptr;
+        record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, true);
+        hip_check(tfs::launch_weights(wp, j.max_blk, s), "weights kernel");
+        record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, false);
+
+        tfs::ExpValuParams p{};
+        p.at = at.view();
+        p.n_t0 = n_t0;
+        p.n_tau = n_tau;
+        p.n_row_tiles = j.n_row_tiles;
+        p.n_blocks = j.NB;
+        p.n_tasks = j.NB * j.n_row_tiles;
+        p.tasks_per_xcd = 0;
+        p.n_tiles = j.n_tiles;
+        p.rows = rows;
+        p.tau = tau;
+        p.lcol = lcol;
+        p.lblk = wp.lblk;
+        p.blk_off = wp.blk_off;
+        p.blk_order = ws_ptr<int32_t>(j, j.off_order);
+        p.g32 = wp.g32;
+        p.g64 = wp.g64;
+        p.gsq = wp.gsq;
+        p.twoF = j.twoF;
+        p.part = part;
+        record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
+        hip_check(tfs::launch_exp_valu(p, j.prec == TFSTAT_PREC_FP64 ? 0 : 1, j.R, j.BG, s),
+                  "exp kernel");
+        record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
+    } else {
+        double *pabc = ws_ptr<double>(j, j.off_pabc);
+        double *px = ws_ptr<double>(j, j.off_px);
+        record_kernel(ctx, j, TFSTAT_K_SCAN, s, true);
+        hip_check(tfs::launch_scan(at.abc, 4, pabc, at.K, 4, s), "scan kernel");
+        hip_check(tfs::launch_scan(at.x64, 4 * (int64_t)at.n_bins, px, at.K, 4 * at.n_bins, s),
+                  "scan kernel");
+        record_kernel(ctx, j, TFSTAT_K_SCAN, s, false);
+        tfs::RectParams p{};
+        p.K = at.K;
+        p.n_bins = at.n_bins;
+        p.n_t0 = n_t0;
+        p.n_tau = n_tau;
+        p.t_sft = at.t_sft;
+        p.n_tiles_n = j.n_tiles_n;
+        p.n_tiles = j.n_tiles;
+        p.rows = rows;
+        p.tau = tau;
+        p.pabc = pabc;
+        p.px = px;
+        p.twoF = j.twoF;
+        p.part = part;
+        record_kernel(ctx, j, TFSTAT_K_RECT, s, true);
+        hip_check(tfs::launch_rect(p, s), "rect kernel");
+        record_kernel(ctx, j, TFSTAT_K_RECT, s, false);
+    }
+    tfs::MergeParams mp{};
+    mp.n_tiles = j.n_tiles;
+    mp.n_maps = at.n_bins;
+    mp.n_cells = (int64_t)n_t0 * n_tau;
+    mp.part = part;
+    mp.out = res;
+    record_kernel(ctx, j, TFSTAT_K_MERGE, s, true);
+    hip_check(tfs::launch_merge(mp, s), "merge kernel");
+    record_kernel(ctx, j, TFSTAT_K_MERGE, s, false);
+    hip_check(hipMemcpyAsync(j.pin, res, res_bytes, hipMemcpyDeviceToHost, s), "download results");
+}
+
+void finish_job(tfstat_ctx *ctx, Job &j, tfstat_bin_result *out) {
+    collect_timing(ctx, j);
+    const auto *r = static_cast<const tfs::BinResultDev *>(j.pin);
+    const int64_t n_tau = (int64_t)j.win.tau.size();
+    for (int b = 0; b < j.at->n_bins; ++b) {
+        tfstat_bin_result o{};
+        o.max2F = r[b].max2F;
+        o.logB = r[b].logB;
+        const int64_t idx = r[b].idx;
+        o.m = (int32_t)(idx / n_tau);
+        o.n = (int32_t)(idx % n_tau);
+        o.t0 = j.win.t0[o.m];
+        o.tau = j.win.tau[o.n];
+        out[b] = o;
+    }
+}
+
+AtomsSet *find_atoms(tfstat_ctx *ctx, tfstat_atoms_id id) {
+    auto it = ctx->atoms.find(id);
+    if (it == ctx->atoms.end()) raise(TFSTAT_E_NOTFOUND, "unknown atoms id");
+    return it->second.get();
+}
+
+// ---------------------------------------------------------------------------
+// Serving loop: admits queued requests FIFO as stream slots and arena memory
+// free up, runs them concurrently on the slot streams, completes tickets.
+// ---------------------------------------------------------------------------
+void worker_loop(tfstat_ctx *ctx) {
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    while (true) {
+        bool progressed = false;
+        // completions
+        for (int s = 0; s < tfstat_ctx::kSlots; ++s) {
+            const uint64_t id = ctx->slot_ticket[s];
+            if (!id) continue;
+            auto &t = ctx->tickets[id];
+            const hipError_t q = hipEventQuery(t.job->done);
+            if (q == hipErrorNotReady) continue;
+            if (q == hipSuccess) {
+                t.res.resize(t.job->at->n_bins);
+                lk.unlock();
+                finish_job(ctx, *t.job, t.res.data());
+                lk.lock();
+                t.state = t.cancel_requested ? tfstat_ctx::Ticket::CANCELLED : tfstat_ctx::Ticket::DONE;
+            } else {
+                t.state = tfstat_ctx::Ticket::FAILED;
+                t.err = TFSTAT_E_DEVICE;
+                t.msg = std::string("request failed on the device: ") + hipGetErrorString(q);
+            }
+            ctx->events.put(t.job->done);
+            t.job->done = nullptr;
+            t.job->at->busy -= 1;
+            release_job(ctx, *t.job);
+            ctx->slot_ticket[s] = 0;
+            progressed = true;
+        }
+        // admissions
+        while (!ctx->queue.empty()) {
+            int slot = -1;
+            for (int s = 0; s < tfstat_ctx::kSlots; ++s)
+                if (!ctx->slot_ticket[s]) {
+                    slot = s;
+                    break;
+                }
+            if (slot < 0) break;
+            const uint64_t id = ctx->queue.front();
+            auto it = ctx->tickets.find(id);
+            if (it == ctx->tickets.end() || it->second.cancel_requested) {
+                if (it != ctx->tickets.end()) {
+                    it->second.state = tfstat_ctx::Ticket::CANCELLED;
+                    if (it->second.job) it->second.job->at->busy -= 1;
+                }
+                ctx->queue.pop_front();
+                progressed = true;
+                continue;
+            }
+            auto &t = it->second;
+            if (!alloc_job(ctx, *t.job)) break;  // wait for memory
+            ctx->queue.pop_front();
+            try {
+                enqueue_job(ctx, *t.job, ctx->slots[slot]);
+                t.job->done = ctx->events.get();
+                hip_check(hipEventRecord(t.job->done, ctx->slots[slot]), "hipEventRecord");
+                t.state = tfstat_ctx::Ticket::RUNNING;
+                t.slot = slot;
+                ctx->slot_ticket[slot] = id;
+            } catch (const Failure &f) {
+                t.state = tfstat_ctx::Ticket::FAILED;
+                t.err = f.code;
+                t.msg = f.msg;
+                t.job->at->busy -= 1;
+                release_job(ctx, *t.job);
+            }
+            progressed = true;
+        }
+        bool running = false;
+        for (int s = 0; s < tfstat_ctx::kSlots; ++s) running |= ctx->slot_ticket[s] != 0;
+        if (ctx->stop && !running && ctx->queue.empty()) break;
+        if (ctx->stop && !running) {
+            // drain: cancel what never started
+            for (uint64_t id : ctx->queue) {
+                auto it = ctx->tickets.find(id);
+                if (it != ctx->tickets.end()) {
+                    it->second.state = tfstat_ctx::Ticket::CANCELLED;
+                    it->second.job->at->busy -= 1;
+                }
+            }
+            ctx->queue.clear();
+            break;
+        }
+        if (!running && ctx->queue.empty()) {
+            ctx->cv.wait(lk);
+        } else if (!progressed) {
+            ctx->cv.wait_for(lk, std::chrono::microseconds(20));
+        }
+    }
+}
+
+void ensure_worker(tfstat_ctx *ctx) {
+    if (ctx->worker_started) return;
+    for (int s = 0; s < tfstat_ctx::kSlots; ++s)
+        hip_check(hipStreamCreateWithFlags(&ctx->slots[s], hipStreamNonBlocking), "hipStreamCreate");
+    ctx->worker = std::thread(worker_loop, ctx);
+    ctx->worker_started = true;
+}
+
+template <typename F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Failure &e) {
+        return fail(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(TFSTAT_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(TFSTAT_E_INVAL, e.what());
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *tfstat_last_error(void) { return g_err.c_str(); }
+
+const char *tfstat_version(void) { return "tfstat 0.1 (gfx950)"; }
+
+int tfstat_ctx_create(int device, void *arena_dev, size_t arena_bytes, void *hip_stream,
+                      tfstat_ctx **out) {
+    return guarded([&] {
+        if (!out) raise(TFSTAT_E_INVAL, "out is null");
+        if (!arena_dev || (reinterpret_cast<uintptr_t>(arena_dev) & 255))
+            raise(TFSTAT_E_INVAL, "arena must be non-null and 256-byte aligned");
+        if (arena_bytes < (1u << 20)) raise(TFSTAT_E_INVAL, "arena must be at least 1 MiB");
+        int n = 0;
+        hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
+        if (device < 0 || device >= n) raise(TFSTAT_E_DEVICE, "no such device");
+        hip_check(hipSetDevice(device), "hipSetDevice");
+        auto ctx = std::make_unique<tfstat_ctx>();
+        ctx->device = device;
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+        ctx->arena.init(arena_dev, arena_bytes);
+        *out = ctx.release();
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_ctx_destroy(tfstat_ctx *ctx) {
+    if (!ctx) return fail(TFSTAT_E_INVAL, "ctx is null");
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->stop = true;
+    }
+    ctx->cv.notify_all();
+    if (ctx->worker.joinable()) ctx->worker.join();
+    for (int s = 0; s < tfstat_ctx::kSlots; ++s)
+        if (ctx->slots[s]) (void)hipStreamDestroy(ctx->slots[s]);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return TFSTAT_OK;
+}
+
+int tfstat_atoms_upload(tfstat_ctx *ctx, const tfstat_atoms_desc *d, tfstat_atoms_id *out) {
+    return guarded([&] {
+        if (!ctx || !d || !out) raise(TFSTAT_E_INVAL, "null argument");
+        if (d->n_sft < 1 || d->n_bins < 1 || d->t_sft < 1)
+            raise(TFSTAT_E_INVAL, "n_sft, n_bins and t_sft must be >= 1");
+        if (!d->timestamps || !d->a2 || !d->b2 || !d->ab || !d->fa || !d->fb)
+            raise(TFSTAT_E_INVAL, "null atom array");
+        if (d->t_sft > (1 << 30)) raise(TFSTAT_E_INVAL, "t_sft too large");
+        const int64_t T = d->t_sft, T0 = d->timestamps[0];
+        for (int32_t i = 1; i < d->n_sft; ++i)
+            if (d->timestamps[i] <= d->timestamps[i - 1])
+                raise(TFSTAT_E_GRID, "timestamps must be strictly increasing");
+        for (int32_t i = 0; i < d->n_sft; ++i)
+            if ((d->timestamps[i] - T0) % T != 0)
+                raise(TFSTAT_E_GRID, "timestamps must lie on timestamps[0] + k * t_sft");
+        const int64_t K64 = (d->timestamps[d->n_sft - 1] - T0) / T + 1;
+        if (K64 > (1 << 28)) raise(TFSTAT_E_GRID, "data span too long");
+        const int32_t K = (int32_t)K64;
+        const int32_t nb = d->n_bins;
+        const size_t rows = (size_t)K + 1;
+        const size_t abc_b = round_up(sizeof(double) * 4 * rows, 256);
+        const size_t x64_b = round_up(sizeof(double) * 4 * nb * rows, 256);
+        const size_t x32_b = round_up(sizeof(float) * 4 * nb * rows, 256);
+        auto set = std::make_unique<AtomsSet>();
+        set->K = K;
+        set->n_bins = nb;
+        set->n_sft = d->n_sft;
+        set->T0 = T0;
+        set->t_sft = T;
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            set->mem = ctx->arena.alloc(abc_b + x64_b + x32_b);
+        }
+        if (!set->mem) raise(TFSTAT_E_NOMEM, "arena cannot hold the atoms");
+        set->bytes = abc_b + x64_b + x32_b;
+        char *base = static_cast<char *>(set->mem);
+        set->abc = reinterpret_cast<double *>(base);
+        set->x64 = reinterpret_cast<double *>(base + abc_b);
+        set->x32 = reinterpret_cast<float *>(base + abc_b + x64_b);
+        size_t pin_bytes = 0;
+        void *pin = ctx->pinned.get(abc_b + x64_b, &pin_bytes);
+        try {
+            std::memset(pin, 0, abc_b + x64_b);
+            double *habc = static_cast<double *>(pin);
+            double *hx = reinterpret_cast<double *>(static_cast<char *>(pin) + abc_b);
+            for (int32_t i = 0; i < d->n_sft; ++i) {
+                const int64_t k = (d->timestamps[i] - T0) / T;
+                habc[k * 4 + 0] = d->a2[i];
+                habc[k * 4 + 1] = d->b2[i];
+                habc[k * 4 + 2] = d->ab[i];
+                for (int32_t b = 0; b < nb; ++b) {
+                    const double *pa = d->fa + ((size_t)b * d->n_sft + i) * 2;
+                    const double *pb = d->fb + ((size_t)b * d->n_sft + i) * 2;
+                    double *o = hx + ((size_t)k * nb + b) * 4;
+                    o[0] = pa[0];
+                    o[1] = pa[1];
+                    o[2] = pb[0];
+                    o[3] = pb[1];
+                }
+            }
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            hip_check(hipMemcpyAsync(set->mem, pin, abc_b + x64_b, hipMemcpyHostToDevice, ctx->stream),
+                      "upload atoms");
+            Job dummy;
+            record_kernel(ctx, dummy, TFSTAT_K_UPLOAD, ctx->stream, true);
+            hip_check(tfs::launch_build_x32(set->x64, set->x32, (int64_t)4 * nb * rows, ctx->stream),
+                      "x32 kernel");
+            record_kernel(ctx, dummy, TFSTAT_K_UPLOAD, ctx->stream, false);
+            hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+            collect_timing(ctx, dummy);
+        } catch (...) {
+            ctx->pinned.put(pin, pin_bytes);
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->arena.release(set->mem);
+            throw;
+        }
+        ctx->pinned.put(pin, pin_bytes);
+        std::lock_guard<std::mutex> g(ctx->mu);
+        const uint64_t id = ctx->next_atoms++;
+        ctx->atoms[id] = std::move(set);
+        *out = id;
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_atoms_free(tfstat_ctx *ctx, tfstat_atoms_id id) {
+    return guarded([&] {
+        if (!ctx) raise(TFSTAT_E_INVAL, "ctx is null");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        AtomsSet *s = find_atoms(ctx, id);
+        if (s->busy > 0) raise(TFSTAT_E_BUSY, "atoms are in use by submitted requests");
+        ctx->arena.release(s->mem);
+        ctx->atoms.erase(id);
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_atoms_info(tfstat_ctx *ctx, tfstat_atoms_id id, int32_t *n_slots, int32_t *n_bins) {
+    return guarded([&] {
+        if (!ctx) raise(TFSTAT_E_INVAL, "ctx is null");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        AtomsSet *s = find_atoms(ctx, id);
+        if (n_slots) *n_slots = s->K;
+        if (n_bins) *n_bins = s->n_bins;
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_fmap(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win, int32_t precision,
+                float *twoF_dev, tfstat_bin_result *res_host) {
+    return guarded([&] {
+        if (!ctx || !res_host) raise(TFSTAT_E_INVAL, "null argument");
+        if (precision != TFSTAT_PREC_FP64 && precision != TFSTAT_PREC_FP32 &&
+            precision != TFSTAT_PREC_BF16X3)
+            raise(TFSTAT_E_INVAL, "unknown precision");
+        if (precision == TFSTAT_PREC_BF16X3)
+            raise(TFSTAT_E_INVAL, "BF16X3 precision is not available in this build");
+        Job j;
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            j.at = find_atoms(ctx, id);
+        }
+        j.win = copy_window(win);
+        j.prec = precision;
+        j.twoF = twoF_dev;
+        plan_job(j);
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            if (!alloc_job(ctx, j)) raise(TFSTAT_E_NOMEM, "arena cannot hold the map workspace");
+        }
+        try {
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            enqueue_job(ctx, j, ctx->stream);
+            hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+            finish_job(ctx, j, res_host);
+        } catch (...) {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            release_job(ctx, j);
+            throw;
+        }
+        std::lock_guard<std::mutex> g(ctx->mu);
+        release_job(ctx, j);
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_logB(tfstat_ctx *ctx, const float *twoF_dev, int32_t n_maps, int32_t n_t0, int32_t n_tau,
+                double *logB_host) {
+    return guarded([&] {
+        if (!ctx || !twoF_dev || !logB_host) raise(TFSTAT_E_INVAL, "null argument");
+        if (n_maps < 1 || n_t0 < 1 || n_tau < 1) raise(TFSTAT_E_INVAL, "sizes must be >= 1");
+        const int64_t cells = (int64_t)n_t0 * n_tau;
+        const int64_t cpt = 16384;
+        const int32_t n_tiles = (int32_t)((cells + cpt - 1) / cpt);
+        const size_t part_b = round_up(sizeof(tfs::Partial) * (size_t)n_tiles * n_maps, 256);
+        const size_t res_b = sizeof(tfs::BinResultDev) * n_maps;
+        void *ws;
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ws = ctx->arena.alloc(part_b + res_b);
+        }
+        if (!ws) raise(TFSTAT_E_NOMEM, "arena cannot hold the reduction workspace");
+        size_t pin_b = 0;
+        void *pin = nullptr;
+        try {
+            hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            pin = ctx->pinned.get(res_b, &pin_b);
+            tfs::MapReduceParams rp{};
+            rp.twoF = twoF_dev;
+            rp.n_cells = cells;
+            rp.n_maps = n_maps;
+            rp.n_tiles = n_tiles;
+            rp.cells_per_tile = cpt;
+            rp.part = static_cast<tfs::Partial *>(ws);
+            hip_check(tfs::launch_map_reduce(rp, ctx->stream), "map reduce kernel");
+            tfs::MergeParams mp{};
+            mp.n_tiles = n_tiles;
+            mp.n_maps = n_maps;
+            mp.n_cells = cells;
+            mp.part = rp.part;
+            mp.out = reinterpret_cast<tfs::BinResultDev *>(static_cast<char *>(ws) + part_b);
+            hip_check(tfs::launch_merge(mp, ctx->stream), "merge kernel");
+            hip_check(hipMemcpyAsync(pin, mp.out, res_b, hipMemcpyDeviceToHost, ctx->stream),
+                      "download results");
+            hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+            const auto *r = static_cast<const tfs::BinResultDev *>(pin);
+            for (int32_t k = 0; k < n_maps; ++k) logB_host[k] = r[k].logB;
+        } catch (...) {
+            if (pin) ctx->pinned.put(pin, pin_b);
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->arena.release(ws);
+            throw;
+        }
+        ctx->pinned.put(pin, pin_b);
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->arena.release(ws);
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_submit(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win, int32_t precision,
+                  tfstat_ticket *out) {
+    return guarded([&] {
+        if (!ctx || !out) raise(TFSTAT_E_INVAL, "null argument");
+        if (precision != TFSTAT_PREC_FP64 && precision != TFSTAT_PREC_FP32 &&
+            precision != TFSTAT_PREC_BF16X3)
+            raise(TFSTAT_E_INVAL, "unknown precision");
+        if (precision == TFSTAT_PREC_BF16X3)
+            raise(TFSTAT_E_INVAL, "BF16X3 precision is not available in this build");
+        auto job = std::make_unique<Job>();
+        job->win = copy_window(win);
+        job->prec = precision;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        job->at = find_atoms(ctx, id);
+        plan_job(*job);
+        // A request whose workspace cannot fit beside the resident atoms
+        // would wait forever: refuse it now.
+        size_t resident = 0;
+        for (auto &kv : ctx->atoms) resident += kv.second->bytes;
+        if (job->ws_bytes + resident > ctx->arena.capacity())
+            raise(TFSTAT_E_NOMEM, "request workspace cannot fit beside the resident atoms");
+        if (ctx->queue.size() >= tfstat_ctx::kMaxQueue) raise(TFSTAT_E_BUSY, "serving queue is full");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        ensure_worker(ctx);
+        const uint64_t t = ctx->next_ticket++;
+        auto &tk = ctx->tickets[t];
+        tk.atoms_id = id;
+        job->at->busy += 1;
+        tk.job = std::move(job);
+        ctx->queue.push_back(t);
+        ctx->cv.notify_all();
+        *out = t;
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_poll(tfstat_ctx *ctx, tfstat_ticket t, tfstat_bin_result *res_host, int *done) {
+    return guarded([&] {
+        if (!ctx || !done) raise(TFSTAT_E_INVAL, "null argument");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tickets.find(t);
+        if (it == ctx->tickets.end()) raise(TFSTAT_E_NOTFOUND, "unknown or retired ticket");
+        auto &tk = it->second;
+        switch (tk.state) {
+            case tfstat_ctx::Ticket::DONE:
+                if (!res_host) raise(TFSTAT_E_INVAL, "res_host is null");
+                std::memcpy(res_host, tk.res.data(), sizeof(tfstat_bin_result) * tk.res.size());
+                *done = 1;
+                ctx->tickets.erase(it);
+                return (int)TFSTAT_OK;
+            case tfstat_ctx::Ticket::FAILED: {
+                *done = 1;
+                const int e = tk.err;
+                const std::string m = tk.msg;
+                ctx->tickets.erase(it);
+                raise(e, m);
+            }
+            case tfstat_ctx::Ticket::CANCELLED:
+                *done = 1;
+                ctx->tickets.erase(it);
+                raise(TFSTAT_E_CANCELLED, "ticket was cancelled");
+            default:
+                *done = 0;
+                return (int)TFSTAT_OK;
+        }
+    });
+}
+
+int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t) {
+    return guarded([&] {
+        if (!ctx) raise(TFSTAT_E_INVAL, "ctx is null");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tickets.find(t);
+        if (it == ctx->tickets.end()) raise(TFSTAT_E_NOTFOUND, "unknown or retired ticket");
+        it->second.cancel_requested = true;
+        ctx->cv.notify_all();
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_profile_enable(tfstat_ctx *ctx, int on) {
+    if (!ctx) return fail(TFSTAT_E_INVAL, "ctx is null");
+    ctx->profile.store(on ? 1 : 0);
+    return TFSTAT_OK;
+}
+
+int tfstat_profile_read(tfstat_ctx *ctx, int32_t kind, int64_t *launches, double *total_ms) {
+    if (!ctx || kind < 0 || kind >= NK) return fail(TFSTAT_E_INVAL, "bad argument");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (launches) *launches = ctx->k_launches[kind];
+    if (total_ms) *total_ms = ctx->k_ms[kind];
+    return TFSTAT_OK;
+}
+
+int tfstat_profile_reset(tfstat_ctx *ctx) {
+    if (!ctx) return fail(TFSTAT_E_INVAL, "ctx is null");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (int k = 0; k < NK; ++k) {
+        ctx->k_launches[k] = 0;
+        ctx->k_ms[k] = 0.0;
+    }
+    return TFSTAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Device-side parameter blocks and kernel launchers of the tfstat library.
+// Shared by the kernels (kernels.hip) and the host runtime (runtime.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfs {
+
+// Threshold of the degenerate-window rule: 2F := 0 when D <= rtol * A * B.
+constexpr double kDegenerateRtol = 1e-10;
+
+// One t0 row of the planned grid.  k0 is the first slot whose start time is
+// >= t0 (it may lie before slot 0 or after the last slot: such slots hold
+// zeros), delta = t_{k0} - t0 in [0, t_sft).
+struct RowPlan {
+    int32_t k0;
+    int32_t delta;
+};
+
+// Per-tile reduction partial: running maximum of F = 2F/2, the sum of
+// exp(F - fmax) over the tile's cells, and the smallest linear cell index
+// (m * n_tau + n) holding the maximum.
+struct Partial {
+    double fmax;
+    double s;
+    int64_t idx;
+};
+
+// Per-bin reduction result.
+struct BinResultDev {
+    double max2F;
+    double logB;
+    int64_t idx;
+};
+
+// Resident atoms of one candidate on the slot grid (row K is all zeros).
+struct AtomsView {
+    int32_t K;            // number of slots
+    int32_t n_bins;
+    int64_t t_sft;
+    const double *abc;    // [K+1][4]: a2, b2, ab, 0
+    const double *x64;    // [K+1][n_bins][4]: Re Fa, Im Fa, Re Fb, Im Fb
+    const float *x32;     // [K+1][n_bins][4]
+};
+
+// Exponential-window sums, VALU form.  A work item is a (t0 tile of 64 rows,
+// tau block of R columns) pair; the d-loop over the window band is split
+// across the four waves of a workgroup.
+struct ExpValuParams {
+    AtomsView at;
+    int32_t n_t0, n_tau;
+    int32_t n_row_tiles;      // ceil(n_t0 / 64)
+    int32_t n_blocks;         // ceil(n_tau / R)
+    int32_t n_tasks;          // n_row_tiles * n_blocks
+    int32_t tasks_per_xcd;    // ceil(n_tasks_padded / 8)
+    int32_t n_tiles;          // partial slots per bin (== n_tasks)
+    int32_t pad0;
+    const RowPlan *rows;      // [n_t0]
+    const int64_t *tau;       // [n_tau]
+    const int32_t *lcol;      // [n_tau] table length per tau (slots)
+    const int32_t *lblk;      // [n_blocks] max lcol over the block
+    const int64_t *blk_off;   // [n_blocks] element offset of the block's table
+    const int32_t *blk_order; // [n_blocks] block processed at each rank (largest first)
+    const float *g32;         // weight tables [blk][d][R]
+    const double *g64;        //   (FP64 weights, FP64 mode only)
+    const double *gsq;        //   (squared weights, FP64)
+    float *twoF;              // optional map [n_bins][n_t0][n_tau]
+    Partial *part;            // [n_bins][n_tiles]
+};
+
+struct WeightParams {
+    int32_t n_tau;
+    int32_t n_blocks;
+    int32_t R;
+    int32_t want64;
+    int64_t t_sft;
+    const int64_t *tau;
+    const int32_t *lcol;
+    const int32_t *lblk;
+    const int64_t *blk_off;
+    float *g32;
+    double *g64;
+    double *gsq;
+};
+
+struct RectParams {
+    int32_t K, n_bins;
+    int32_t n_t0, n_tau;
+    int64_t t_sft;
+    int32_t n_tiles_n;        // ceil(n_tau / 64)
+    int32_t n_tiles;          // per bin
+    const RowPlan *rows;
+    const int64_t *tau;
+    const double *pabc;       // [K+1][4] exclusive prefix
+    const double *px;         // [K+1][n_bins*4]
+    float *twoF;
+    Partial *part;
+};
+
+struct MergeParams {
+    int32_t n_tiles;
+    int32_t n_maps;
+    int64_t n_cells;
+    const Partial *part;      // [n_maps][n_tiles]
+    BinResultDev *out;        // [n_maps]
+};
+
+struct MapReduceParams {
+    const float *twoF;        // [n_maps][n_cells]
+    int64_t n_cells;
+    int32_t n_maps;
+    int32_t n_tiles;          // per map
+    int64_t cells_per_tile;
+    Partial *part;
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+// Each returns hipSuccess or the launch error.
+hipError_t launch_build_x32(const double *x64, float *x32, int64_t n, hipStream_t s);
+hipError_t launch_weights(const WeightParams &p, int64_t total_max_per_block,
+                          hipStream_t s);
+// prec: 0 = FP64 sums, 1 = FP32 sums.  bins_per_group chosen by the caller
+// from the supported set reported by exp_valu_config().
+hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG,
+                           hipStream_t s);
+hipError_t launch_scan(const double *in, int64_t in_row_stride, double *out,
+                       int32_t K, int32_t C, hipStream_t s);
+hipError_t launch_rect(const RectParams &p, hipStream_t s);
+hipError_t launch_merge(const MergeParams &p, hipStream_t s);
+hipError_t launch_map_reduce(const MapReduceParams &p, hipStream_t s);
+
+// Supported VALU tile shapes: tau columns per block R and bins per lane BG
+// for a precision and bin count.
+void exp_valu_config(int prec, int n_bins, int *R, int *BG);
+
+}  // namespace tfs

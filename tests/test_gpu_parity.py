@@ -1,0 +1,347 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances (floating point):
+  * 2F: |2F_gpu - 2F_oracle| <= tol * max(2F_oracle, 1) with tol = 1e-4 for
+    FP32 sums and 1e-9 for FP64 sums; the stored map is float32, so map
+    comparisons also allow its rounding (2^-23 relative).
+  * logB: absolute 1e-3.
+  * argmax: exact, or a near-tie: 2F_oracle at the GPU's argmax is at least
+    (1 - 1e-4) * max 2F_oracle.
+  * degenerate cells (2F = 0 in the oracle) are exactly 0 on the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tfsynth
+
+pytestmark = pytest.mark.gpu
+
+T = tfsynth.T_SFT
+F32_MAP = 2.0 ** -23
+TOL = {"fp32": 1e-4, "fp64": 1e-9}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1805_05652_amd as tf
+    c = tf.Context(0, arena_bytes=3 << 30)
+    yield c
+    c.close()
+
+
+def _case(msg):
+    print("case:", msg, flush=True)
+
+
+def check_map(got, ref, tol):
+    got = np.asarray(got, dtype=np.float64)
+    assert got.shape == ref.shape
+    zero = ref == 0.0
+    assert np.all(got[zero] == 0.0), "degenerate cells differ"
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    bound = tol + F32_MAP
+    worst = np.unravel_index(np.argmax(err), err.shape)
+    assert err.max() <= bound, ("max rel err %.3e at %s: gpu %r oracle %r"
+                                % (err.max(), worst, got[worst], ref[worst]))
+    return float(err.max())
+
+
+def check_results(res, ref_map, win, tol):
+    mx, am, lb = oracle.reduce(ref_map)
+    for b, r in enumerate(res):
+        assert abs(r["logB"] - lb[b]) <= 1e-3, (b, r["logB"], lb[b])
+        assert abs(r["max2F"] - mx[b]) <= tol * max(mx[b], 1.0), (b, r["max2F"], mx[b])
+        flat = ref_map[b].ravel()
+        idx = r["m"] * win.n_tau + r["n"]
+        assert idx == am[b] or flat[idx] >= (1 - 1e-4) * mx[b], (b, idx, am[b])
+        assert r["t0"] == win.t0[r["m"]] and r["tau"] == win.tau[r["n"]]
+
+
+def run_and_check(ctx, atoms, win, prec):
+    aid = ctx.upload_atoms(atoms)
+    try:
+        res, twoF = ctx.fmap(aid, win, prec, want_map=True)
+        ref = oracle.fmap_atoms(atoms, win)
+        err = check_map(twoF.cpu().numpy(), ref, TOL[prec])
+        check_results(res, ref, win, TOL[prec])
+        return res, ref, err
+    finally:
+        ctx.free(aid)
+
+
+# ---------------------------------------------------------------------------
+# Small cases spanning several tiles with ragged tails
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rect_small_workload(ctx, prec):
+    _case("rect small workload " + prec)
+    atoms, win = tfsynth.workload_rect_small()
+    run_and_check(ctx, atoms, win, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["rect", "exp"])
+def test_ragged_grid_with_edges(ctx, prec, kind):
+    """t0 off the slot grid, before the data and after it; tau not a multiple
+    of T_sft, shorter than one SFT and longer than the data; 3 bins."""
+    _case("ragged edges %s %s" % (kind, prec))
+    atoms = tfsynth.make_atoms(101, 300, 0.2, n_bins=3,
+                               injections=[tfsynth.Injection(2, kind, 40 * T, 30 * T, 1.2)])
+    rng = np.random.default_rng(5)
+    t0 = np.unique(np.concatenate([
+        [-5 * T - 77, -T, -1, 0, 1, T - 1],
+        rng.integers(0, 300 * T, size=120),
+        [299 * T, 299 * T + 1, 300 * T + 5, 400 * T]]))
+    tau = np.unique(np.concatenate([
+        [1, T - 1, T, T + 1, 2 * T],
+        rng.integers(2 * T, 200 * T, size=37),
+        [300 * T, 1000 * T]]))
+    win = tfsynth.list_window(kind, t0, tau)
+    run_and_check(ctx, atoms, win, prec)
+
+
+@pytest.mark.parametrize("n_bins", [1, 2, 3, 5, 8])
+def test_exp_bins_groups(ctx, n_bins):
+    _case("exp bins %d" % n_bins)
+    atoms = tfsynth.make_atoms(200 + n_bins, 180, 0.1, n_bins=n_bins)
+    win = tfsynth.regular_window("exp", 0, T, 130, 2 * T, T, 77)
+    run_and_check(ctx, atoms, win, "fp32")
+
+
+def test_exp_sparse_rows_read_through_cache(ctx):
+    """Rows 10 slots apart: a 64-row tile spans more slots than one LDS stage."""
+    _case("exp sparse rows")
+    atoms = tfsynth.make_atoms(301, 900, 0.1, n_bins=2)
+    win = tfsynth.regular_window("exp", 0, 10 * T, 85, 2 * T, 7 * T + 13, 30)
+    run_and_check(ctx, atoms, win, "fp32")
+    run_and_check(ctx, atoms, win, "fp64")
+
+
+def test_exp_long_bands_many_chunks(ctx):
+    """Bands longer than several LDS chunks and truncated at the data end."""
+    _case("exp long bands")
+    atoms = tfsynth.make_atoms(401, 1500, 0.15,
+                               injections=[tfsynth.Injection(0, "exp", 100 * T, 200 * T, 0.6)])
+    win = tfsynth.regular_window("exp", 0, T, 200, 2 * T, 61 * T, 24)
+    run_and_check(ctx, atoms, win, "fp32")
+
+
+def test_single_cell_and_single_sft(ctx):
+    _case("single cell / single sft")
+    atoms = tfsynth.make_atoms(5, 2, 0.0)
+    for kind in ("rect", "exp"):
+        win = tfsynth.regular_window(kind, 0, T, 1, 5 * T, T, 1)
+        run_and_check(ctx, atoms, win, "fp32")
+    one = tfsynth.Atoms(np.array([7 * T], dtype=np.int64), np.array([0.3]), np.array([0.1]),
+                        np.array([0.09]), np.array([0.01]), np.array([0.03]),
+                        np.array([[[0.5, -0.25]]]), np.array([[[0.125, 1.0]]]))
+    for kind in ("rect", "exp"):
+        win = tfsynth.regular_window(kind, 6 * T, T, 3, T, T, 3)
+        res, ref, _ = run_and_check(ctx, one, win, "fp64")
+        assert np.all(ref == 0.0)
+
+
+def test_loud_injection_argmax(ctx):
+    _case("loud injection")
+    t0, tau = 40 * T, 25 * T
+    for kind in ("rect", "exp"):
+        atoms = tfsynth.make_atoms(91, 150, 0.1, injections=[tfsynth.Injection(0, kind, t0, tau, 4.5)])
+        win = tfsynth.regular_window(kind, 0, T, 100, 2 * T, T, 140)
+        res, ref, _ = run_and_check(ctx, atoms, win, "fp32")
+        assert res[0]["max2F"] > 150
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+
+def _sample_cells(rng, win, n):
+    m = rng.integers(0, win.n_t0, size=n)
+    k = rng.integers(0, win.n_tau, size=n)
+    # corners and edges
+    m = np.concatenate([m, [0, 0, win.n_t0 - 1, win.n_t0 - 1, win.n_t0 // 2]])
+    k = np.concatenate([k, [0, win.n_tau - 1, 0, win.n_tau - 1, win.n_tau // 2]])
+    return m.astype(np.int32), k.astype(np.int32)
+
+
+def test_full_exp_1bin_fp32(ctx):
+    """5000 slots, 1000 x 1000 grid, tau to 30 days: every cell against the
+    oracle's full map, and the per-bin results."""
+    _case("full exp 1 bin fp32")
+    atoms, win = tfsynth.workload_exp_1bin()
+    aid = ctx.upload_atoms(atoms)
+    try:
+        res, twoF = ctx.fmap(aid, win, "fp32", want_map=True)
+        res2, _ = ctx.fmap(aid, win, "fp32", want_map=False)
+        assert res == res2, "results depend on whether the map is written"
+    finally:
+        ctx.free(aid)
+    ref = oracle.fmap_atoms(atoms, win)
+    err = check_map(twoF.cpu().numpy(), ref, 1e-4)
+    check_results(res, ref, win, 1e-4)
+    print("full exp 1 bin: max rel err %.3e" % err, flush=True)
+
+
+def test_full_exp_256_bins_sampled(ctx):
+    """256 bins sharing antenna atoms, 2000 slots, 500 x 500 grid: sampled
+    cells of every bin against the oracle."""
+    _case("full exp 256 bins fp32 sampled")
+    atoms, win = tfsynth.workload_exp_bins()
+    aid = ctx.upload_atoms(atoms)
+    try:
+        res, twoF = ctx.fmap(aid, win, "fp32", want_map=True)
+    finally:
+        ctx.free(aid)
+    got = twoF.cpu().numpy()
+    rng = np.random.default_rng(17)
+    mi, ni = _sample_cells(rng, win, 400)
+    ref = oracle.cells("exp", atoms.timestamps, atoms.a2, atoms.b2, atoms.ab, atoms.fa, atoms.fb,
+                       win.t0, win.tau, mi, ni)
+    sel = got[:, mi, ni]
+    check_map(sel, ref, 1e-4)
+    # results agree with the GPU's own map (reductions at full size)
+    mx = got.reshape(got.shape[0], -1).max(axis=1)
+    for b in range(atoms.n_bins):
+        assert abs(res[b]["max2F"] - mx[b]) <= 1e-6 * max(mx[b], 1.0)
+        F = got[b].astype(np.float64).ravel() / 2
+        lb = F.max() + np.log(np.exp(F - F.max()).sum()) - np.log(F.size)
+        assert abs(res[b]["logB"] - lb) <= 1e-4
+
+
+def test_full_rect_workload_results(ctx):
+    _case("full rect 256 bins")
+    atoms, win = tfsynth.workload_exp_bins()
+    win = tfsynth.regular_window("rect", 0, T, 500, 2 * T, T, 500)
+    aid = ctx.upload_atoms(atoms)
+    try:
+        res, twoF = ctx.fmap(aid, win, "fp64", want_map=True)
+    finally:
+        ctx.free(aid)
+    rng = np.random.default_rng(19)
+    mi, ni = _sample_cells(rng, win, 400)
+    ref = oracle.cells("rect", atoms.timestamps, atoms.a2, atoms.b2, atoms.ab, atoms.fa, atoms.fb,
+                       win.t0, win.tau, mi, ni)
+    check_map(twoF.cpu().numpy()[:, mi, ni], ref, 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# logB of stored maps, determinism
+# ---------------------------------------------------------------------------
+
+def test_logB_of_stored_map(ctx):
+    import torch
+    _case("logB stored map")
+    rng = np.random.default_rng(23)
+    maps = rng.chisquare(4, size=(3, 123, 457)).astype(np.float32)
+    maps[1, 7, 9] = 1400.0      # exp(700) overflows a double without the shift
+    dev = torch.from_numpy(maps).to("cuda:0")
+    got = ctx.logB(dev)
+    _, _, lb = oracle.reduce(maps.astype(np.float64))
+    assert np.allclose(got, lb, atol=1e-9, rtol=0)
+
+
+def test_deterministic_repeat(ctx):
+    _case("determinism")
+    atoms = tfsynth.make_atoms(77, 700, 0.1, n_bins=4)
+    win = tfsynth.regular_window("exp", 0, T, 300, 2 * T, 2 * T, 150)
+    aid = ctx.upload_atoms(atoms)
+    try:
+        r1, m1 = ctx.fmap(aid, win, "fp32", want_map=True)
+        r2, m2 = ctx.fmap(aid, win, "fp32", want_map=True)
+    finally:
+        ctx.free(aid)
+    assert r1 == r2
+    assert bool((m1 == m2).all())
+
+
+# ---------------------------------------------------------------------------
+# Serving: results alone and in a concurrent mix are identical
+# ---------------------------------------------------------------------------
+
+def test_submit_poll_mix_invariance(ctx):
+    import time
+    _case("serving mix")
+    reqs = []
+    for i in range(12):
+        atoms, win = tfsynth.candidate(i, max_slots=3000, max_grid=400, max_bins=6)
+        reqs.append((atoms, win))
+    ids = [ctx.upload_atoms(a) for a, _ in reqs]
+    try:
+        alone = [ctx.fmap(aid, w, "fp32")[0] for aid, (_, w) in zip(ids, reqs)]
+        tickets = [ctx.submit(aid, w, "fp32") for aid, (_, w) in zip(ids, reqs)]
+        pending = dict(enumerate(tickets))
+        got = {}
+        t_end = time.time() + 60
+        while pending and time.time() < t_end:
+            for i, t in list(pending.items()):
+                r = ctx.poll(t, reqs[i][0].n_bins)
+                if r is not None:
+                    got[i] = r
+                    del pending[i]
+            time.sleep(0.001)
+        assert not pending, "requests did not finish"
+        for i in range(len(reqs)):
+            assert got[i] == alone[i], i
+        # spot-check parity of a few against the oracle
+        for i in (0, 1):
+            atoms, win = reqs[i]
+            check_results(got[i], oracle.fmap_atoms(atoms, win), win, 1e-4)
+    finally:
+        for aid in ids:
+            ctx.free(aid)
+
+
+def test_cancel_and_errors(ctx):
+    from paper_1805_05652_amd import TfstatError, _abi
+    _case("errors")
+    atoms = tfsynth.make_atoms(3, 100, 0.1)
+    aid = ctx.upload_atoms(atoms)
+    try:
+        bad = tfsynth.list_window("exp", [0, 0], [T])
+        with pytest.raises(TfstatError) as e:
+            ctx.fmap(aid, bad, "fp32")
+        assert e.value.code == _abi.E_GRID
+        with pytest.raises(TfstatError) as e:
+            ctx.fmap(aid + 1000, tfsynth.regular_window("exp", 0, T, 2, T, T, 2), "fp32")
+        assert e.value.code == _abi.E_NOTFOUND
+        with pytest.raises(TfstatError) as e:
+            ctx.upload(np.array([0, 1000]), [1, 1], [1, 1], [0, 0], np.zeros((2, 2)),
+                       np.zeros((2, 2)), 1800)
+        assert e.value.code == _abi.E_GRID
+        win = tfsynth.regular_window("exp", 0, T, 50, 2 * T, T, 50)
+        tickets = [ctx.submit(aid, win, "fp32") for _ in range(6)]
+        ctx.cancel(tickets[-1])
+        import time
+        t_end = time.time() + 30
+        states = {}
+        while len(states) < len(tickets) and time.time() < t_end:
+            for t in tickets:
+                if t in states:
+                    continue
+                try:
+                    r = ctx.poll(t, 1)
+                    if r is not None:
+                        states[t] = "done"
+                except TfstatError as err:
+                    states[t] = err.code
+            time.sleep(0.001)
+        assert all(states[t] == "done" for t in tickets[:-1])
+        assert states[tickets[-1]] in ("done", _abi.E_CANCELLED)
+    finally:
+        ctx.free(aid)
+
+
+def test_arena_too_small():
+    import paper_1805_05652_amd as tf
+    from paper_1805_05652_amd import TfstatError, _abi
+    _case("small arena")
+    with tf.Context(0, arena_bytes=2 << 20) as small:
+        atoms, win = tfsynth.workload_exp_1bin(n_slots=5000, n_t0=1000, n_tau=1000)
+        aid = small.upload_atoms(atoms)
+        with pytest.raises(TfstatError) as e:
+            small.fmap(aid, win, "fp32")
+        assert e.value.code == _abi.E_NOMEM
+        small.free(aid)
