@@ -332,25 +332,26 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
         for (int b = 0; b < BG; ++b)
 #pragma unroll
             for (int c = 0; c < 4; ++c) f[b][c] = (double)sm.u.comb.f[0][r][b][c][lane];
-        // The table holds the band of a row with delta = 0; a row with
-        // delta > 0 may end one slot earlier.  Remove such terms exactly as
-        // they were added.
-        for (int64_t d = lmn; d < lc; ++d) {
+        // The table holds the shortest band over all rows of the grid; a row
+        // whose band reaches further (smaller delta) adds its last terms
+        // here, in FP64, with weights exp(-d T / tau).
+        const int64_t dend = min(lmn, (int64_t)K - rp.k0);
+        for (int64_t d = lc; d < dend; ++d) {
             const int64_t k = (int64_t)rp.k0 + d;
-            if (k < 0 || k >= K) continue;
-            const double qd = gq_base[d * R + r];
-            const XT gd = gw_base[d * R + r];
-            A -= qd * abc[k * 4 + 0];
-            B -= qd * abc[k * 4 + 1];
-            C -= qd * abc[k * 4 + 2];
+            if (k < 0) continue;
+            const double gd = exp(-(double)(d * T) / (double)tau);
+            const double qd = gd * gd;
+            A += qd * abc[k * 4 + 0];
+            B += qd * abc[k * 4 + 1];
+            C += qd * abc[k * 4 + 2];
 #pragma unroll
             for (int b = 0; b < BG; ++b) {
                 if (bin0 + b >= n_bins) continue;
                 const Q4<XT> x = load_q4(xg + ((size_t)k * n_bins + bin0 + b) * 4);
-                f[b][0] -= (double)(gd * x.x);
-                f[b][1] -= (double)(gd * x.y);
-                f[b][2] -= (double)(gd * x.z);
-                f[b][3] -= (double)(gd * x.w);
+                f[b][0] += gd * (double)x.x;
+                f[b][1] += gd * (double)x.y;
+                f[b][2] += gd * (double)x.z;
+                f[b][3] += gd * (double)x.w;
             }
         }
         if (rp.delta != 0) {
@@ -420,34 +421,64 @@ __global__ __launch_bounds__(256) void build_x32_kernel(const double *x64, float
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive prefix sums over slots (rectangular windows, section 3's running
-// sums turned into O(1) differences per cell).  out[0][c] = 0,
-// out[k+1][c] = out[k][c] + in[k][c].  Lane = channel, wave = slot segment.
+// Exclusive prefix sums over slots (rectangular windows: section 3's running
+// sums turned into O(1) differences per cell), carried as unevaluated
+// double-double pairs so that a window's difference keeps full FP64 accuracy
+// relative to the window sum itself, however long the prefix.
+//   out[k][c] = hi, out[k][C + c] = lo with hi + lo = sum_{j<k} in[j][c].
+// Lane = channel, wave = slot segment.
 // ---------------------------------------------------------------------------
 constexpr int kScanWaves = 16;
+
+struct DD {
+    double h, l;
+};
+
+// Error-free sum of two doubles (Knuth's TwoSum).
+__device__ inline DD two_sum(double a, double b) {
+    const double s = a + b;
+    const double bb = s - a;
+    const double e = (a - (s - bb)) + (b - bb);
+    return DD{s, e};
+}
+
+__device__ inline DD dd_add(DD x, double v) {
+    const DD t = two_sum(x.h, v);
+    return DD{t.h, x.l + t.l};
+}
+
+__device__ inline DD dd_add(DD x, DD y) {
+    const DD t = two_sum(x.h, y.h);
+    return DD{t.h, x.l + y.l + t.l};
+}
 
 __global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(const double *__restrict__ in,
                                                                int64_t stride, double *__restrict__ out,
                                                                int32_t K, int32_t C) {
-    __shared__ double tot[kScanWaves][64];
+    __shared__ DD tot[kScanWaves][64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int c = blockIdx.x * 64 + lane;
     const int seg = (K + kScanWaves - 1) / kScanWaves;
     const int kb = min(K, wave * seg);
     const int ke = min(K, kb + seg);
-    double sum = 0.0;
+    const size_t row = 2 * (size_t)C;
+    DD sum{0.0, 0.0};
     if (c < C)
-        for (int k = kb; k < ke; ++k) sum += in[(size_t)k * stride + c];
+        for (int k = kb; k < ke; ++k) sum = dd_add(sum, in[(size_t)k * stride + c]);
     tot[wave][lane] = sum;
     __syncthreads();
-    double run = 0.0;
-    for (int w = 0; w < wave; ++w) run += tot[w][lane];
+    DD run{0.0, 0.0};
+    for (int w = 0; w < wave; ++w) run = dd_add(run, tot[w][lane]);
     if (c < C) {
-        if (wave == 0) out[c] = 0.0;
+        if (wave == 0) {
+            out[c] = 0.0;
+            out[C + c] = 0.0;
+        }
         for (int k = kb; k < ke; ++k) {
-            run += in[(size_t)k * stride + c];
-            out[(size_t)(k + 1) * C + c] = run;
+            run = dd_add(run, in[(size_t)k * stride + c]);
+            out[(size_t)(k + 1) * row + c] = run.h;
+            out[(size_t)(k + 1) * row + C + c] = run.l;
         }
     }
 }
@@ -473,16 +504,19 @@ __global__ __launch_bounds__(256) void rect_kernel(RectParams p) {
     const int64_t K = p.K;
     const int64_t lo = min(max((int64_t)rp.k0, (int64_t)0), K);
     const int64_t hi = min(max((int64_t)rp.k0 + L, (int64_t)0), K);
-    const double *a_hi = p.pabc + hi * 4;
-    const double *a_lo = p.pabc + lo * 4;
-    const double A = a_hi[0] - a_lo[0];
-    const double B = a_hi[1] - a_lo[1];
-    const double C = a_hi[2] - a_lo[2];
+    // window sums from compensated prefixes: (hi_h - hi_l) + (lo_h - lo_l)
+    const double *a_hi = p.pabc + hi * 8;
+    const double *a_lo = p.pabc + lo * 8;
+    const double A = (a_hi[0] - a_lo[0]) + (a_hi[4] - a_lo[4]);
+    const double B = (a_hi[1] - a_lo[1]) + (a_hi[5] - a_lo[5]);
+    const double C = (a_hi[2] - a_lo[2]) + (a_hi[6] - a_lo[6]);
     const int64_t CW = (int64_t)p.n_bins * 4;
-    const double *x_hi = p.px + hi * CW + bin * 4;
-    const double *x_lo = p.px + lo * CW + bin * 4;
-    const double v = twoF_cell(A, B, C, x_hi[0] - x_lo[0], x_hi[1] - x_lo[1],
-                               x_hi[2] - x_lo[2], x_hi[3] - x_lo[3]);
+    const double *x_hi = p.px + hi * 2 * CW + bin * 4;
+    const double *x_lo = p.px + lo * 2 * CW + bin * 4;
+    double f[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) f[c] = (x_hi[c] - x_lo[c]) + (x_hi[CW + c] - x_lo[CW + c]);
+    const double v = twoF_cell(A, B, C, f[0], f[1], f[2], f[3]);
     Red r = red_empty();
     if (ok) {
         if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;

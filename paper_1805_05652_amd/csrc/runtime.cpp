@@ -269,11 +269,17 @@ void plan_job(Job &j) {
         k0_min = std::min(k0_min, k0);
     }
     const bool is_exp = j.win.type == TFSTAT_WIN_EXP;
+    // Table length per tau: the shortest band over all rows (the row with
+    // the largest delta), capped where no row can reach data any more.
+    // Rows with longer bands add their extra terms in the finalize step.
+    int64_t delta_max = 0;
+    for (int m = 0; m < n_t0; ++m) delta_max = std::max<int64_t>(delta_max, j.rows[m].delta);
     j.lcol.assign(n_tau, 0);
     const int64_t cap = std::max<int64_t>(0, (int64_t)at.K - k0_min);
     for (int n = 0; n < n_tau; ++n) {
         const int64_t span = is_exp ? 3 * j.win.tau[n] : j.win.tau[n];
-        j.lcol[n] = (int32_t)std::min(ceil_div(span, T), cap);
+        const int64_t shortest = span > delta_max ? ceil_div(span - delta_max, T) : 0;
+        j.lcol[n] = (int32_t)std::min(shortest, cap);
     }
     j.n_row_tiles = (n_t0 + 63) / 64;
     if (is_exp) {
@@ -324,8 +330,8 @@ void plan_job(Job &j) {
         j.off_gsq = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
         if (j.prec == TFSTAT_PREC_FP64) j.off_g64 = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
     } else {
-        j.off_pabc = take(sizeof(double) * 4 * ((size_t)at.K + 1));
-        j.off_px = take(sizeof(double) * 4 * (size_t)at.n_bins * ((size_t)at.K + 1));
+        j.off_pabc = take(sizeof(double) * 8 * ((size_t)at.K + 1));
+        j.off_px = take(sizeof(double) * 8 * (size_t)at.n_bins * ((size_t)at.K + 1));
     }
     j.off_part = take(sizeof(tfs::Partial) * (size_t)j.n_tiles * at.n_bins);
     j.off_res = take(sizeof(tfs::BinResultDev) * at.n_bins);

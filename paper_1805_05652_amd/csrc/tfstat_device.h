@@ -58,7 +58,7 @@ struct ExpValuParams {
     int32_t pad0;
     const RowPlan *rows;      // [n_t0]
     const int64_t *tau;       // [n_tau]
-    const int32_t *lcol;      // [n_tau] table length per tau (slots)
+    const int32_t *lcol;      // [n_tau] table length per tau: shortest band over rows
     const int32_t *lblk;      // [n_blocks] max lcol over the block
     const int64_t *blk_off;   // [n_blocks] element offset of the block's table
     const int32_t *blk_order; // [n_blocks] block processed at each rank (largest first)
@@ -92,8 +92,8 @@ struct RectParams {
     int32_t n_tiles;          // per bin
     const RowPlan *rows;
     const int64_t *tau;
-    const double *pabc;       // [K+1][4] exclusive prefix
-    const double *px;         // [K+1][n_bins*4]
+    const double *pabc;       // [K+1][8] exclusive prefix: 4 hi then 4 lo terms
+    const double *px;         // [K+1][2][n_bins*4]: hi terms then lo terms
     float *twoF;
     Partial *part;
 };

@@ -144,6 +144,26 @@ def test_single_cell_and_single_sft(ctx):
         assert np.all(ref == 0.0)
 
 
+def test_degenerate_windows(ctx):
+    """Collinear antenna patterns make every window rank one (D = 0), and a
+    pattern vanishing at some SFTs makes single-SFT windows badly scaled;
+    both must give exactly 2F = 0 where the oracle does."""
+    _case("degenerate windows")
+    base = tfsynth.make_atoms(81, 400, 0.1, n_bins=2)
+    x = base.fa[..., 0] / np.where(base.a == 0, 1, base.a)
+    a = base.a.copy()
+    a[::7] *= 1e-5
+    for b_of_a in (lambda a: 2 * a, lambda a: base.b):
+        b = b_of_a(a)
+        fa = np.stack([a * x, 0 * x], -1)
+        fb = np.stack([b * x, 0 * x], -1)
+        atoms = tfsynth.Atoms(base.timestamps, a, b, a * a, b * b, a * b, fa, fb)
+        for kind in ("rect", "exp"):
+            win = tfsynth.regular_window(kind, 0, T, 390, T // 2, T, 12)
+            for prec in ("fp64", "fp32"):
+                run_and_check(ctx, atoms, win, prec)
+
+
 def test_loud_injection_argmax(ctx):
     _case("loud injection")
     t0, tau = 40 * T, 25 * T
