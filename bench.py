@@ -111,6 +111,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="exp1bin", choices=["exp1bin", "exp256", "rect", "rect256"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the map, time a plain device-to-device copy of this many "
+                         "bytes (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py: this path runs on one GPU; --gpus %d is not supported (use --gpus 1)"
@@ -119,7 +122,22 @@ def main(argv=None):
 
     import torch
     import paper_1805_05652_amd as tf
-    from paper_1805_05652_amd import _abi
+
+    if args.copy_bytes:
+        n = args.copy_bytes // 4
+        src = torch.rand(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        print(json.dumps({"copy_bytes": 4 * n, "ms_per_copy": ms,
+                          "GBps_read_plus_write": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return 0
 
     desc, atoms, win = make_workload(args.workload)
     present, slots = work_counts(atoms, win)

@@ -127,6 +127,12 @@ class Context:
         _abi.check(self._lib.tfstat_atoms_free(self._ctx, ctypes.c_uint64(atoms_id)))
         self._bins.pop(atoms_id, None)
 
+    def _n_bins(self, atoms_id: int) -> int:
+        nb = self._bins.get(atoms_id)
+        if nb is None:
+            nb = self.atoms_info(atoms_id)[1]
+        return nb
+
     def atoms_info(self, atoms_id: int):
         k = ctypes.c_int32()
         b = ctypes.c_int32()
@@ -143,7 +149,7 @@ class Context:
         None).  `out` may be a preallocated float32 CUDA tensor for the map.
         """
         wa = _WindowArgs.from_window(win)
-        nb = self._bins[atoms_id]
+        nb = self._n_bins(atoms_id)
         res = (_abi.BinResult * nb)()
         twoF = out
         if want_map and twoF is None:
