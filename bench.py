@@ -103,6 +103,22 @@ def cpu_baseline(atoms, win, budget_s: float = 20.0):
                       % (sample.n_t0, win.n_t0, win.n_tau, atoms.n_bins, dt)}
 
 
+def traffic_from_profile(workload: str, kernel_file: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by a
+    plain copy's reading), or None when the counters are missing or the
+    kernel source changed since they were taken."""
+    import hashlib
+    meta = os.path.join(ROOT, "profiles", kernel_file + "_" + workload + ".json")
+    if not os.path.exists(meta):
+        return None
+    m = json.load(open(meta))
+    src = os.path.join(ROOT, "paper_1805_05652_amd", "csrc", m.get("source", "kernels.hip"))
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m["kernels_source_sha256"]:
+        return None
+    return m["traffic_bytes_per_launch"]
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,7 +192,7 @@ def main(argv=None):
         roof = {"bound": "hbm", "achieved": byts / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = traffic_from_profile(args.workload, "exp_valu" if dom == "exp" else "rect")
     roof["kernel"] = dom
     roof["kernel_avg_ms"] = avg_ms
     out = {
