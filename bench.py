@@ -38,6 +38,22 @@ import tfsynth  # noqa: E402
 T = tfsynth.T_SFT
 PEAK_ALU_TFLOPS = 78.6    # non-packed FP32 and FP64 vector FMA, 256 CU x 64 lanes x 2 x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense bf16 matrix cores
+
+
+def mfma_cells(atoms, win, taus_per_block: int = 8, min_band: int = 64):
+    """cells*present SFTs*bins of the tau blocks long enough for the matrix
+    cores (blocks of 8 consecutive taus whose longest band, in slots, is at
+    least 64; shorter ones run on the VALU).  Rows must start on slots."""
+    T_ = atoms.t_sft
+    span = 3 * win.tau
+    lcol = -(-span // T_)
+    keep = np.zeros(win.n_tau, dtype=bool)
+    for b0 in range(0, win.n_tau, taus_per_block):
+        if lcol[b0:b0 + taus_per_block].max() >= min_band:
+            keep[b0:b0 + taus_per_block] = True
+    sub = tfsynth.Window(win.kind, win.t0, win.tau[keep])
+    return work_counts(atoms, sub)[0]
 
 
 def work_counts(atoms, win):
@@ -125,7 +141,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="exp1bin", choices=["exp1bin", "exp256", "rect", "rect256"])
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the map, time a plain device-to-device copy of this many "
@@ -177,13 +193,24 @@ def main(argv=None):
     ms = (t1 - t0) * 1e3 / args.steps
     value = present / (ms * 1e-3)
 
-    dom = "exp" if win.kind == "exp" else "rect"
+    mfma = win.kind == "exp" and args.prec == "bf16x3" and prof["mfma"][0] > 0
+    dom = "mfma" if mfma else ("exp" if win.kind == "exp" else "rect")
     n_launch, k_ms = prof[dom]
     avg_ms = k_ms / max(n_launch, 1)
-    if win.kind == "exp":
-        # 4 FP32 FMA (F_a, F_b) per cell*SFT*bin + 3 FP64 FMA (A, B, C) per
-        # cell*SFT per bin group
-        flops = 8.0 * present + 6.0 * present
+    if mfma:
+        # 4 complex-by-real MACs = 8 flops per cell*SFT*bin, issued as three
+        # bf16 products (hi*hi + hi*lo + lo*hi): 24 bf16 flops, counted over
+        # the tau blocks the matrix-core kernel runs
+        long_cells = mfma_cells(atoms, win)
+        flops = 24.0 * long_cells
+        roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_BF16_TFLOPS,
+                "unit": "TFLOP/s", "cells_sfts_bins": long_cells}
+    elif win.kind == "exp":
+        # 4 FMA (F_a, F_b) per cell*SFT*bin + 3 FP64 FMA (A, B, C) per cell*SFT
+        # per group of bins sharing a lane
+        bg = 1 if (args.prec == "fp64" or atoms.n_bins == 1) else (4 if atoms.n_bins >= 4 else 2)
+        cells = present // atoms.n_bins
+        flops = 8.0 * present + 6.0 * cells * ((atoms.n_bins + bg - 1) // bg)
         roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_ALU_TFLOPS,
                 "unit": "TFLOP/s"}
     else:

@@ -74,8 +74,11 @@ typedef enum {
  *   FP64   : F_a, F_b sums in FP64.
  *   FP32   : F_a, F_b sums in FP32 (the paper's single precision).
  *   BF16X3 : F_a, F_b sums on bf16 matrix cores with split hi + lo operands
- *            (three products) and FP32 accumulation; exponential windows of
- *            several bins only, other requests fall back to FP32.
+ *            (three products) and FP32 accumulation, for exponential windows
+ *            whose t0 rows fall on consecutive slots with one common offset
+ *            (dt0 = t_sft); bands shorter than 64 slots, and every other
+ *            grid, run the FP32 path.  The first BF16X3 call on an atoms set
+ *            builds its bf16 planes (16 bytes per slot and bin of arena).
  * Rectangular windows use FP64 prefix sums in every mode.
  */
 typedef enum {

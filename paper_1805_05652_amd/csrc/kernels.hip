@@ -129,7 +129,7 @@ struct ExpSmem {
     Red wred[kWaves][BG];
 };
 
-template <typename XT, int R, int BG>
+template <typename XT, int R, int BG, bool ABC_ONLY = false>
 struct ExpAcc {
     double A[R], B[R], C[R];
     XT f[R][BG][4];
@@ -153,6 +153,7 @@ struct ExpAcc {
             A[r] = fma(q, a2, A[r]);
             B[r] = fma(q, b2, B[r]);
             C[r] = fma(q, ab, C[r]);
+            if constexpr (ABC_ONLY) continue;
             const XT g = gw[r];
 #pragma unroll
             for (int b = 0; b < BG; ++b) {
@@ -171,6 +172,7 @@ struct ExpAcc {
             sm.u.comb.abc[j][r][0][lane] = A[r];
             sm.u.comb.abc[j][r][1][lane] = B[r];
             sm.u.comb.abc[j][r][2][lane] = C[r];
+            if constexpr (ABC_ONLY) continue;
 #pragma unroll
             for (int b = 0; b < BG; ++b)
 #pragma unroll
@@ -185,6 +187,7 @@ struct ExpAcc {
             A[r] += sm.u.comb.abc[j][r][0][lane];
             B[r] += sm.u.comb.abc[j][r][1][lane];
             C[r] += sm.u.comb.abc[j][r][2][lane];
+            if constexpr (ABC_ONLY) continue;
 #pragma unroll
             for (int b = 0; b < BG; ++b)
 #pragma unroll
@@ -193,7 +196,7 @@ struct ExpAcc {
     }
 };
 
-template <typename XT, int R, int BG>
+template <typename XT, int R, int BG, bool ABC_ONLY = false>
 __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
     __shared__ ExpSmem<XT, R, BG> sm;
     const int tid = threadIdx.x;
@@ -208,10 +211,10 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
     const int xcd = bid & 7;
     const int slot = bid >> 3;
     const int q = (slot / p.n_row_tiles) * 8 + xcd;
-    if (q >= p.n_blocks) return;
+    if (q >= p.n_list) return;
     const int row_tile = slot % p.n_row_tiles;
-    const int nb = p.blk_order[q];
-    const int tile = q * p.n_row_tiles + row_tile;
+    const int nb = p.blk_list[q];
+    const int tile = nb * p.n_row_tiles + row_tile;
     const int bin0 = blockIdx.y * BG;
     const int n_bins = p.at.n_bins;
     const int K = p.at.K;
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
     const XT *__restrict__ xg = xplane<XT>(p.at);
     const double *__restrict__ abc = p.at.abc;
 
-    ExpAcc<XT, R, BG> acc;
+    ExpAcc<XT, R, BG, ABC_ONLY> acc;
     acc.zero();
 
     if (spread <= kSpreadMax) {
@@ -254,12 +257,14 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
                 sm.u.stage.a2[i] = a2;
                 sm.u.stage.b2[i] = b2;
                 sm.u.stage.ab[i] = ab;
+                if constexpr (!ABC_ONLY) {
 #pragma unroll
-                for (int b = 0; b < BG; ++b) {
-                    Q4<XT> x{XT(0), XT(0), XT(0), XT(0)};
-                    if (in && bin0 + b < n_bins)
-                        x = load_q4(xg + ((size_t)k * n_bins + bin0 + b) * 4);
-                    sm.u.stage.x[b][i] = x;
+                    for (int b = 0; b < BG; ++b) {
+                        Q4<XT> x{XT(0), XT(0), XT(0), XT(0)};
+                        if (in && bin0 + b < n_bins)
+                            x = load_q4(xg + ((size_t)k * n_bins + bin0 + b) * 4);
+                        sm.u.stage.x[b][i] = x;
+                    }
                 }
             }
             __syncthreads();
@@ -269,8 +274,10 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
             for (int dd = ds; dd < de; ++dd) {
                 const int li = my + dd;
                 Q4<XT> x[BG];
+                if constexpr (!ABC_ONLY) {
 #pragma unroll
-                for (int b = 0; b < BG; ++b) x[b] = sm.u.stage.x[b][li];
+                    for (int b = 0; b < BG; ++b) x[b] = sm.u.stage.x[b][li];
+                }
                 const int d = d0 + dd;
                 acc.step(gw_base + (size_t)d * R, gq_base + (size_t)d * R,
                          sm.u.stage.a2[li], sm.u.stage.b2[li], sm.u.stage.ab[li], x);
@@ -287,10 +294,12 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
             const double2 v = *reinterpret_cast<const double2 *>(abc + (size_t)kk * 4);
             const double ab = abc[(size_t)kk * 4 + 2];
             Q4<XT> x[BG];
+            if constexpr (!ABC_ONLY) {
 #pragma unroll
-            for (int b = 0; b < BG; ++b)
-                x[b] = (bin0 + b < n_bins) ? load_q4(xg + ((size_t)kk * n_bins + bin0 + b) * 4)
-                                           : Q4<XT>{XT(0), XT(0), XT(0), XT(0)};
+                for (int b = 0; b < BG; ++b)
+                    x[b] = (bin0 + b < n_bins) ? load_q4(xg + ((size_t)kk * n_bins + bin0 + b) * 4)
+                                               : Q4<XT>{XT(0), XT(0), XT(0), XT(0)};
+            }
             acc.step(gw_base + (size_t)d * R, gq_base + (size_t)d * R, v.x, v.y, ab, x);
         }
     }
@@ -331,7 +340,8 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
 #pragma unroll
         for (int b = 0; b < BG; ++b)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) f[b][c] = (double)sm.u.comb.f[0][r][b][c][lane];
+            for (int c = 0; c < 4; ++c)
+                f[b][c] = ABC_ONLY ? 0.0 : (double)sm.u.comb.f[0][r][b][c][lane];
         // The table holds the shortest band over all rows of the grid; a row
         // whose band reaches further (smaller delta) adds its last terms
         // here, in FP64, with weights exp(-d T / tau).
@@ -346,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
             C += qd * abc[k * 4 + 2];
 #pragma unroll
             for (int b = 0; b < BG; ++b) {
-                if (bin0 + b >= n_bins) continue;
+                if (ABC_ONLY || bin0 + b >= n_bins) continue;
                 const Q4<XT> x = load_q4(xg + ((size_t)k * n_bins + bin0 + b) * 4);
                 f[b][0] += gd * (double)x.x;
                 f[b][1] += gd * (double)x.y;
@@ -363,6 +373,15 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) f[b][c] *= s;
         }
+        if constexpr (ABC_ONLY) {
+            if (ok) {
+                double *o = p.abc_out + ((size_t)m * p.n_tau + n) * 3;
+                o[0] = A;
+                o[1] = B;
+                o[2] = C;
+            }
+            continue;
+        }
 #pragma unroll
         for (int b = 0; b < BG; ++b) {
             const int bin = bin0 + b;
@@ -373,6 +392,7 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
             red[b] = red_combine(red[b], cell);
         }
     }
+    if constexpr (ABC_ONLY) return;
 #pragma unroll
     for (int b = 0; b < BG; ++b) {
         const Red w = red_wave(red[b]);
@@ -619,8 +639,17 @@ void exp_valu_config(int prec, int n_bins, int *R, int *BG) {
     }
 }
 
+hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s) {
+    if (p.n_list <= 0) return hipSuccess;
+    const int groups = (p.n_list + 7) / 8;
+    const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), 1u);
+    hipLaunchKernelGGL((exp_valu_kernel<float, 8, 1, true>), grid, dim3(kThreads), 0, s, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, hipStream_t s) {
-    const int groups = (p.n_blocks + 7) / 8;
+    if (p.n_list <= 0) return hipSuccess;
+    const int groups = (p.n_list + 7) / 8;
     const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), (unsigned)((p.at.n_bins + BG - 1) / BG));
     if (prec == 0 && R == 4 && BG == 1)
         hipLaunchKernelGGL((exp_valu_kernel<double, 4, 1>), grid, dim3(kThreads), 0, s, p);

@@ -166,6 +166,10 @@ struct AtomsSet {
     double *abc = nullptr;
     double *x64 = nullptr;
     float *x32 = nullptr;
+    // bf16 hi / lo planes for the matrix-core path, built on first use
+    void *planes = nullptr;
+    unsigned short *xhi = nullptr, *xlo = nullptr;
+    int32_t bins16 = 0, kp = 0;
     int busy = 0;
     tfs::AtomsView view() const {
         tfs::AtomsView v;
@@ -218,6 +222,9 @@ WindowOwned copy_window(const tfstat_window *w) {
 
 enum { NK = TFSTAT_K_COUNT };
 
+constexpr int kMfmaTaus = 8;       // taus per matrix-core work item
+constexpr int kMfmaMinBand = 64;   // shorter bands stay on the VALU path
+
 // ---------------------------------------------------------------------------
 // One map computation: plan (host, integer), workspace, launches, results.
 // ---------------------------------------------------------------------------
@@ -233,6 +240,8 @@ struct Job {
     std::vector<int64_t> blk_off;
     int R = 0, BG = 0, NB = 0, n_row_tiles = 0, n_tiles = 0, n_tiles_n = 0;
     int64_t wtot = 0, max_blk = 0;
+    bool use_mfma = false;     // BF16X3 on matrix cores for long bands
+    int n_valu = 0, n_mfma = 0;  // block lists: order[0..n_valu) VALU, then MFMA
 
     // memory
     size_t ws_bytes = 0;
@@ -242,7 +251,7 @@ struct Job {
     size_t off_rows = 0, off_tau = 0, off_lcol = 0, off_lblk = 0, off_boff = 0, off_order = 0,
            tables_bytes = 0;
     size_t off_g32 = 0, off_gsq = 0, off_g64 = 0, off_pabc = 0, off_px = 0, off_part = 0,
-           off_res = 0;
+           off_res = 0, off_abc = 0;
 
     // timing
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timed;
@@ -282,9 +291,21 @@ void plan_job(Job &j) {
         j.lcol[n] = (int32_t)std::min(shortest, cap);
     }
     j.n_row_tiles = (n_t0 + 63) / 64;
+    // Matrix-core path: BF16X3, rows on consecutive slots with one delta.
+    j.use_mfma = false;
+    if (is_exp && j.prec == TFSTAT_PREC_BF16X3 && j.rows[0].k0 >= 0) {
+        bool ok = true;
+        for (int m = 1; m < n_t0 && ok; ++m)
+            ok = j.rows[m].k0 == j.rows[0].k0 + m && j.rows[m].delta == j.rows[0].delta;
+        j.use_mfma = ok;
+    }
     if (is_exp) {
         const int prec = (j.prec == TFSTAT_PREC_FP64) ? 0 : 1;
         tfs::exp_valu_config(prec, at.n_bins, &j.R, &j.BG);
+        if (j.use_mfma) {
+            j.R = kMfmaTaus;
+            j.BG = 1;
+        }
         j.NB = (n_tau + j.R - 1) / j.R;
         j.lblk.assign(j.NB, 0);
         j.blk_off.assign(j.NB, 0);
@@ -304,6 +325,18 @@ void plan_job(Job &j) {
         std::stable_sort(j.order.begin(), j.order.end(),
                          [&](int a, int b) { return j.lblk[a] > j.lblk[b]; });
         j.n_tiles = j.NB * j.n_row_tiles;
+        j.n_valu = j.NB;
+        j.n_mfma = 0;
+        if (j.use_mfma) {
+            // short bands stay on the FP32 VALU path: little work, and the
+            // worst-conditioned windows
+            std::vector<int32_t> lv, lm;
+            for (int32_t b : j.order) (j.lblk[b] >= kMfmaMinBand ? lm : lv).push_back(b);
+            j.n_valu = (int)lv.size();
+            j.n_mfma = (int)lm.size();
+            j.order = lv;
+            j.order.insert(j.order.end(), lm.begin(), lm.end());
+        }
     } else {
         j.n_tiles_n = (n_tau + 63) / 64;
         j.n_tiles = j.n_tiles_n * ((n_t0 + 3) / 4);
@@ -329,6 +362,7 @@ void plan_job(Job &j) {
         j.off_g32 = take(sizeof(float) * std::max<int64_t>(j.wtot, 1));
         j.off_gsq = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
         if (j.prec == TFSTAT_PREC_FP64) j.off_g64 = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
+        if (j.use_mfma && j.n_mfma > 0) j.off_abc = take(sizeof(double) * 3 * (size_t)n_t0 * n_tau);
     } else {
         j.off_pabc = take(sizeof(double) * 8 * ((size_t)at.K + 1));
         j.off_px = take(sizeof(double) * 8 * (size_t)at.n_bins * ((size_t)at.K + 1));
@@ -501,25 +535,62 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         p.n_t0 = n_t0;
         p.n_tau = n_tau;
         p.n_row_tiles = j.n_row_tiles;
-        p.n_blocks = j.NB;
-        p.n_tasks = j.NB * j.n_row_tiles;
-        p.tasks_per_xcd = 0;
+        p.n_list = j.n_valu;
         p.n_tiles = j.n_tiles;
         p.rows = rows;
         p.tau = tau;
         p.lcol = lcol;
         p.lblk = wp.lblk;
         p.blk_off = wp.blk_off;
-        p.blk_order = ws_ptr<int32_t>(j, j.off_order);
+        p.blk_list = ws_ptr<int32_t>(j, j.off_order);
         p.g32 = wp.g32;
         p.g64 = wp.g64;
         p.gsq = wp.gsq;
         p.twoF = j.twoF;
         p.part = part;
-        record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
-        hip_check(tfs::launch_exp_valu(p, j.prec == TFSTAT_PREC_FP64 ? 0 : 1, j.R, j.BG, s),
-                  "exp kernel");
-        record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
+        p.abc_out = nullptr;
+        if (j.n_valu > 0) {
+            record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
+            hip_check(tfs::launch_exp_valu(p, j.prec == TFSTAT_PREC_FP64 ? 0 : 1, j.R, j.BG, s),
+                      "exp kernel");
+            record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
+        }
+        if (j.n_mfma > 0) {
+            tfs::ExpValuParams pa = p;
+            pa.n_list = j.n_mfma;
+            pa.blk_list = p.blk_list + j.n_valu;
+            pa.twoF = nullptr;
+            pa.abc_out = ws_ptr<double>(j, j.off_abc);
+            record_kernel(ctx, j, TFSTAT_K_ABC, s, true);
+            hip_check(tfs::launch_exp_abc(pa, s), "exp abc kernel");
+            record_kernel(ctx, j, TFSTAT_K_ABC, s, false);
+            tfs::ExpMfmaParams q{};
+            q.n_bins = at.n_bins;
+            q.bins16 = at.bins16;
+            q.kp = at.kp;
+            q.kp_data = (at.K + 31) & ~31;
+            q.n_t0 = n_t0;
+            q.n_tau = n_tau;
+            q.n_row_tiles = j.n_row_tiles;
+            q.n_col_tiles = at.bins16 / 16;
+            q.n_blocks = j.n_mfma;
+            q.n_tiles = j.n_tiles;
+            q.k0_first = j.rows[0].k0;
+            q.delta = j.rows[0].delta;
+            q.tau = tau;
+            q.lblk = wp.lblk;
+            q.blk_off = wp.blk_off;
+            q.blk_list = pa.blk_list;
+            q.g32 = wp.g32;
+            q.xhi = at.xhi;
+            q.xlo = at.xlo;
+            q.abc_cell = pa.abc_out;
+            q.twoF = j.twoF;
+            q.part = part;
+            record_kernel(ctx, j, TFSTAT_K_MFMA, s, true);
+            hip_check(tfs::launch_exp_mfma(q, s), "exp mfma kernel");
+            record_kernel(ctx, j, TFSTAT_K_MFMA, s, false);
+        }
     } else {
         double *pabc = ws_ptr<double>(j, j.off_pabc);
         double *px = ws_ptr<double>(j, j.off_px);
@@ -573,6 +644,35 @@ void finish_job(tfstat_ctx *ctx, Job &j, tfstat_bin_result *out) {
         o.tau = j.win.tau[o.n];
         out[b] = o;
     }
+}
+
+// bf16 hi / lo planes of the data atoms for the matrix-core path; built
+// once per atoms set on the context stream.  Caller holds ctx->mu.
+void ensure_planes(tfstat_ctx *ctx, AtomsSet *at) {
+    if (at->planes) return;
+    const int32_t bins16 = (at->n_bins + 15) / 16 * 16;
+    const int32_t kp = (at->K + 31) / 32 * 32 + 32;
+    const size_t plane = sizeof(unsigned short) * 4 * (size_t)bins16 * kp;
+    const size_t plane_b = round_up(plane, 256);
+    void *mem = ctx->arena.alloc(2 * plane_b);
+    if (!mem) raise(TFSTAT_E_NOMEM, "arena cannot hold the bf16 planes");
+    try {
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        auto *xhi = static_cast<unsigned short *>(mem);
+        auto *xlo = reinterpret_cast<unsigned short *>(static_cast<char *>(mem) + plane_b);
+        hip_check(tfs::launch_build_planes(at->x32, at->K, at->n_bins, bins16, kp, xhi, xlo, ctx->stream),
+                  "planes kernel");
+        hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        at->xhi = xhi;
+        at->xlo = xlo;
+    } catch (...) {
+        ctx->arena.release(mem);
+        throw;
+    }
+    at->planes = mem;
+    at->bins16 = bins16;
+    at->kp = kp;
+    at->bytes += 2 * plane_b;
 }
 
 AtomsSet *find_atoms(tfstat_ctx *ctx, tfstat_atoms_id id) {
@@ -836,6 +936,7 @@ int tfstat_atoms_free(tfstat_ctx *ctx, tfstat_atoms_id id) {
         AtomsSet *s = find_atoms(ctx, id);
         if (s->busy > 0) raise(TFSTAT_E_BUSY, "atoms are in use by submitted requests");
         ctx->arena.release(s->mem);
+        if (s->planes) ctx->arena.release(s->planes);
         ctx->atoms.erase(id);
         return (int)TFSTAT_OK;
     });
@@ -859,12 +960,11 @@ int tfstat_fmap(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win, i
         if (precision != TFSTAT_PREC_FP64 && precision != TFSTAT_PREC_FP32 &&
             precision != TFSTAT_PREC_BF16X3)
             raise(TFSTAT_E_INVAL, "unknown precision");
-        if (precision == TFSTAT_PREC_BF16X3)
-            raise(TFSTAT_E_INVAL, "BF16X3 precision is not available in this build");
         Job j;
         {
             std::lock_guard<std::mutex> g(ctx->mu);
             j.at = find_atoms(ctx, id);
+            if (precision == TFSTAT_PREC_BF16X3) ensure_planes(ctx, j.at);
         }
         j.win = copy_window(win);
         j.prec = precision;
@@ -951,13 +1051,12 @@ int tfstat_submit(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win,
         if (precision != TFSTAT_PREC_FP64 && precision != TFSTAT_PREC_FP32 &&
             precision != TFSTAT_PREC_BF16X3)
             raise(TFSTAT_E_INVAL, "unknown precision");
-        if (precision == TFSTAT_PREC_BF16X3)
-            raise(TFSTAT_E_INVAL, "BF16X3 precision is not available in this build");
         auto job = std::make_unique<Job>();
         job->win = copy_window(win);
         job->prec = precision;
         std::lock_guard<std::mutex> g(ctx->mu);
         job->at = find_atoms(ctx, id);
+        if (precision == TFSTAT_PREC_BF16X3) ensure_planes(ctx, job->at);
         plan_job(*job);
         // A request whose workspace cannot fit beside the resident atoms
         // would wait forever: refuse it now.

@@ -51,22 +51,45 @@ struct ExpValuParams {
     AtomsView at;
     int32_t n_t0, n_tau;
     int32_t n_row_tiles;      // ceil(n_t0 / 64)
-    int32_t n_blocks;         // ceil(n_tau / R)
-    int32_t n_tasks;          // n_row_tiles * n_blocks
-    int32_t tasks_per_xcd;    // ceil(n_tasks_padded / 8)
-    int32_t n_tiles;          // partial slots per bin (== n_tasks)
+    int32_t n_list;           // number of tau blocks this launch processes
+    int32_t n_tiles;          // partial slots per bin (all blocks x row tiles)
     int32_t pad0;
     const RowPlan *rows;      // [n_t0]
     const int64_t *tau;       // [n_tau]
     const int32_t *lcol;      // [n_tau] table length per tau: shortest band over rows
     const int32_t *lblk;      // [n_blocks] max lcol over the block
     const int64_t *blk_off;   // [n_blocks] element offset of the block's table
-    const int32_t *blk_order; // [n_blocks] block processed at each rank (largest first)
+    const int32_t *blk_list;  // [n_list] blocks processed, largest band first
     const float *g32;         // weight tables [blk][d][R]
     const double *g64;        //   (FP64 weights, FP64 mode only)
     const double *gsq;        //   (squared weights, FP64)
     float *twoF;              // optional map [n_bins][n_t0][n_tau]
     Partial *part;            // [n_bins][n_tiles]
+    double *abc_out;          // A/B/C-only mode: [n_t0][n_tau][3] (scaled, exact band)
+};
+
+// Exponential-window F_a, F_b on bf16 matrix cores for grids whose t0 rows
+// are consecutive slots with one common delta.
+struct ExpMfmaParams {
+    int32_t n_bins, bins16;   // bins, rounded up to 16
+    int32_t kp;               // plane pitch (slots), multiple of 32
+    int32_t kp_data;          // round_up(K, 32): slots that may hold data
+    int32_t n_t0, n_tau;
+    int32_t n_row_tiles;      // ceil(n_t0 / 64)
+    int32_t n_col_tiles;      // bins16 / 16
+    int32_t n_blocks;         // blocks in blk_list
+    int32_t n_tiles;          // partial slots per bin
+    int32_t k0_first;         // slot of row 0 (>= 0); row m starts at k0_first + m
+    int32_t delta;            // t_{k0} - t0, common to all rows
+    const int64_t *tau;
+    const int32_t *lblk;      // [blocks] band length of the block's table
+    const int64_t *blk_off;   // [blocks] table offsets, [blk][d][8] layout
+    const int32_t *blk_list;  // [n_blocks]
+    const float *g32;         // FP32 weights g_n[d]
+    const unsigned short *xhi, *xlo;  // [4][bins16][kp] bf16 planes
+    const double *abc_cell;   // [n_t0][n_tau][3]
+    float *twoF;
+    Partial *part;
 };
 
 struct WeightParams {
@@ -124,6 +147,12 @@ hipError_t launch_weights(const WeightParams &p, int64_t total_max_per_block,
 // from the supported set reported by exp_valu_config().
 hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG,
                            hipStream_t s);
+// A/B/C only (FP64), R = 8 blocks, into p.abc_out.
+hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s);
+hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s);
+hipError_t launch_build_planes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16,
+                               int32_t kp, unsigned short *xhi, unsigned short *xlo,
+                               hipStream_t s);
 hipError_t launch_scan(const double *in, int64_t in_row_stride, double *out,
                        int32_t K, int32_t C, hipStream_t s);
 hipError_t launch_rect(const RectParams &p, hipStream_t s);

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 T = tfsynth.T_SFT
 F32_MAP = 2.0 ** -23
-TOL = {"fp32": 1e-4, "fp64": 1e-9}
+TOL = {"fp32": 1e-4, "fp64": 1e-9, "bf16x3": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -229,6 +229,51 @@ def test_full_exp_256_bins_sampled(ctx):
         F = got[b].astype(np.float64).ravel() / 2
         lb = F.max() + np.log(np.exp(F - F.max()).sum()) - np.log(F.size)
         assert abs(res[b]["logB"] - lb) <= 1e-4
+
+
+@pytest.mark.parametrize("case", ["offset", "tail", "sparse_rows"])
+def test_bf16x3_ragged(ctx, case):
+    """Matrix-core path: 21 bins (ragged bin tile), rows off the slot grid by
+    a common offset, a partial row tile, bands past the data end; sparse rows
+    fall back to the FP32 path."""
+    _case("bf16x3 " + case)
+    atoms = tfsynth.make_atoms(3, 777, 0.1, n_bins=21,
+                               injections=[tfsynth.Injection(4, "exp", 90 * T, 50 * T, 0.8)])
+    if case == "offset":
+        win = tfsynth.regular_window("exp", 5 * T + 77, T, 123, 2 * T, 3 * T + 5, 61)
+    elif case == "tail":
+        win = tfsynth.regular_window("exp", 700 * T, T, 77, 2 * T, 40 * T, 9)
+    else:
+        win = tfsynth.regular_window("exp", 0, 3 * T, 90, 2 * T, 5 * T, 30)
+    _, _, err = run_and_check(ctx, atoms, win, "bf16x3")
+    print("bf16x3 %s: max rel err %.3e" % (case, err), flush=True)
+
+
+def test_full_exp_256_bins_bf16x3(ctx):
+    """256 bins on matrix cores against the oracle on sampled cells, and
+    against the FP32 VALU form on the whole map."""
+    _case("full exp 256 bins bf16x3")
+    atoms, win = tfsynth.workload_exp_bins()
+    aid = ctx.upload_atoms(atoms)
+    try:
+        res, twoF = ctx.fmap(aid, win, "bf16x3", want_map=True)
+        res32, twoF32 = ctx.fmap(aid, win, "fp32", want_map=True)
+    finally:
+        ctx.free(aid)
+    got = twoF.cpu().numpy()
+    rng = np.random.default_rng(29)
+    mi, ni = _sample_cells(rng, win, 400)
+    ref = oracle.cells("exp", atoms.timestamps, atoms.a2, atoms.b2, atoms.ab, atoms.fa, atoms.fb,
+                       win.t0, win.tau, mi, ni)
+    err = check_map(got[:, mi, ni], ref, 1e-4)
+    g32 = twoF32.cpu().numpy().astype(np.float64)
+    dev = np.abs(got - g32) / np.maximum(g32, 1.0)
+    print("bf16x3 256 bins: max rel err vs oracle (sampled) %.3e, vs fp32 map %.3e"
+          % (err, dev.max()), flush=True)
+    assert dev.max() <= 2e-4
+    for b in range(atoms.n_bins):
+        assert abs(res[b]["logB"] - res32[b]["logB"]) <= 1e-3
+        assert abs(res[b]["max2F"] - res32[b]["max2F"]) <= 2e-4 * max(res32[b]["max2F"], 1.0)
 
 
 def test_full_rect_workload_results(ctx):
