@@ -42,15 +42,15 @@ PEAK_BF16_TFLOPS = 2500.0  # dense bf16 matrix cores
 
 
 def mfma_cells(atoms, win, taus_per_block: int = 8, min_band: int = 64):
-    """cells*present SFTs*bins of the tau blocks long enough for the matrix
-    cores (blocks of 8 consecutive taus whose longest band, in slots, is at
-    least 64; shorter ones run on the VALU).  Rows must start on slots."""
+    """cells*present SFTs*bins of the tau blocks that run on the matrix cores
+    (blocks of 8 consecutive taus whose shortest band is at least 64 slots;
+    the others run on the VALU).  Rows must start on slots."""
     T_ = atoms.t_sft
     span = 3 * win.tau
     lcol = -(-span // T_)
     keep = np.zeros(win.n_tau, dtype=bool)
     for b0 in range(0, win.n_tau, taus_per_block):
-        if lcol[b0:b0 + taus_per_block].max() >= min_band:
+        if lcol[b0:b0 + taus_per_block].min() >= min_band:
             keep[b0:b0 + taus_per_block] = True
     sub = tfsynth.Window(win.kind, win.t0, win.tau[keep])
     return work_counts(atoms, sub)[0]
@@ -135,6 +135,72 @@ def traffic_from_profile(workload: str, kernel_file: str):
     return m["traffic_bytes_per_launch"]
 
 
+def serving(ctx, seed: int = 4000, rate_hz: float = 200.0, duration_s: float = 4.0,
+            precision: str = "fp32", max_slots: int = 10000, max_grid: int = 2000,
+            max_bins: int = 64):
+    """Served maps: a Poisson stream of map requests over resident atoms.
+
+    Each request (slots log-uniform up to max_slots, grids up to max_grid,
+    1..max_bins bins, window type random) is uploaded before the stream
+    starts; requests are then submitted at their arrival times and polled.
+    Latency is arrival to observed completion.  The baseline runs the same
+    requests one after another through tfstat_fmap in plain FP32 and derives
+    FIFO latencies from the measured service times and the same arrivals."""
+    reqs = tfsynth.request_stream(seed, rate_hz, duration_s, max_slots, max_grid, max_bins)
+    jobs = []
+    for r in reqs:
+        atoms, win = tfsynth.request_atoms(r)
+        jobs.append((r["arrival"], ctx.upload_atoms(atoms), win, atoms.n_bins))
+        del atoms
+    # warm the kernels
+    ctx.fmap(jobs[0][1], jobs[0][2], precision)
+    t_start = time.perf_counter() + 0.05
+    pending = {}
+    lat = []
+    i = 0
+    while i < len(jobs) or pending:
+        now = time.perf_counter() - t_start
+        while i < len(jobs) and jobs[i][0] <= now:
+            arr, aid, win, nb = jobs[i]
+            pending[ctx.submit(aid, win, precision)] = (arr, nb)
+            i += 1
+        for t, (arr, nb) in list(pending.items()):
+            if ctx.poll(t, nb) is not None:
+                lat.append(time.perf_counter() - t_start - arr)
+                del pending[t]
+        if not pending and i < len(jobs):
+            time.sleep(max(0.0, min(0.0005, jobs[i][0] - (time.perf_counter() - t_start))))
+    wall = time.perf_counter() - t_start
+    # sequential plain FP32 baseline on the same requests
+    svc = []
+    for arr, aid, win, nb in jobs:
+        t0 = time.perf_counter()
+        ctx.fmap(aid, win, "fp32")
+        svc.append(time.perf_counter() - t0)
+    free_at = 0.0
+    seq_lat = []
+    for (arr, _, _, _), sv in zip(jobs, svc):
+        start = max(arr, free_at)
+        free_at = start + sv
+        seq_lat.append(free_at - arr)
+    for _, aid, _, _ in jobs:
+        ctx.free(aid)
+    lat = np.array(lat) * 1e3
+    seq_lat = np.array(seq_lat) * 1e3
+    return {
+        "requests": len(jobs), "offered_rate_hz": rate_hz, "duration_s": duration_s,
+        "precision": precision, "maps_per_s": len(jobs) / wall,
+        "bin_maps_per_s": sum(j[3] for j in jobs) / wall,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "sequential_fp32": {"maps_per_s": len(jobs) / sum(svc),
+                            "p50_ms": float(np.percentile(seq_lat, 50)),
+                            "p99_ms": float(np.percentile(seq_lat, 99))},
+        "workload": "Poisson %.0f/s for %.1f s; slots log-uniform [200, %d], grids U{100..%d}, "
+                    "bins U{1..%d}, rect or exp at random, linspace grids" %
+                    (rate_hz, duration_s, max_slots, max_grid, max_bins),
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +209,12 @@ def main(argv=None):
     ap.add_argument("--workload", default="exp1bin", choices=["exp1bin", "exp256", "rect", "rect256"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-map", action="store_true",
+                    help="do not write the 2F map (per-bin results only)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="length of the served request stream (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the map, time a plain device-to-device copy of this many "
                          "bytes (calibrates HBM byte counters)")
@@ -173,9 +245,10 @@ def main(argv=None):
 
     desc, atoms, win = make_workload(args.workload)
     present, slots = work_counts(atoms, win)
-    ctx = tf.Context(0, arena_bytes=4 << 30)
+    ctx = tf.Context(0, arena_bytes=(24 << 30) if args.serve_seconds > 0 else (4 << 30))
     aid = ctx.upload_atoms(atoms)
-    twoF = torch.empty((atoms.n_bins, win.n_t0, win.n_tau), dtype=torch.float32, device="cuda:0")
+    twoF = None if args.no_map else torch.empty((atoms.n_bins, win.n_t0, win.n_tau),
+                                                  dtype=torch.float32, device="cuda:0")
     for _ in range(args.warmup):
         ctx.fmap(aid, win, args.prec, out=twoF)
     torch.cuda.synchronize()
@@ -223,7 +296,7 @@ def main(argv=None):
     roof["kernel"] = dom
     roof["kernel_avg_ms"] = avg_ms
     out = {
-        "metric": "F-map cells*SFTs/s (exp window)",
+        "metric": "F-map cells*SFTs/s (exp window) and served maps/s with p50/p99 latency",
         "value": value,
         "unit": "cells*SFTs/s",
         "n_gpus": 1,
@@ -233,17 +306,21 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16x3": "bf16x3(f32 acc)+f64"}[args.prec],
         "data": "synthetic",
         "config": {"workload": desc, "n_slots": atoms.n_slots, "n_sft": atoms.n_sft,
                    "n_t0": win.n_t0, "n_tau": win.n_tau, "n_bins": atoms.n_bins,
                    "window": win.kind, "precision": args.prec, "cells_sfts": present,
-                   "cells_slots": slots, "parallelism": "single GPU"},
+                   "cells_slots": slots, "map_written": not args.no_map,
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "kernels_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in prof.items()},
         "result_bin0": res[0],
     }
     ctx.free(aid)
+    if args.serve_seconds > 0:
+        out["serving"] = serving(ctx, rate_hz=args.serve_rate, duration_s=args.serve_seconds,
+                                 precision=args.serve_prec)
     ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(atoms, win)

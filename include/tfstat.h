@@ -76,8 +76,8 @@ typedef enum {
  *   BF16X3 : F_a, F_b sums on bf16 matrix cores with split hi + lo operands
  *            (three products) and FP32 accumulation, for exponential windows
  *            whose t0 rows fall on consecutive slots with one common offset
- *            (dt0 = t_sft); bands shorter than 64 slots, and every other
- *            grid, run the FP32 path.  The first BF16X3 call on an atoms set
+ *            (dt0 = t_sft); groups of 8 taus holding a band shorter than
+ *            64 slots, and every other grid, run the FP32 path.  The first BF16X3 call on an atoms set
  *            builds its bf16 planes (16 bytes per slot and bin of arena).
  * Rectangular windows use FP64 prefix sums in every mode.
  */

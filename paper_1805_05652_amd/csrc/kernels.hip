@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
         }
         if constexpr (ABC_ONLY) {
             if (ok) {
-                double *o = p.abc_out + ((size_t)m * p.n_tau + n) * 3;
+                double *o = p.abc_out + ((size_t)m * p.abc_pitch + n) * 3;
                 o[0] = A;
                 o[1] = B;
                 o[2] = C;

@@ -13,10 +13,11 @@
 // and three products W_hi X_hi + W_hi X_lo + W_lo X_hi are accumulated in
 // FP32.  A, B, C (FP64) come from the VALU kernel in its A/B/C-only mode.
 //
-// Work item: 64 consecutive t0 rows x 16 bins (64 data columns) x 8 taus.
-// Wave w owns rows 16w..16w+15; its four 16x16 output tiles per tau are the
-// four data components of the same 16 bins, so every lane ends with all four
-// components of (row, bin) cells and finalizes them in place.
+// Work item: 64 consecutive t0 rows x 16 bins (64 data columns) x 8 taus,
+// in two passes of 4 taus.  Wave w owns rows 16w..16w+15; its four 16x16
+// output tiles per tau are the four data components of the same 16 bins, so
+// every lane ends with all four components of (row, bin) cells and
+// finalizes them in place.
 #include "tfstat_device.h"
 
 #include <hip/hip_runtime.h>
@@ -31,9 +32,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kNT = 8;        // taus per work item (== VALU block width)
+constexpr int kBlk = 8;       // taus per block (shared with the VALU tiling)
+constexpr int kNT = 4;        // taus per matrix-core pass (two passes per block)
 constexpr int kSK = 256;      // band slots per staged weight window
-constexpr int kTW = kSK + 64; // staged weight window width
+constexpr int kTW = kSK + 72; // staged window width (multiple of 8)
+constexpr int kPad = 128;     // zero entries in front of every shifted table
+constexpr int kRowChunks = kTW / 8;                 // 16-byte chunks per table row
+constexpr int kTabChunks = kNT * 16 * kRowChunks;   // chunks per staged window
+constexpr int kTabInstr = (kTabChunks + 63) / 64;   // 64-lane copies per window
+constexpr int kAbcChunks = 64 * kBlk * 3 / 2;       // A/B/C of the tile, 16-byte chunks
 
 struct Red {
     double f;
@@ -91,26 +98,74 @@ __device__ inline T bitcast4(u32x4 v) {
     return __builtin_bit_cast(T, v);
 }
 
-__global__ __launch_bounds__(256) void exp_mfma_kernel(ExpMfmaParams p) {
-    __shared__ unsigned int tab[kNT][kTW];
+// Shifted bf16 weight tables, built once per map: for block nb, tau t,
+// part (0 = hi, 1 = lo) and shift s, entry x holds part(g_t[x - kPad + s])
+// (zero outside 0 <= d < lblk), so that 8 weights starting anywhere are one
+// aligned 16-byte read from the copy matching their start modulo 8.
+__global__ __launch_bounds__(256) void shift_tables_kernel(ShiftTableParams p) {
+    const int nb = p.blk_list[blockIdx.y];
+    const int lblk = p.lblk[nb];
+    const int lg = p.lg[nb];
+    const int64_t src = p.blk_off[nb];
+    unsigned short *dst = p.gsh + p.gsh_off[nb];
+    const int64_t total = (int64_t)kBlk * 2 * 8 * lg;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const int x = (int)(i % lg);
+        const int64_t r = i / lg;
+        const int sh = (int)(r % 8);
+        const int part = (int)((r / 8) % 2);
+        const int t = (int)(r / 16);
+        const int d = x - kPad + sh;
+        float g = 0.f;
+        if (d >= 0 && d < lblk) g = p.g32[src + (int64_t)d * kBlk + t];
+        const unsigned int pk = split_pack(g);
+        dst[i] = (unsigned short)(part ? (pk >> 16) : (pk & 0xffffu));
+    }
+}
+
+// Copies 16 bytes per lane from global memory straight into LDS: lane l of
+// the wave writes dst + 16 l (gfx950 global_load_lds_dwordx4).
+__device__ inline void copy16_to_lds(const void *src, void *dst_wave_base) {
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst_wave_base, 16, 0,
+                                     0);
+}
+
+__global__ __launch_bounds__(256, 2) void exp_mfma_kernel(ExpMfmaParams p) {
+    // weight window: flat 16-byte chunks, row (t, part, shift) by row
+    __shared__ __attribute__((aligned(16))) unsigned short tab[kTabInstr * 64 * 8];
+    __shared__ __attribute__((aligned(16))) double abcs[64][kBlk][3];
     __shared__ Red wred[4][16];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    // task decode: (block rank q, row tile, column tile); block ranks are
-    // dealt round-robin to the 8 XCDs (workgroup b runs on XCD b % 8), the
-    // tasks of one block stay on one XCD.
-    const int per_block = p.n_row_tiles * p.n_col_tiles;
+    // Task decode.  Workgroup b runs on XCD b % 8, and each XCD has its own
+    // L2.  With 8 or more column tiles (16 bins each), the column tiles are
+    // dealt round-robin to the XCDs, so an XCD streams only its own bins'
+    // bf16 planes; its tasks run block by block (largest band first), row
+    // tile by row tile, so one block's weight tables are reused while hot.
+    // With fewer column tiles, the blocks are dealt to the XCDs instead.
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
     const int slot = bid >> 3;
-    const int q = (slot / per_block) * 8 + xcd;
-    if (q >= p.n_blocks) return;
-    const int rem = slot % per_block;
-    const int row_tile = rem / p.n_col_tiles;
-    const int col_tile = rem % p.n_col_tiles;
+    int q, row_tile, col_tile;
+    if (p.n_col_tiles >= 8) {
+        const int cpx = (p.n_col_tiles + 7) / 8;          // column tiles per XCD
+        const int per_block = p.n_row_tiles * cpx;
+        q = slot / per_block;
+        const int rem = slot % per_block;
+        row_tile = rem / cpx;
+        col_tile = (rem % cpx) * 8 + xcd;
+        if (q >= p.n_blocks || col_tile >= p.n_col_tiles) return;
+    } else {
+        const int per_block = p.n_row_tiles * p.n_col_tiles;
+        q = (slot / per_block) * 8 + xcd;
+        if (q >= p.n_blocks) return;
+        const int rem = slot % per_block;
+        row_tile = rem / p.n_col_tiles;
+        col_tile = rem % p.n_col_tiles;
+    }
     const int nb = p.blk_list[q];
     const int tile = nb * p.n_row_tiles + row_tile;
 
@@ -120,97 +175,163 @@ __global__ __launch_bounds__(256) void exp_mfma_kernel(ExpMfmaParams p) {
     const int k_last = p.k0_first + m_last;
     const int k_nom = k_first + 63;                      // slot of the tile's nominal last row
     const int lblk = p.lblk[nb];
+    const int lg = p.lg[nb];
     const int kb_begin = k_first & ~31;
     const int kb_end = min((k_last + lblk + 31) & ~31, p.kp_data);
-    const int64_t off = p.blk_off[nb];
+    const unsigned short *gsh = p.gsh + p.gsh_off[nb];
 
     // lane geometry
     const int lrow = lane & 15;           // A row / C column within a 16 tile
     const int kg = lane >> 4;             // K group of 8
     const int my_row = 16 * wave + lrow;  // A operand row within the 64-row tile
     const int bin = col_tile * 16 + lrow; // B / C column -> bin
+    const bool bin_ok = bin < p.n_bins;
 
-    f32x4 acc[kNT][4];
+    const unsigned short *bh_base = p.xhi + (size_t)bin * p.kp + 8 * kg;
+    const unsigned short *bl_base = p.xlo + (size_t)bin * p.kp + 8 * kg;
+    const size_t comp_stride = (size_t)p.bins16 * p.kp;
+    auto load_b = [&](int kb, u32x4 *h, u32x4 *l) {
 #pragma unroll
-    for (int t = 0; t < kNT; ++t)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const unsigned short *xhi = p.xhi;
-    const unsigned short *xlo = p.xlo;
-    const size_t plane_col = (size_t)p.kp;   // elements per (component, bin) row
-
-    for (int ks = kb_begin; ks < kb_end; ks += kSK) {
-        // Stage weights for d in [d_lo, d_lo + kTW) with d_lo = ks - k_nom:
-        // every row of the tile (also rows past n_t0, whose outputs are
-        // discarded) reads inside the window.
-        const int d_lo = ks - k_nom;
-        __syncthreads();
-        for (int i = tid; i < kNT * kTW; i += 256) {
-            const int t = i / kTW;
-            const int dd = i - t * kTW;
-            const int d = d_lo + dd;
-            float g = 0.f;
-            if (d >= 0 && d < lblk) g = p.g32[off + (int64_t)d * kNT + t];
-            tab[t][dd] = split_pack(g);
+        for (int c = 0; c < 4; ++c) {
+            h[c] = *reinterpret_cast<const u32x4 *>(bh_base + c * comp_stride + kb);
+            l[c] = *reinterpret_cast<const u32x4 *>(bl_base + c * comp_stride + kb);
         }
-        __syncthreads();
-        const int ke = min(ks + kSK, kb_end);
-        for (int kb = ks; kb < ke; kb += 32) {
-            // B operands: 8 consecutive slots of one bin column, 4 components
-            bf16x8 bh[4], bl[4];
+    };
+
+    // A, B, C of the tile's 64 rows x 8 taus into LDS (rows past n_t0 read a
+    // valid row; rows of abc_cell hold whole blocks and start 16-byte aligned).
+    for (int i = wave; i < (kAbcChunks + 63) / 64; i += 4) {
+        int f = i * 64 + lane;
+        if (f >= kAbcChunks) f = 0;
+        const int row = f / (kBlk * 3 / 2);
+        const int ch = f - row * (kBlk * 3 / 2);
+        const int m = min(m_first + row, p.n_t0 - 1);
+        copy16_to_lds(p.abc_cell + ((size_t)m * p.abc_pitch + (size_t)nb * kBlk) * 3 + 2 * ch,
+                      reinterpret_cast<double *>(abcs) + (size_t)i * 64 * 2);
+    }
+
+    Red red = red_empty();
+
+#pragma unroll 1
+    for (int half = 0; half < kBlk / kNT; ++half) {
+        const int t0 = half * kNT;        // first tau of this pass within the block
+        f32x4 acc[kNT][4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const size_t o = ((size_t)(c * p.bins16 + bin)) * plane_col + kb + 8 * kg;
-                bh[c] = bitcast4<bf16x8>(*reinterpret_cast<const u32x4 *>(xhi + o));
-                bl[c] = bitcast4<bf16x8>(*reinterpret_cast<const u32x4 *>(xlo + o));
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        // Window of weights: copy s, position x holds g[d_lo + x + s] with
+        // d_lo = floor8(ks - k_nom), a straight aligned copy of the global
+        // shifted tables starting at entry d_lo + kPad.
+        int ks = kb_begin;
+        int d_lo = 0;
+        auto stage = [&](int ks_) {
+            d_lo = (ks_ - k_nom) & ~7;
+            __syncthreads();
+            const unsigned short *src0 = gsh + (size_t)t0 * 16 * lg + (d_lo + kPad);
+            for (int i = wave; i < kTabInstr; i += 4) {
+                int f = i * 64 + lane;
+                if (f >= kTabChunks) f = 0;     // padding chunks: any valid source
+                const int row = f / kRowChunks;
+                const int ch = f - row * kRowChunks;
+                copy16_to_lds(src0 + (size_t)row * lg + 8 * ch, &tab[i * 64 * 8]);
             }
-            // A operand index: d = kb + 8 kg + j - k0(row) relative to d_lo
-            const int base = (kb - ks) + (63 - my_row) + 8 * kg;
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        };
+        u32x4 bh[4], bl[4], nh[4], nl[4];
+        auto step = [&](int kb, u32x4 (&ch)[4], u32x4 (&cl)[4], u32x4 (&nh_)[4], u32x4 (&nl_)[4]) {
+            if (kb - ks == kSK) {
+                ks = kb;
+                stage(ks);
+            }
+            load_b(kb + 32 < kb_end ? kb + 32 : kb, nh_, nl_);
+            __builtin_amdgcn_sched_barrier(0);
+            // lane's weights g[kb + 8 kg - k0(row) .. + 8)
+            const int u = kb + 8 * kg - (k_first + my_row) - d_lo;
+            const int sh = u & 7;
+            const int q0 = u - sh;
+            const unsigned short *tl = tab + sh * kTW + q0;   // (t, part) rows stride 8 kTW
+            bf16x8 ah[kNT], al[kNT];
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
-                unsigned int w[8];
+                ah[t] = bitcast4<bf16x8>(*reinterpret_cast<const u32x4 *>(tl + (t * 2 + 0) * 8 * kTW));
+                al[t] = bitcast4<bf16x8>(*reinterpret_cast<const u32x4 *>(tl + (t * 2 + 1) * 8 * kTW));
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) w[j] = tab[t][base + j];
-                u32x4 hv, lv;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    hv[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], 0x05040100u);
-                    lv[j] = __builtin_amdgcn_perm(w[2 * j + 1], w[2 * j], 0x07060302u);
-                }
-                const bf16x8 ah = bitcast4<bf16x8>(hv);
-                const bf16x8 al = bitcast4<bf16x8>(lv);
+            for (int t = 0; t < kNT; ++t) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[c], acc[t][c], 0, 0, 0);
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[c], acc[t][c], 0, 0, 0);
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[c], acc[t][c], 0, 0, 0);
+                    const bf16x8 xh = bitcast4<bf16x8>(ch[c]);
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], xh, acc[t][c], 0, 0, 0);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const bf16x8 xl = bitcast4<bf16x8>(cl[c]);
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], xl, acc[t][c], 0, 0, 0);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const bf16x8 xh = bitcast4<bf16x8>(ch[c]);
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t], xh, acc[t][c], 0, 0, 0);
+                }
+            }
+        };
+        if (kb_begin < kb_end) {
+            stage(ks);
+            load_b(kb_begin, bh, bl);
+        }
+        for (int kb = kb_begin; kb < kb_end; kb += 64) {
+            step(kb, bh, bl, nh, nl);
+            if (kb + 32 < kb_end) step(kb + 32, nh, nl, bh, bl);
+        }
+
+        if (half == 0) {   // A/B/C copies have landed (also with no K steps)
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+        // Finalize this pass: lane holds rows 16w + 4 kg + r (r < 4) of bin
+        // `bin`; 2F in FP64, then max, first argmax and sum of exp(F - max).
+        double v2[kNT][4];
+        double fmx = -INFINITY;
+        long long imx = 0x7fffffffffffffffLL;
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+            const int n = nb * kBlk + t0 + t;
+            const bool n_ok = n < p.n_tau;
+            const double tau = (double)p.tau[n_ok ? n : p.n_tau - 1];
+            const double s = p.delta ? exp(-(double)p.delta / tau) : 1.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m_first + 16 * wave + 4 * kg + r;
+                v2[t][r] = -INFINITY;
+                if (!n_ok || m >= p.n_t0 || !bin_ok) continue;
+                const double *abc = abcs[m - m_first][t0 + t];
+                const double v = twoF_cell(abc[0], abc[1], abc[2], s * (double)acc[t][0][r],
+                                           s * (double)acc[t][1][r], s * (double)acc[t][2][r],
+                                           s * (double)acc[t][3][r]);
+                if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
+                v2[t][r] = v;
+                const long long idx = (long long)m * p.n_tau + n;
+                if (v > fmx || (v == fmx && idx < imx)) {
+                    fmx = v;
+                    imx = idx;
                 }
             }
         }
-    }
-
-    // Finalize: lane holds rows 16w + 4 kg + r (r < 4) of bin `bin`.
-    Red red = red_empty();
-    const bool bin_ok = bin < p.n_bins;
+        if (fmx != -INFINITY) {
+            double sum = 0.0;
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) {
-        const int n = nb * kNT + t;
-        if (n >= p.n_tau) continue;
-        const double tau = (double)p.tau[n];
-        const double s = p.delta ? exp(-(double)p.delta / tau) : 1.0;
+            for (int t = 0; t < kNT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int m = m_first + 16 * wave + 4 * kg + r;
-            if (m >= p.n_t0 || !bin_ok) continue;
-            const double *abc = p.abc_cell + ((size_t)m * p.n_tau + n) * 3;
-            const double v = twoF_cell(abc[0], abc[1], abc[2], s * (double)acc[t][0][r],
-                                       s * (double)acc[t][1][r], s * (double)acc[t][2][r],
-                                       s * (double)acc[t][3][r]);
-            if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
-            red = red_combine(red, Red{0.5 * v, 1.0, (long long)m * p.n_tau + n});
+                for (int r = 0; r < 4; ++r)
+                    if (v2[t][r] != -INFINITY) sum += (double)__expf((float)(0.5 * (v2[t][r] - fmx)));
+            red = red_combine(red, Red{0.5 * fmx, sum, imx});
         }
     }
+
     // lanes sharing a bin: xor 16, 32; then the four waves in order
     red = red_combine(red, red_shfl_xor(red, 16));
     red = red_combine(red, red_shfl_xor(red, 32));
@@ -251,9 +372,24 @@ __global__ __launch_bounds__(256) void build_planes_kernel(const float *x32, int
 
 hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s) {
     if (p.n_blocks <= 0) return hipSuccess;
-    const int groups = (p.n_blocks + 7) / 8;
-    const unsigned grid = (unsigned)(8 * groups * p.n_row_tiles * p.n_col_tiles);
+    unsigned grid;
+    if (p.n_col_tiles >= 8) {
+        const int cpx = (p.n_col_tiles + 7) / 8;
+        grid = (unsigned)(8 * p.n_blocks * p.n_row_tiles * cpx);
+    } else {
+        const int groups = (p.n_blocks + 7) / 8;
+        grid = (unsigned)(8 * groups * p.n_row_tiles * p.n_col_tiles);
+    }
     hipLaunchKernelGGL(exp_mfma_kernel, dim3(grid), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_tables(const ShiftTableParams &p, int64_t max_entries, hipStream_t s) {
+    if (p.n_blocks <= 0) return hipSuccess;
+    int64_t gx = (max_entries + 255) / 256;
+    if (gx < 1) gx = 1;
+    if (gx > 1024) gx = 1024;
+    hipLaunchKernelGGL(shift_tables_kernel, dim3((unsigned)gx, (unsigned)p.n_blocks), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

@@ -223,6 +223,7 @@ WindowOwned copy_window(const tfstat_window *w) {
 enum { NK = TFSTAT_K_COUNT };
 
 constexpr int kMfmaTaus = 8;       // taus per matrix-core work item
+inline int32_t abc_pitch(int32_t n_tau) { return (n_tau + kMfmaTaus - 1) / kMfmaTaus * kMfmaTaus; }
 constexpr int kMfmaMinBand = 64;   // shorter bands stay on the VALU path
 
 // ---------------------------------------------------------------------------
@@ -242,6 +243,9 @@ struct Job {
     int64_t wtot = 0, max_blk = 0;
     bool use_mfma = false;     // BF16X3 on matrix cores for long bands
     int n_valu = 0, n_mfma = 0;  // block lists: order[0..n_valu) VALU, then MFMA
+    std::vector<int32_t> lg;     // shifted bf16 table length per block (MFMA blocks)
+    std::vector<int64_t> gsh_off;
+    int64_t gsh_total = 0, gsh_max = 0;
 
     // memory
     size_t ws_bytes = 0;
@@ -251,7 +255,7 @@ struct Job {
     size_t off_rows = 0, off_tau = 0, off_lcol = 0, off_lblk = 0, off_boff = 0, off_order = 0,
            tables_bytes = 0;
     size_t off_g32 = 0, off_gsq = 0, off_g64 = 0, off_pabc = 0, off_px = 0, off_part = 0,
-           off_res = 0, off_abc = 0;
+           off_res = 0, off_abc = 0, off_lg = 0, off_gshoff = 0, off_gsh = 0;
 
     // timing
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timed;
@@ -328,14 +332,31 @@ void plan_job(Job &j) {
         j.n_valu = j.NB;
         j.n_mfma = 0;
         if (j.use_mfma) {
-            // short bands stay on the FP32 VALU path: little work, and the
-            // worst-conditioned windows
+            // a block with any short band stays on the FP32 VALU path: short
+            // windows carry little work and the worst conditioning, which
+            // would amplify the ~2^-16 error of the split operands
             std::vector<int32_t> lv, lm;
-            for (int32_t b : j.order) (j.lblk[b] >= kMfmaMinBand ? lm : lv).push_back(b);
+            for (int32_t b : j.order) {
+                int32_t shortest = INT32_MAX;
+                for (int r = 0; r < j.R && b * j.R + r < n_tau; ++r)
+                    shortest = std::min(shortest, j.lcol[b * j.R + r]);
+                (shortest >= kMfmaMinBand ? lm : lv).push_back(b);
+            }
             j.n_valu = (int)lv.size();
             j.n_mfma = (int)lm.size();
             j.order = lv;
             j.order.insert(j.order.end(), lm.begin(), lm.end());
+            j.lg.assign(j.NB, 0);
+            j.gsh_off.assign(j.NB, 0);
+            j.gsh_total = 0;
+            j.gsh_max = 0;
+            for (int32_t b : lm) {
+                j.lg[b] = tfs::shift_table_len(j.lblk[b]);
+                j.gsh_off[b] = j.gsh_total;
+                const int64_t n = (int64_t)kMfmaTaus * 16 * j.lg[b];
+                j.gsh_total += n;
+                j.gsh_max = std::max(j.gsh_max, n);
+            }
         }
     } else {
         j.n_tiles_n = (n_tau + 63) / 64;
@@ -356,13 +377,21 @@ void plan_job(Job &j) {
         j.off_lblk = take(sizeof(int32_t) * j.NB);
         j.off_boff = take(sizeof(int64_t) * j.NB);
         j.off_order = take(sizeof(int32_t) * j.NB);
+        if (j.use_mfma) {
+            j.off_lg = take(sizeof(int32_t) * j.NB);
+            j.off_gshoff = take(sizeof(int64_t) * j.NB);
+        }
     }
     j.tables_bytes = o;
     if (is_exp) {
         j.off_g32 = take(sizeof(float) * std::max<int64_t>(j.wtot, 1));
         j.off_gsq = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
         if (j.prec == TFSTAT_PREC_FP64) j.off_g64 = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
-        if (j.use_mfma && j.n_mfma > 0) j.off_abc = take(sizeof(double) * 3 * (size_t)n_t0 * n_tau);
+        if (j.use_mfma && j.n_mfma > 0) {
+            // rows padded to whole blocks: the matrix-core kernel copies them
+            j.off_abc = take(sizeof(double) * 3 * (size_t)n_t0 * abc_pitch(n_tau));
+            j.off_gsh = take(sizeof(unsigned short) * (size_t)j.gsh_total);
+        }
     } else {
         j.off_pabc = take(sizeof(double) * 8 * ((size_t)at.K + 1));
         j.off_px = take(sizeof(double) * 8 * (size_t)at.n_bins * ((size_t)at.K + 1));
@@ -503,6 +532,10 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         std::memcpy(h + j.off_lblk, j.lblk.data(), sizeof(int32_t) * j.NB);
         std::memcpy(h + j.off_boff, j.blk_off.data(), sizeof(int64_t) * j.NB);
         std::memcpy(h + j.off_order, j.order.data(), sizeof(int32_t) * j.NB);
+        if (j.use_mfma) {
+            std::memcpy(h + j.off_lg, j.lg.data(), sizeof(int32_t) * j.NB);
+            std::memcpy(h + j.off_gshoff, j.gsh_off.data(), sizeof(int64_t) * j.NB);
+        }
     }
     hip_check(hipMemcpyAsync(j.ws, h, j.tables_bytes, hipMemcpyHostToDevice, s), "upload tables");
 
@@ -561,6 +594,7 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
             pa.blk_list = p.blk_list + j.n_valu;
             pa.twoF = nullptr;
             pa.abc_out = ws_ptr<double>(j, j.off_abc);
+            pa.abc_pitch = abc_pitch(n_tau);
             record_kernel(ctx, j, TFSTAT_K_ABC, s, true);
             hip_check(tfs::launch_exp_abc(pa, s), "exp abc kernel");
             record_kernel(ctx, j, TFSTAT_K_ABC, s, false);
@@ -581,10 +615,25 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
             q.lblk = wp.lblk;
             q.blk_off = wp.blk_off;
             q.blk_list = pa.blk_list;
-            q.g32 = wp.g32;
+            q.lg = ws_ptr<int32_t>(j, j.off_lg);
+            q.gsh_off = ws_ptr<int64_t>(j, j.off_gshoff);
+            q.gsh = ws_ptr<unsigned short>(j, j.off_gsh);
+            tfs::ShiftTableParams sp{};
+            sp.n_blocks = j.n_mfma;
+            sp.blk_list = pa.blk_list;
+            sp.lblk = wp.lblk;
+            sp.lg = q.lg;
+            sp.blk_off = wp.blk_off;
+            sp.gsh_off = q.gsh_off;
+            sp.g32 = wp.g32;
+            sp.gsh = ws_ptr<unsigned short>(j, j.off_gsh);
+            record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, true);
+            hip_check(tfs::launch_shift_tables(sp, j.gsh_max, s), "shift tables kernel");
+            record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, false);
             q.xhi = at.xhi;
             q.xlo = at.xlo;
             q.abc_cell = pa.abc_out;
+            q.abc_pitch = pa.abc_pitch;
             q.twoF = j.twoF;
             q.part = part;
             record_kernel(ctx, j, TFSTAT_K_MFMA, s, true);

@@ -65,7 +65,9 @@ struct ExpValuParams {
     const double *gsq;        //   (squared weights, FP64)
     float *twoF;              // optional map [n_bins][n_t0][n_tau]
     Partial *part;            // [n_bins][n_tiles]
-    double *abc_out;          // A/B/C-only mode: [n_t0][n_tau][3] (scaled, exact band)
+    double *abc_out;          // A/B/C-only mode: [n_t0][abc_pitch][3] (scaled, exact band)
+    int32_t abc_pitch;        // cells per row of abc_out (n_tau rounded up to 8)
+    int32_t pad1;
 };
 
 // Exponential-window F_a, F_b on bf16 matrix cores for grids whose t0 rows
@@ -85,11 +87,27 @@ struct ExpMfmaParams {
     const int32_t *lblk;      // [blocks] band length of the block's table
     const int64_t *blk_off;   // [blocks] table offsets, [blk][d][8] layout
     const int32_t *blk_list;  // [n_blocks]
-    const float *g32;         // FP32 weights g_n[d]
+    const int32_t *lg;        // [blocks] length of each shifted table
+    const int64_t *gsh_off;   // [blocks] element offset of the block's shifted tables
+    const unsigned short *gsh;  // shifted bf16 tables [blk][t 8][part 2][shift 8][lg]
     const unsigned short *xhi, *xlo;  // [4][bins16][kp] bf16 planes
-    const double *abc_cell;   // [n_t0][n_tau][3]
+    const double *abc_cell;   // [n_t0][abc_pitch][3]
+    int32_t abc_pitch;        // n_tau rounded up to 8 (rows start 16-byte aligned)
+    int32_t pad2;
     float *twoF;
     Partial *part;
+};
+
+struct ShiftTableParams {
+    int32_t n_blocks;
+    int32_t pad0;
+    const int32_t *blk_list;  // [n_blocks]
+    const int32_t *lblk;
+    const int32_t *lg;
+    const int64_t *blk_off;   // offsets into g32 ([blk][d][8])
+    const int64_t *gsh_off;
+    const float *g32;
+    unsigned short *gsh;
 };
 
 struct WeightParams {
@@ -150,6 +168,9 @@ hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG,
 // A/B/C only (FP64), R = 8 blocks, into p.abc_out.
 hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s);
 hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s);
+hipError_t launch_shift_tables(const ShiftTableParams &p, int64_t max_entries, hipStream_t s);
+// Entries per shifted table (one tau, part and shift) for a band of lblk.
+inline int32_t shift_table_len(int32_t lblk) { return (128 + lblk + 256 + 72 + 8 + 7) / 8 * 8; }
 hipError_t launch_build_planes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16,
                                int32_t kp, unsigned short *xhi, unsigned short *xlo,
                                hipStream_t s);
