@@ -207,14 +207,14 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="exp1bin", choices=["exp1bin", "exp256", "rect", "rect256"])
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3", "recur64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-map", action="store_true",
                     help="do not write the 2F map (per-bin results only)")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="length of the served request stream (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-prec", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--serve-prec", default="fp32", choices=["fp32", "fp64", "bf16x3", "recur64"])
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the map, time a plain device-to-device copy of this many "
                          "bytes (calibrates HBM byte counters)")
@@ -267,10 +267,21 @@ def main(argv=None):
     value = present / (ms * 1e-3)
 
     mfma = win.kind == "exp" and args.prec == "bf16x3" and prof["mfma"][0] > 0
-    dom = "mfma" if mfma else ("exp" if win.kind == "exp" else "rect")
+    recur = win.kind == "exp" and args.prec == "recur64" and prof["recur"][0] > 0
+    dom = "mfma" if mfma else ("recur" if recur else ("exp" if win.kind == "exp" else "rect"))
     n_launch, k_ms = prof[dom]
     avg_ms = k_ms / max(n_launch, 1)
-    if mfma:
+    if recur:
+        # FP64 flops of the recurrence: the boundary window per tau (w^2 and
+        # one FMA per antenna and data channel per slot), two passes per row
+        # of (scale + head FMA + tail FMA) per channel, and the finalize
+        # (about 30 flops per cell and bin)
+        ch = 3 + 4 * atoms.n_bins
+        band = np.minimum(-(-3 * win.tau // atoms.t_sft), atoms.n_slots)
+        flops = float((band * (1 + 2 * ch)).sum()) + win.n_tau * win.n_t0 * (2 * 5 * ch + 30 * atoms.n_bins)
+        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_ALU_TFLOPS,
+                "unit": "TFLOP/s"}
+    elif mfma:
         # 4 complex-by-real MACs = 8 flops per cell*SFT*bin, issued as three
         # bf16 products (hi*hi + hi*lo + lo*hi): 24 bf16 flops, counted over
         # the tau blocks the matrix-core kernel runs
@@ -292,7 +303,8 @@ def main(argv=None):
         roof = {"bound": "hbm", "achieved": byts / (avg_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic_from_profile(args.workload, "exp_valu" if dom == "exp" else "rect")
+    roof["traffic"] = traffic_from_profile(args.workload, {"exp": "exp_valu", "rect": "rect",
+                                                           "mfma": "exp_mfma", "recur": "exp_recur"}[dom])
     roof["kernel"] = dom
     roof["kernel_avg_ms"] = avg_ms
     out = {
@@ -306,7 +318,8 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16x3": "bf16x3(f32 acc)+f64"}[args.prec],
+        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16x3": "bf16x3(f32 acc)+f64",
+                  "recur64": "f64"}[args.prec],
         "data": "synthetic",
         "config": {"workload": desc, "n_slots": atoms.n_slots, "n_sft": atoms.n_sft,
                    "n_t0": win.n_t0, "n_tau": win.n_tau, "n_bins": atoms.n_bins,

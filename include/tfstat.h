@@ -79,12 +79,19 @@ typedef enum {
  *            (dt0 = t_sft); groups of 8 taus holding a band shorter than
  *            64 slots, and every other grid, run the FP32 path.  The first BF16X3 call on an atoms set
  *            builds its bf16 planes (16 bytes per slot and bin of arena).
+ *   RECUR64: exponential windows on a regular t0 grid whose step is a whole
+ *            number of SFT slots (at most 64): every sum in FP64 by the exact
+ *            recurrence of the window sums from one t0 to the next, O(1)
+ *            per cell and channel instead of O(window length); windows
+ *            holding fewer than two SFTs are summed directly.  Other grids
+ *            run the FP64 direct sums.
  * Rectangular windows use FP64 prefix sums in every mode.
  */
 typedef enum {
     TFSTAT_PREC_FP64 = 0,
     TFSTAT_PREC_FP32 = 1,
-    TFSTAT_PREC_BF16X3 = 2
+    TFSTAT_PREC_BF16X3 = 2,
+    TFSTAT_PREC_RECUR64 = 3
 } tfstat_precision;
 
 /*
@@ -223,7 +230,8 @@ typedef enum {
     TFSTAT_K_MERGE = 5,       /* per-bin reduction merge */
     TFSTAT_K_MFMA = 6,        /* exponential F_a, F_b on matrix cores */
     TFSTAT_K_ABC = 7,         /* exponential A, B, C (FP64) */
-    TFSTAT_K_COUNT = 8
+    TFSTAT_K_RECUR = 8,       /* exponential sums by the t0 recurrence */
+    TFSTAT_K_COUNT = 9
 } tfstat_kernel_kind;
 
 int tfstat_profile_enable(tfstat_ctx *ctx, int on);

@@ -19,7 +19,8 @@ import numpy as np
 from . import _abi
 from ._abi import TfstatError  # noqa: F401
 
-PRECISIONS = {"fp64": _abi.PREC_FP64, "fp32": _abi.PREC_FP32, "bf16x3": _abi.PREC_BF16X3}
+PRECISIONS = {"fp64": _abi.PREC_FP64, "fp32": _abi.PREC_FP32, "bf16x3": _abi.PREC_BF16X3,
+              "recur64": _abi.PREC_RECUR64}
 WINDOWS = {"rect": _abi.WIN_RECT, "exp": _abi.WIN_EXP}
 
 

@@ -19,10 +19,10 @@ STATUS_NAMES = {
 }
 
 WIN_RECT, WIN_EXP = 0, 1
-PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_RECUR64 = 0, 1, 2, 3
 
-K_UPLOAD, K_WEIGHTS, K_EXP, K_SCAN, K_RECT, K_MERGE, K_MFMA, K_ABC = range(8)
-KERNEL_NAMES = ["upload", "weights", "exp", "scan", "rect", "merge", "mfma", "abc"]
+K_UPLOAD, K_WEIGHTS, K_EXP, K_SCAN, K_RECT, K_MERGE, K_MFMA, K_ABC, K_RECUR = range(9)
+KERNEL_NAMES = ["upload", "weights", "exp", "scan", "rect", "merge", "mfma", "abc", "recur"]
 
 
 class Window(ctypes.Structure):

@@ -34,13 +34,18 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlk = 8;       // taus per block (shared with the VALU tiling)
 constexpr int kNT = 4;        // taus per matrix-core pass (two passes per block)
-constexpr int kSK = 256;      // band slots per staged weight window
-constexpr int kTW = kSK + 72; // staged window width (multiple of 8)
-constexpr int kPad = 128;     // zero entries in front of every shifted table
+constexpr int kSK = kMfmaSK;  // band slots per staged weight window
+static_assert(kSK % 64 == 0, "windows hold an even number of 32-slot K steps");
+constexpr int kTW = kMfmaTW;  // staged window width (multiple of 8; sets the LDS pitch)
+constexpr int kPad = kMfmaPad;  // zero entries in front of every shifted table
+constexpr int kShifts = kMfmaShifts;  // shifted copies per (tau, part)
 constexpr int kRowChunks = kTW / 8;                 // 16-byte chunks per table row
-constexpr int kTabChunks = kNT * 16 * kRowChunks;   // chunks per staged window
+constexpr int kTabChunks = kNT * 2 * kShifts * kRowChunks;   // chunks per staged window
 constexpr int kTabInstr = (kTabChunks + 63) / 64;   // 64-lane copies per window
 constexpr int kAbcChunks = 64 * kBlk * 3 / 2;       // A/B/C of the tile, 16-byte chunks
+// s_waitcnt operand (gfx9 encoding) that waits for LDS / scalar memory only:
+// vmcnt 63, expcnt 7, lgkmcnt 0
+constexpr int kWaitLgkm0 = 0xC07F;
 
 struct Red {
     double f;
@@ -99,22 +104,22 @@ __device__ inline T bitcast4(u32x4 v) {
 }
 
 // Shifted bf16 weight tables, built once per map: for block nb, tau t,
-// part (0 = hi, 1 = lo) and shift s, entry x holds part(g_t[x - kPad + s])
-// (zero outside 0 <= d < lblk), so that 8 weights starting anywhere are one
-// aligned 16-byte read from the copy matching their start modulo 8.
+// part (0 = hi, 1 = lo) and shift s < 4, entry x holds part(g_t[x - kPad + s])
+// (zero outside 0 <= d < lblk), so that 8 weights starting anywhere are two
+// aligned 8-byte reads from the copy matching their start modulo 4.
 __global__ __launch_bounds__(256) void shift_tables_kernel(ShiftTableParams p) {
     const int nb = p.blk_list[blockIdx.y];
     const int lblk = p.lblk[nb];
     const int lg = p.lg[nb];
     const int64_t src = p.blk_off[nb];
     unsigned short *dst = p.gsh + p.gsh_off[nb];
-    const int64_t total = (int64_t)kBlk * 2 * 8 * lg;
+    const int64_t total = (int64_t)kBlk * 2 * kShifts * lg;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         const int x = (int)(i % lg);
         const int64_t r = i / lg;
-        const int sh = (int)(r % 8);
-        const int part = (int)((r / 8) % 2);
-        const int t = (int)(r / 16);
+        const int sh = (int)(r % kShifts);
+        const int part = (int)((r / kShifts) % 2);
+        const int t = (int)(r / (2 * kShifts));
         const int d = x - kPad + sh;
         float g = 0.f;
         if (d >= 0 && d < lblk) g = p.g32[src + (int64_t)d * kBlk + t];
@@ -130,9 +135,19 @@ __device__ inline void copy16_to_lds(const void *src, void *dst_wave_base) {
                                      0);
 }
 
-__global__ __launch_bounds__(256, 2) void exp_mfma_kernel(ExpMfmaParams p) {
-    // weight window: flat 16-byte chunks, row (t, part, shift) by row
-    __shared__ __attribute__((aligned(16))) unsigned short tab[kTabInstr * 64 * 8];
+#ifndef TFS_MFMA_WAVES
+#define TFS_MFMA_WAVES 2       // waves per SIMD the register budget targets
+#endif
+#ifndef TFS_MFMA_APREFETCH
+#define TFS_MFMA_APREFETCH 1   // 1: weights read from LDS one K step ahead
+#endif
+
+__global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaParams p) {
+    // two weight windows: flat 16-byte chunks, row (t, part, shift) by row
+    // two weight-window buffers as two objects, so that the compiler can see
+    // that reads of one do not wait for the direct-to-LDS copies into the other
+    __shared__ __attribute__((aligned(16))) unsigned short tab0[kTabInstr * 64 * 8];
+    __shared__ __attribute__((aligned(16))) unsigned short tab1[kTabInstr * 64 * 8];
     __shared__ __attribute__((aligned(16))) double abcs[64][kBlk][3];
     __shared__ Red wred[4][16];
 
@@ -177,7 +192,10 @@ __global__ __launch_bounds__(256, 2) void exp_mfma_kernel(ExpMfmaParams p) {
     const int lblk = p.lblk[nb];
     const int lg = p.lg[nb];
     const int kb_begin = k_first & ~31;
-    const int kb_end = min((k_last + lblk + 31) & ~31, p.kp_data);
+    // K steps of 32 slots from kb_begin; their number is rounded up to even
+    // (columns kp_data .. kp of the B planes are zero)
+    const int kb_data_end = min((k_last + lblk + 31) & ~31, p.kp_data);
+    const int kb_end = kb_data_end > kb_begin ? kb_begin + ((kb_data_end - kb_begin + 63) & ~63) : kb_begin;
     const unsigned short *gsh = p.gsh + p.gsh_off[nb];
 
     // lane geometry
@@ -221,71 +239,127 @@ __global__ __launch_bounds__(256, 2) void exp_mfma_kernel(ExpMfmaParams p) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-        // Window of weights: copy s, position x holds g[d_lo + x + s] with
-        // d_lo = floor8(ks - k_nom), a straight aligned copy of the global
-        // shifted tables starting at entry d_lo + kPad.
-        int ks = kb_begin;
-        int d_lo = 0;
-        auto stage = [&](int ks_) {
-            d_lo = (ks_ - k_nom) & ~7;
-            __syncthreads();
-            const unsigned short *src0 = gsh + (size_t)t0 * 16 * lg + (d_lo + kPad);
+        // Windows of weights: in window w, copy s, position x holds
+        // g[d_lo(w) + x + s] with d_lo(w) = floor8(kb_begin + w kSK - k_nom),
+        // a straight aligned copy of the global shifted tables from entry
+        // d_lo(w) + kPad.  Window w + 1 is copied into the other buffer while
+        // window w is in use.
+        auto issue = [&](int w, unsigned short *dst) {
+            const int dl = (kb_begin + w * kSK - k_nom) & ~7;
+            const unsigned short *src0 = gsh + (size_t)t0 * 2 * kShifts * lg + (dl + kPad);
             for (int i = wave; i < kTabInstr; i += 4) {
                 int f = i * 64 + lane;
                 if (f >= kTabChunks) f = 0;     // padding chunks: any valid source
                 const int row = f / kRowChunks;
                 const int ch = f - row * kRowChunks;
-                copy16_to_lds(src0 + (size_t)row * lg + 8 * ch, &tab[i * 64 * 8]);
+                copy16_to_lds(src0 + (size_t)row * lg + 8 * ch, dst + i * 64 * 8);
             }
+        };
+        const int n_win = (kb_end - kb_begin + kSK - 1) / kSK;
+        int ks = kb_begin;
+        int d_lo = (kb_begin - k_nom) & ~7;
+        auto enter_window = [&](int w, unsigned short *nxt) {
+            // window w has landed and every wave is done with window w - 1
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
+            ks = kb_begin + w * kSK;
+            d_lo = (ks - k_nom) & ~7;
+            if (w + 1 < n_win) issue(w + 1, nxt);
         };
-        u32x4 bh[4], bl[4], nh[4], nl[4];
-        auto step = [&](int kb, u32x4 (&ch)[4], u32x4 (&cl)[4], u32x4 (&nh_)[4], u32x4 (&nl_)[4]) {
-            if (kb - ks == kSK) {
-                ks = kb;
-                stage(ks);
-            }
-            load_b(kb + 32 < kb_end ? kb + 32 : kb, nh_, nl_);
-            __builtin_amdgcn_sched_barrier(0);
-            // lane's weights g[kb + 8 kg - k0(row) .. + 8)
+        // Lane's weights for the K step at kb: g[kb + 8 kg - k0(row) .. + 8)
+        // from copy u % kShifts of the staged window.
+        auto load_a = [&](const unsigned short *cur, int kb, bf16x8 *ah, bf16x8 *al) {
             const int u = kb + 8 * kg - (k_first + my_row) - d_lo;
-            const int sh = u & 7;
+            const int sh = u & (kShifts - 1);
             const int q0 = u - sh;
-            const unsigned short *tl = tab + sh * kTW + q0;   // (t, part) rows stride 8 kTW
-            bf16x8 ah[kNT], al[kNT];
+            const unsigned short *tl = cur + sh * kTW + q0;   // (t, part) rows stride kShifts kTW
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
-                ah[t] = bitcast4<bf16x8>(*reinterpret_cast<const u32x4 *>(tl + (t * 2 + 0) * 8 * kTW));
-                al[t] = bitcast4<bf16x8>(*reinterpret_cast<const u32x4 *>(tl + (t * 2 + 1) * 8 * kTW));
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int t = 0; t < kNT; ++t) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const bf16x8 xh = bitcast4<bf16x8>(ch[c]);
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], xh, acc[t][c], 0, 0, 0);
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const bf16x8 xl = bitcast4<bf16x8>(cl[c]);
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], xl, acc[t][c], 0, 0, 0);
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const bf16x8 xh = bitcast4<bf16x8>(ch[c]);
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t], xh, acc[t][c], 0, 0, 0);
+                const unsigned short *th = tl + (t * 2 + 0) * kShifts * kTW;
+                const unsigned short *tw = tl + (t * 2 + 1) * kShifts * kTW;
+                if constexpr (kShifts == 8) {
+                    ah[t] = bitcast4<bf16x8>(*reinterpret_cast<const u32x4 *>(th));
+                    al[t] = bitcast4<bf16x8>(*reinterpret_cast<const u32x4 *>(tw));
+                } else {
+                    const uint64_t *ph = reinterpret_cast<const uint64_t *>(th);
+                    const uint64_t *pl = reinterpret_cast<const uint64_t *>(tw);
+                    u32x4 h, l;
+                    const uint64_t h0 = ph[0], h1 = ph[1], l0 = pl[0], l1 = pl[1];
+                    h[0] = (unsigned)h0; h[1] = (unsigned)(h0 >> 32); h[2] = (unsigned)h1; h[3] = (unsigned)(h1 >> 32);
+                    l[0] = (unsigned)l0; l[1] = (unsigned)(l0 >> 32); l[2] = (unsigned)l1; l[3] = (unsigned)(l1 >> 32);
+                    ah[t] = bitcast4<bf16x8>(h);
+                    al[t] = bitcast4<bf16x8>(l);
                 }
             }
         };
+        // 48 products of one K step.  The three products run one after the
+        // other over all 16 accumulators, so dependent matrix-core ops on one
+        // accumulator are 16 apart.
+        auto mfma_step = [&](const bf16x8 *ah, const bf16x8 *al, const u32x4 *ch, const u32x4 *cl) {
+#pragma unroll
+            for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bitcast4<bf16x8>(ch[c]), acc[t][c], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bitcast4<bf16x8>(cl[c]), acc[t][c], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t], bitcast4<bf16x8>(ch[c]), acc[t][c], 0, 0, 0);
+        };
+        // Software pipeline: while the products of step kb run, the B
+        // operands of step kb + 32 (global) and the weights of step kb + 32
+        // (LDS, same window) are already on their way.  Every window holds an
+        // even number of K steps (kSK is a multiple of 64 and the pass end is
+        // rounded up to one, over zero B columns), so the loop body is two
+        // steps with no branch; a prefetch past the window or the pass end
+        // re-reads an in-range step and is discarded.
+        u32x4 bh[4], bl[4], nh[4], nl[4];
+        bf16x8 ah[kNT], al[kNT], mh[kNT], ml[kNT];
         if (kb_begin < kb_end) {
-            stage(ks);
+            __syncthreads();   // the previous pass is done with both buffers
+            issue(0, tab0);
             load_b(kb_begin, bh, bl);
         }
-        for (int kb = kb_begin; kb < kb_end; kb += 64) {
-            step(kb, bh, bl, nh, nl);
-            if (kb + 32 < kb_end) step(kb + 32, nh, nl, bh, bl);
+        // Two K steps from kb (kb + 32 < kw_end always holds).
+        auto pair = [&](const unsigned short *cur, int kb, int ka_last) {
+            load_b(kb + 32, nh, nl);
+            load_a(cur, kb + 32, mh, ml);
+            if constexpr (!TFS_MFMA_APREFETCH) load_a(cur, kb, ah, al);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_step(ah, al, bh, bl);
+            __builtin_amdgcn_sched_barrier(0);
+            load_b(min(kb + 64, kb_end - 32), bh, bl);
+            if constexpr (TFS_MFMA_APREFETCH) load_a(cur, min(kb + 64, ka_last), ah, al);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_step(mh, ml, nh, nl);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto run_window = [&](int w, const unsigned short *cur, unsigned short *nxt) {
+            enter_window(w, nxt);
+            const int kw_end = min(ks + kSK, kb_end);
+            const int ka_last = ks + kSK - 32;      // last K step this window's weights cover
+            if constexpr (TFS_MFMA_APREFETCH) load_a(cur, ks, ah, al);
+            // Only the weights just read are waited for here; without this the
+            // loop's first products would also wait for every B prefetch.
+            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+            // The first pair is peeled off: while the next window's direct
+            // copies are in flight, B loads can only be waited for all at once,
+            // and the peeled pair takes that wait once per window instead of
+            // once per loop trip.
+            pair(cur, ks, ka_last);
+#pragma unroll 1
+            for (int kb = ks + 64; kb < kw_end; kb += 64) pair(cur, kb, ka_last);
+        };
+#pragma unroll 1
+        for (int w = 0; w < n_win; w += 2) {
+            run_window(w, tab0, tab1);
+            if (w + 1 < n_win) run_window(w + 1, tab1, tab0);
         }
 
         if (half == 0) {   // A/B/C copies have landed (also with no K steps)
@@ -372,6 +446,7 @@ __global__ __launch_bounds__(256) void build_planes_kernel(const float *x32, int
 
 hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s) {
     if (p.n_blocks <= 0) return hipSuccess;
+    if (p.kp < p.kp_data + 32) return hipErrorInvalidValue;   // even-step padding reads up to kp_data + 32
     unsigned grid;
     if (p.n_col_tiles >= 8) {
         const int cpx = (p.n_col_tiles + 7) / 8;

@@ -166,6 +166,7 @@ struct AtomsSet {
     double *abc = nullptr;
     double *x64 = nullptr;
     float *x32 = nullptr;
+    int32_t *npref = nullptr;   // [K+1] present SFTs in slots [0, k)
     // bf16 hi / lo planes for the matrix-core path, built on first use
     void *planes = nullptr;
     unsigned short *xhi = nullptr, *xlo = nullptr;
@@ -241,6 +242,8 @@ struct Job {
     std::vector<int64_t> blk_off;
     int R = 0, BG = 0, NB = 0, n_row_tiles = 0, n_tiles = 0, n_tiles_n = 0;
     int64_t wtot = 0, max_blk = 0;
+    bool use_recur = false;    // RECUR64: exponential sums by the t0 recurrence
+    int32_t recur_stride = 0, recur_k0 = 0, recur_bg = 1;
     bool use_mfma = false;     // BF16X3 on matrix cores for long bands
     int n_valu = 0, n_mfma = 0;  // block lists: order[0..n_valu) VALU, then MFMA
     std::vector<int32_t> lg;     // shifted bf16 table length per block (MFMA blocks)
@@ -295,6 +298,24 @@ void plan_job(Job &j) {
         j.lcol[n] = (int32_t)std::min(shortest, cap);
     }
     j.n_row_tiles = (n_t0 + 63) / 64;
+    // Recurrence path: RECUR64 on a regular t0 grid whose step is a whole
+    // number of slots (then every row has the same delta).
+    j.use_recur = false;
+    if (is_exp && j.prec == TFSTAT_PREC_RECUR64) {
+        bool ok = true;
+        int64_t step = n_t0 > 1 ? j.win.t0[1] - j.win.t0[0] : T;
+        for (int m = 1; m < n_t0 && ok; ++m) ok = j.win.t0[m] - j.win.t0[m - 1] == step;
+        ok = ok && step % T == 0 && step / T <= 64;
+        const int64_t k0 = ceil_div(j.win.t0[0] - at.T0, T);
+        const int64_t klast = k0 + (int64_t)(n_t0 - 1) * (step / T);
+        ok = ok && k0 > -((int64_t)1 << 30) && klast < ((int64_t)1 << 30);
+        if (ok) {
+            j.use_recur = true;
+            j.recur_stride = (int32_t)(step / T);
+            j.recur_k0 = (int32_t)k0;
+            j.recur_bg = at.n_bins >= 4 ? 4 : (at.n_bins >= 2 ? 2 : 1);
+        }
+    }
     // Matrix-core path: BF16X3, rows on consecutive slots with one delta.
     j.use_mfma = false;
     if (is_exp && j.prec == TFSTAT_PREC_BF16X3 && j.rows[0].k0 >= 0) {
@@ -303,8 +324,11 @@ void plan_job(Job &j) {
             ok = j.rows[m].k0 == j.rows[0].k0 + m && j.rows[m].delta == j.rows[0].delta;
         j.use_mfma = ok;
     }
-    if (is_exp) {
-        const int prec = (j.prec == TFSTAT_PREC_FP64) ? 0 : 1;
+    if (is_exp && j.use_recur) {
+        j.NB = 0;
+        j.n_tiles = n_tau;
+    } else if (is_exp) {
+        const int prec = (j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64) ? 0 : 1;
         tfs::exp_valu_config(prec, at.n_bins, &j.R, &j.BG);
         if (j.use_mfma) {
             j.R = kMfmaTaus;
@@ -353,7 +377,7 @@ void plan_job(Job &j) {
             for (int32_t b : lm) {
                 j.lg[b] = tfs::shift_table_len(j.lblk[b]);
                 j.gsh_off[b] = j.gsh_total;
-                const int64_t n = (int64_t)kMfmaTaus * 16 * j.lg[b];
+                const int64_t n = (int64_t)kMfmaTaus * 2 * tfs::kMfmaShifts * j.lg[b];
                 j.gsh_total += n;
                 j.gsh_max = std::max(j.gsh_max, n);
             }
@@ -373,7 +397,7 @@ void plan_job(Job &j) {
     j.off_rows = take(sizeof(tfs::RowPlan) * n_t0);
     j.off_tau = take(sizeof(int64_t) * n_tau);
     j.off_lcol = take(sizeof(int32_t) * n_tau);
-    if (is_exp) {
+    if (is_exp && !j.use_recur) {
         j.off_lblk = take(sizeof(int32_t) * j.NB);
         j.off_boff = take(sizeof(int64_t) * j.NB);
         j.off_order = take(sizeof(int32_t) * j.NB);
@@ -383,10 +407,13 @@ void plan_job(Job &j) {
         }
     }
     j.tables_bytes = o;
-    if (is_exp) {
+    if (is_exp && j.use_recur) {
+        // no weight tables
+    } else if (is_exp) {
         j.off_g32 = take(sizeof(float) * std::max<int64_t>(j.wtot, 1));
         j.off_gsq = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
-        if (j.prec == TFSTAT_PREC_FP64) j.off_g64 = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
+        if (j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64)
+            j.off_g64 = take(sizeof(double) * std::max<int64_t>(j.wtot, 1));
         if (j.use_mfma && j.n_mfma > 0) {
             // rows padded to whole blocks: the matrix-core kernel copies them
             j.off_abc = take(sizeof(double) * 3 * (size_t)n_t0 * abc_pitch(n_tau));
@@ -528,7 +555,7 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
     std::memcpy(h + j.off_rows, j.rows.data(), sizeof(tfs::RowPlan) * n_t0);
     std::memcpy(h + j.off_tau, j.win.tau.data(), sizeof(int64_t) * n_tau);
     std::memcpy(h + j.off_lcol, j.lcol.data(), sizeof(int32_t) * n_tau);
-    if (is_exp) {
+    if (is_exp && !j.use_recur) {
         std::memcpy(h + j.off_lblk, j.lblk.data(), sizeof(int32_t) * j.NB);
         std::memcpy(h + j.off_boff, j.blk_off.data(), sizeof(int64_t) * j.NB);
         std::memcpy(h + j.off_order, j.order.data(), sizeof(int32_t) * j.NB);
@@ -545,12 +572,32 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
     auto *part = ws_ptr<tfs::Partial>(j, j.off_part);
     auto *res = ws_ptr<tfs::BinResultDev>(j, j.off_res);
 
-    if (is_exp) {
+    if (is_exp && j.use_recur) {
+        tfs::RecurParams rp{};
+        rp.K = at.K;
+        rp.n_bins = at.n_bins;
+        rp.n_t0 = n_t0;
+        rp.n_tau = n_tau;
+        rp.t_sft = at.t_sft;
+        rp.k0_first = j.recur_k0;
+        rp.stride = j.recur_stride;
+        rp.delta = j.rows[0].delta;
+        rp.n_tiles = j.n_tiles;
+        rp.tau = tau;
+        rp.abc = at.abc;
+        rp.x64 = at.x64;
+        rp.npref = at.npref;
+        rp.twoF = j.twoF;
+        rp.part = part;
+        record_kernel(ctx, j, TFSTAT_K_RECUR, s, true);
+        hip_check(tfs::launch_exp_recur(rp, j.recur_bg, s), "exp recurrence kernel");
+        record_kernel(ctx, j, TFSTAT_K_RECUR, s, false);
+    } else if (is_exp) {
         tfs::WeightParams wp{};
         wp.n_tau = n_tau;
         wp.n_blocks = j.NB;
         wp.R = j.R;
-        wp.want64 = j.prec == TFSTAT_PREC_FP64;
+        wp.want64 = j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64;
         wp.t_sft = at.t_sft;
         wp.tau = tau;
         wp.lcol = lcol;
@@ -584,7 +631,8 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         p.abc_out = nullptr;
         if (j.n_valu > 0) {
             record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
-            hip_check(tfs::launch_exp_valu(p, j.prec == TFSTAT_PREC_FP64 ? 0 : 1, j.R, j.BG, s),
+            hip_check(tfs::launch_exp_valu(p, (j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64) ? 0 : 1,
+                                           j.R, j.BG, s),
                       "exp kernel");
             record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
         }
@@ -916,6 +964,7 @@ int tfstat_atoms_upload(tfstat_ctx *ctx, const tfstat_atoms_desc *d, tfstat_atom
         const size_t abc_b = round_up(sizeof(double) * 4 * rows, 256);
         const size_t x64_b = round_up(sizeof(double) * 4 * nb * rows, 256);
         const size_t x32_b = round_up(sizeof(float) * 4 * nb * rows, 256);
+        const size_t np_b = round_up(sizeof(int32_t) * rows, 256);
         auto set = std::make_unique<AtomsSet>();
         set->K = K;
         set->n_bins = nb;
@@ -924,18 +973,19 @@ int tfstat_atoms_upload(tfstat_ctx *ctx, const tfstat_atoms_desc *d, tfstat_atom
         set->t_sft = T;
         {
             std::lock_guard<std::mutex> g(ctx->mu);
-            set->mem = ctx->arena.alloc(abc_b + x64_b + x32_b);
+            set->mem = ctx->arena.alloc(abc_b + x64_b + x32_b + np_b);
         }
         if (!set->mem) raise(TFSTAT_E_NOMEM, "arena cannot hold the atoms");
-        set->bytes = abc_b + x64_b + x32_b;
+        set->bytes = abc_b + x64_b + x32_b + np_b;
         char *base = static_cast<char *>(set->mem);
         set->abc = reinterpret_cast<double *>(base);
         set->x64 = reinterpret_cast<double *>(base + abc_b);
         set->x32 = reinterpret_cast<float *>(base + abc_b + x64_b);
+        set->npref = reinterpret_cast<int32_t *>(base + abc_b + x64_b + x32_b);
         size_t pin_bytes = 0;
-        void *pin = ctx->pinned.get(abc_b + x64_b, &pin_bytes);
+        void *pin = ctx->pinned.get(abc_b + x64_b + np_b, &pin_bytes);
         try {
-            std::memset(pin, 0, abc_b + x64_b);
+            std::memset(pin, 0, abc_b + x64_b + np_b);
             double *habc = static_cast<double *>(pin);
             double *hx = reinterpret_cast<double *>(static_cast<char *>(pin) + abc_b);
             for (int32_t i = 0; i < d->n_sft; ++i) {
@@ -954,8 +1004,18 @@ int tfstat_atoms_upload(tfstat_ctx *ctx, const tfstat_atoms_desc *d, tfstat_atom
                 }
             }
             hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+            // present-SFT prefix counts (exact integers)
+            int32_t *hnp = reinterpret_cast<int32_t *>(static_cast<char *>(pin) + abc_b + x64_b);
+            {
+                std::vector<char> present(K, 0);
+                for (int32_t i = 0; i < d->n_sft; ++i) present[(d->timestamps[i] - T0) / T] = 1;
+                hnp[0] = 0;
+                for (int32_t k = 0; k < K; ++k) hnp[k + 1] = hnp[k] + present[k];
+            }
             hip_check(hipMemcpyAsync(set->mem, pin, abc_b + x64_b, hipMemcpyHostToDevice, ctx->stream),
                       "upload atoms");
+            hip_check(hipMemcpyAsync(set->npref, hnp, sizeof(int32_t) * rows, hipMemcpyHostToDevice,
+                                     ctx->stream), "upload counts");
             Job dummy;
             record_kernel(ctx, dummy, TFSTAT_K_UPLOAD, ctx->stream, true);
             hip_check(tfs::launch_build_x32(set->x64, set->x32, (int64_t)4 * nb * rows, ctx->stream),
@@ -1006,8 +1066,7 @@ int tfstat_fmap(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win, i
                 float *twoF_dev, tfstat_bin_result *res_host) {
     return guarded([&] {
         if (!ctx || !res_host) raise(TFSTAT_E_INVAL, "null argument");
-        if (precision != TFSTAT_PREC_FP64 && precision != TFSTAT_PREC_FP32 &&
-            precision != TFSTAT_PREC_BF16X3)
+        if (precision < TFSTAT_PREC_FP64 || precision > TFSTAT_PREC_RECUR64)
             raise(TFSTAT_E_INVAL, "unknown precision");
         Job j;
         {
@@ -1097,8 +1156,7 @@ int tfstat_submit(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win,
                   tfstat_ticket *out) {
     return guarded([&] {
         if (!ctx || !out) raise(TFSTAT_E_INVAL, "null argument");
-        if (precision != TFSTAT_PREC_FP64 && precision != TFSTAT_PREC_FP32 &&
-            precision != TFSTAT_PREC_BF16X3)
+        if (precision < TFSTAT_PREC_FP64 || precision > TFSTAT_PREC_RECUR64)
             raise(TFSTAT_E_INVAL, "unknown precision");
         auto job = std::make_unique<Job>();
         job->win = copy_window(win);

@@ -110,6 +110,23 @@ struct ShiftTableParams {
     unsigned short *gsh;
 };
 
+// Exponential-window sums by the t0 recurrence (rows k0_first + m * stride,
+// one common delta).  Partials: one tile per tau column.
+struct RecurParams {
+    int32_t K, n_bins;
+    int32_t n_t0, n_tau;
+    int64_t t_sft;
+    int32_t k0_first, stride;
+    int32_t delta;
+    int32_t n_tiles;          // partial slots per bin (n_tau)
+    const int64_t *tau;
+    const double *abc;        // [K+1][4]
+    const double *x64;        // [K+1][n_bins][4]
+    const int32_t *npref;     // [K+1] SFTs present in slots [0, k)
+    float *twoF;
+    Partial *part;
+};
+
 struct WeightParams {
     int32_t n_tau;
     int32_t n_blocks;
@@ -168,9 +185,28 @@ hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG,
 // A/B/C only (FP64), R = 8 blocks, into p.abc_out.
 hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s);
 hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s);
+hipError_t launch_exp_recur(const RecurParams &p, int BG, hipStream_t s);
 hipError_t launch_shift_tables(const ShiftTableParams &p, int64_t max_entries, hipStream_t s);
 // Entries per shifted table (one tau, part and shift) for a band of lblk.
-inline int32_t shift_table_len(int32_t lblk) { return (128 + lblk + 256 + 72 + 8 + 7) / 8 * 8; }
+// Matrix-core tile constants (compile-time tunables).
+#ifndef TFS_MFMA_SK
+#define TFS_MFMA_SK 256          // band slots per staged weight window
+#endif
+#ifndef TFS_MFMA_SHIFTS
+#define TFS_MFMA_SHIFTS 4        // shifted weight copies: 4 (8-byte reads) or 8 (16-byte reads)
+#endif
+#ifndef TFS_MFMA_TWPAD
+#define TFS_MFMA_TWPAD 80        // window width beyond SK (>= 72, multiple of 8; sets the LDS pitch)
+#endif
+constexpr int kMfmaSK = TFS_MFMA_SK;
+constexpr int kMfmaShifts = TFS_MFMA_SHIFTS;
+constexpr int kMfmaTW = TFS_MFMA_SK + TFS_MFMA_TWPAD;
+constexpr int kMfmaPad = 128;    // zero entries in front of every shifted table
+static_assert(TFS_MFMA_TWPAD >= 72 && TFS_MFMA_TWPAD % 8 == 0, "window padding");
+static_assert(TFS_MFMA_SHIFTS == 4 || TFS_MFMA_SHIFTS == 8, "shifted copies");
+// Entries per shifted table (one tau, part and shift) for a band of lblk:
+// every staged window [d_lo + kPad, d_lo + kPad + kTW) with d_lo <= lblk - 1.
+inline int32_t shift_table_len(int32_t lblk) { return (kMfmaPad + lblk + kMfmaTW + 8 + 7) / 8 * 8; }
 hipError_t launch_build_planes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16,
                                int32_t kp, unsigned short *xhi, unsigned short *xlo,
                                hipStream_t s);

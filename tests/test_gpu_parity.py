@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 T = tfsynth.T_SFT
 F32_MAP = 2.0 ** -23
-TOL = {"fp32": 1e-4, "fp64": 1e-9, "bf16x3": 1e-4}
+TOL = {"fp32": 1e-4, "fp64": 1e-9, "bf16x3": 1e-4, "recur64": 1e-8}
 
 
 @pytest.fixture(scope="module")
@@ -274,6 +274,50 @@ def test_full_exp_256_bins_bf16x3(ctx):
     for b in range(atoms.n_bins):
         assert abs(res[b]["logB"] - res32[b]["logB"]) <= 1e-3
         assert abs(res[b]["max2F"] - res32[b]["max2F"]) <= 2e-4 * max(res32[b]["max2F"], 1.0)
+
+
+@pytest.mark.parametrize("case", ["stride1", "stride3_delta", "past_end", "before_data", "bins5",
+                                  "irregular"])
+def test_recur64_edges(ctx, case):
+    """Exponential sums by the t0 recurrence: strides, a common offset,
+    rows past the end of the data and before its start, ragged bin groups,
+    and an irregular grid (direct FP64 sums)."""
+    _case("recur64 " + case)
+    if case == "stride1":
+        atoms = tfsynth.make_atoms(1, 150, 0.2, 2)
+        win = tfsynth.regular_window("exp", 0, T, 100, 2 * T, 3 * T + 7, 9)
+    elif case == "stride3_delta":
+        atoms = tfsynth.make_atoms(2, 200, 0.1, 1)
+        win = tfsynth.regular_window("exp", 77, 3 * T, 70, T // 2, 5 * T, 8)
+    elif case == "past_end":
+        atoms = tfsynth.make_atoms(3, 120, 0.3, 1)
+        win = tfsynth.regular_window("exp", 60 * T, T, 90, 2 * T, 11 * T, 6)
+    elif case == "before_data":
+        atoms = tfsynth.make_atoms(4, 120, 0.1, 1)
+        win = tfsynth.regular_window("exp", -20 * T - 5, 2 * T, 40, 2 * T, 13 * T, 5)
+    elif case == "bins5":
+        atoms = tfsynth.make_atoms(5, 700, 0.15, 5,
+                                   injections=[tfsynth.Injection(3, "exp", 100 * T, 60 * T, 1.0)])
+        win = tfsynth.regular_window("exp", 0, T, 300, 2 * T, 4 * T, 70)
+    else:
+        atoms = tfsynth.make_atoms(6, 300, 0.1, 2)
+        win = tfsynth.list_window("exp", [0, 5 * T, 7 * T + 3, 40 * T, 41 * T], [2 * T, 9 * T, 70 * T])
+    run_and_check(ctx, atoms, win, "recur64")
+
+
+def test_full_exp_1bin_recur64(ctx):
+    """The 1-bin benchmark workload by the recurrence, every cell."""
+    _case("full exp 1 bin recur64")
+    atoms, win = tfsynth.workload_exp_1bin()
+    aid = ctx.upload_atoms(atoms)
+    try:
+        res, twoF = ctx.fmap(aid, win, "recur64", want_map=True)
+    finally:
+        ctx.free(aid)
+    ref = oracle.fmap_atoms(atoms, win)
+    err = check_map(twoF.cpu().numpy(), ref, 1e-8)
+    check_results(res, ref, win, 1e-8)
+    print("full exp 1 bin recur64: max rel err %.3e" % err, flush=True)
 
 
 def test_full_rect_workload_results(ctx):
