@@ -201,12 +201,89 @@ def serving(ctx, seed: int = 4000, rate_hz: float = 200.0, duration_s: float = 4
     }
 
 
+def bench_batch(args, tf, torch):
+    """The uneven batch: 64 follow-up candidates (slots log-uniform in
+    [500, 8000], gaps U[0, 0.3], grids U{100..1500}^2, 1..16 bins, rect and
+    exp alternating) as one planned batch -- one captured graph with one
+    persistent fused launch per step -- against the same maps computed one
+    map per call."""
+    cands = [tfsynth.candidate(i) for i in range(64)]
+    exp_present = exp_cells_sfts = exp_slots = rect_cells = 0
+    for a, w in cands:
+        if w.kind == "exp":
+            p, sl = work_counts(a, w)
+            exp_present += p
+            exp_slots += sl
+            exp_cells_sfts += p // a.n_bins
+        else:
+            rect_cells += w.n_t0 * w.n_tau * a.n_bins
+    ctx = tf.Context(0, arena_bytes=16 << 30)
+    ids = [ctx.upload_atoms(a) for a, _ in cands]
+    items = list(zip(ids, [w for _, w in cands]))
+    t = time.perf_counter()
+    batch = ctx.batch(items, args.prec, tune=not args.no_tune)
+    plan_s = time.perf_counter() - t
+    for _ in range(args.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    fused = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = batch.run()
+        fused.append(batch.stats()["last_fused_ms"])
+    t1 = time.perf_counter()
+    st = batch.stats()
+    ms = (t1 - t0) * 1e3 / args.steps
+    # one map per call: the same maps, sequentially, plain launches
+    for aid, w in items[:4]:
+        ctx.fmap(aid, w, args.prec)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    seq = [ctx.fmap(aid, w, args.prec)[0] for aid, w in items]
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - ts) * 1e3
+    same = all(r1 == r2 for a, b in zip(res, seq) for r1, r2 in zip(a, b))
+    fused_ms = float(np.mean(fused))
+    # algorithmic flops of the fused kernel: 4 FMA per exp cell*SFT*bin, 3 FP64
+    # FMA (A, B, C) per exp cell*SFT, about 30 FP64 flops per rect cell*bin
+    flops = 8.0 * exp_present + 6.0 * exp_cells_sfts + 30.0 * rect_cells
+    roof = {"bound": "alu", "achieved": flops / (fused_ms * 1e-3) / 1e12, "peak": PEAK_ALU_TFLOPS,
+            "unit": "TFLOP/s", "kernel": "fused", "kernel_avg_ms": fused_ms, "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {
+        "metric": "F-map cells*SFTs/s (exp window) and served maps/s with p50/p99 latency",
+        "value": exp_present / (ms * 1e-3),
+        "unit": "cells*SFTs*bins/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32+f64", "fp64": "f64"}[args.prec], "data": "synthetic",
+        "config": {"workload": "uneven batch: 64 candidates, 32 exp + 32 rect maps, 1-16 bins",
+                   "exp_cells_sfts_bins": exp_present, "exp_cells_slots_bins": exp_slots,
+                   "rect_cells_bins": rect_cells, "maps": len(cands),
+                   "bin_maps": st["n_results"], "precision": args.prec,
+                   "parallelism": "single GPU"},
+        "batch": {"variant": st["variant"], "groups": st["groups"], "tiles": st["n_tiles"],
+                  "tune_ms": st["tune_ms"], "plan_s": plan_s, "graph_ms": st["last_ms"],
+                  "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / ms,
+                  "results_equal_sequential": bool(same)},
+        "roofline": roof,
+    }
+    batch.close()
+    for aid in ids:
+        ctx.free(aid)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="exp1bin", choices=["exp1bin", "exp256", "rect", "rect256"])
+    ap.add_argument("--workload", default="exp1bin",
+                    choices=["exp1bin", "exp256", "rect", "rect256", "batch"])
+    ap.add_argument("--no-tune", action="store_true", help="batch: default tile shapes")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3", "recur64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-map", action="store_true",
@@ -242,6 +319,12 @@ def main(argv=None):
         print(json.dumps({"copy_bytes": 4 * n, "ms_per_copy": ms,
                           "GBps_read_plus_write": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
         return 0
+
+    if args.workload == "batch":
+        if args.prec not in ("fp32", "fp64"):
+            print("bench.py: the batch runs in fp32 or fp64", file=sys.stderr)
+            return 2
+        return bench_batch(args, tf, torch)
 
     desc, atoms, win = make_workload(args.workload)
     present, slots = work_counts(atoms, win)

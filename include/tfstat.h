@@ -216,6 +216,54 @@ int tfstat_poll(tfstat_ctx *ctx, tfstat_ticket t, tfstat_bin_result *res_host,
 int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t);
 
 /*
+ * Uneven batch: many maps -- different resident atoms, grids, numbers of
+ * bins and window types -- computed together (the per-map work of section 3,
+ * for the many candidates and frequency bins of section 5).  A batch is
+ * planned once and can be run many times.  Each run is one captured HIP
+ * graph: the weight tables and prefix sums of all maps, then ONE persistent
+ * launch in which every workgroup draws tiles of all maps from a shared
+ * list (largest expected cost first), then the per-bin merges.  Every
+ * result equals what tfstat_fmap returns for the same map at the same
+ * precision (same arithmetic per cell, same tile partials and merge order).
+ * No maps are materialised.
+ *   n_maps     number of maps; ids[i] and wins[i] describe map i.
+ *   precision  TFSTAT_PREC_FP32 or TFSTAT_PREC_FP64 (exponential sums;
+ *              rectangular windows always use compensated FP64 prefixes).
+ *   tune       0: default tile shapes and launch width; 1: time every
+ *              candidate (tile shape x persistent workgroups per CU) on this
+ *              batch and keep the fastest; the choice is cached in the
+ *              context under the batch's shape signature and reused by
+ *              later batches of the same shape.
+ * The plan keeps its workspace in the arena, and its atoms busy, until
+ * tfstat_batch_destroy.
+ * Errors: E_INVAL, E_GRID, E_NOTFOUND, E_NOMEM, E_DEVICE.
+ */
+typedef struct tfstat_batch tfstat_batch;
+
+typedef struct {
+    int32_t variant;          /* fused-kernel tile shape: 0 FP64 R4, 1 FP32 R8, 2 FP32 R4 x 2 bins,
+                                 3 FP32 R4 x 4 bins, 4 per-map shape by its bin count */
+    int32_t groups;           /* persistent workgroups of the fused launch */
+    int32_t n_tiles;          /* tiles in the shared list */
+    int32_t n_results;        /* sum of n_bins over the maps */
+    double tune_ms;           /* host time spent tuning (0 if not tuned here) */
+    double last_ms;           /* device time of the last run (graph, HIP events) */
+    double last_fused_ms;     /* device time of its persistent fused launch */
+} tfstat_batch_stats;
+
+int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *ids,
+                        const tfstat_window *wins, int32_t precision, int32_t tune,
+                        tfstat_batch **out);
+
+/* Runs the batch (synchronous).  res_host receives n_results entries: the
+ * n_bins results of map 0, then those of map 1, and so on. */
+int tfstat_batch_run(tfstat_ctx *ctx, tfstat_batch *b, tfstat_bin_result *res_host);
+
+int tfstat_batch_stats_read(const tfstat_batch *b, tfstat_batch_stats *out);
+
+int tfstat_batch_destroy(tfstat_ctx *ctx, tfstat_batch *b);
+
+/*
  * Per-kernel timing.  When enabled, the context brackets each kernel launch
  * with HIP events on its stream; tfstat_profile_read returns, for kernel
  * class `kind` (see tfstat_kernel_kind), the number of launches and their

@@ -195,6 +195,11 @@ class Context:
     def cancel(self, ticket: int):
         _abi.check(self._lib.tfstat_cancel(self._ctx, ctypes.c_uint64(ticket)))
 
+    # -- uneven batch ----------------------------------------------------------------
+    def batch(self, items, precision="fp32", tune: bool = False) -> "Batch":
+        """Plans a batch of maps: items is a sequence of (atoms_id, window)."""
+        return Batch(self, items, precision, tune)
+
     # -- profiling -----------------------------------------------------------------
     def profile(self, on: bool = True):
         _abi.check(self._lib.tfstat_profile_enable(self._ctx, 1 if on else 0))
@@ -210,6 +215,53 @@ class Context:
             _abi.check(self._lib.tfstat_profile_read(self._ctx, k, ctypes.byref(n), ctypes.byref(ms)))
             out[name] = (n.value, ms.value)
         return out
+
+
+class Batch:
+    """Many maps planned together and run as one captured graph with one
+    persistent fused launch (tfstat_batch_*)."""
+
+    def __init__(self, ctx: Context, items, precision="fp32", tune: bool = False):
+        self._ctx = ctx
+        self._lib = ctx._lib
+        items = list(items)
+        if not items:
+            raise ValueError("a batch needs at least one map")
+        self._wins = [_WindowArgs.from_window(w) for _, w in items]
+        ids = (ctypes.c_uint64 * len(items))(*[int(a) for a, _ in items])
+        wins = (_abi.Window * len(items))(*[w.struct for w in self._wins])
+        self._bins = [ctx._n_bins(int(a)) for a, _ in items]
+        self._h = ctypes.c_void_p()
+        _abi.check(self._lib.tfstat_batch_create(ctx._ctx, len(items), ids, wins, _prec(precision),
+                                                 1 if tune else 0, ctypes.byref(self._h)))
+
+    def run(self) -> List[List[dict]]:
+        """Runs the batch; per map, the list of its per-bin result dicts."""
+        res = (_abi.BinResult * sum(self._bins))()
+        _abi.check(self._lib.tfstat_batch_run(self._ctx._ctx, self._h, res))
+        out, o = [], 0
+        for nb in self._bins:
+            out.append(_results(res[o:o + nb]))
+            o += nb
+        return out
+
+    def stats(self) -> dict:
+        st = _abi.BatchStats()
+        _abi.check(self._lib.tfstat_batch_stats_read(self._h, ctypes.byref(st)))
+        return dict(variant=_abi.BATCH_VARIANTS[st.variant], groups=st.groups, n_tiles=st.n_tiles,
+                    n_results=st.n_results, tune_ms=st.tune_ms, last_ms=st.last_ms,
+                    last_fused_ms=st.last_fused_ms)
+
+    def close(self):
+        if self._h:
+            _abi.check(self._lib.tfstat_batch_destroy(self._ctx._ctx, self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def version() -> str:

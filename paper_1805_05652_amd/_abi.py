@@ -65,6 +65,21 @@ class BinResult(ctypes.Structure):
     ]
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int32),
+        ("groups", ctypes.c_int32),
+        ("n_tiles", ctypes.c_int32),
+        ("n_results", ctypes.c_int32),
+        ("tune_ms", ctypes.c_double),
+        ("last_ms", ctypes.c_double),
+        ("last_fused_ms", ctypes.c_double),
+    ]
+
+
+BATCH_VARIANTS = ["fp64_r4", "fp32_r8", "fp32_r4_b2", "fp32_r4_b4", "mixed"]
+
+
 # Every symbol the header declares, with (restype, argtypes).
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -82,6 +97,11 @@ SIGNATURES = {
     "tfstat_submit": (ctypes.c_int, [_P, _U64, ctypes.POINTER(Window), _I32, ctypes.POINTER(_U64)]),
     "tfstat_poll": (ctypes.c_int, [_P, _U64, ctypes.POINTER(BinResult), ctypes.POINTER(ctypes.c_int)]),
     "tfstat_cancel": (ctypes.c_int, [_P, _U64]),
+    "tfstat_batch_create": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_U64), ctypes.POINTER(Window), _I32,
+                                           _I32, ctypes.POINTER(_P)]),
+    "tfstat_batch_run": (ctypes.c_int, [_P, _P, ctypes.POINTER(BinResult)]),
+    "tfstat_batch_stats_read": (ctypes.c_int, [_P, ctypes.POINTER(BatchStats)]),
+    "tfstat_batch_destroy": (ctypes.c_int, [_P, _P]),
     "tfstat_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "tfstat_profile_read": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_double)]),
     "tfstat_profile_reset": (ctypes.c_int, [_P]),

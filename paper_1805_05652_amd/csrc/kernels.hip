@@ -14,6 +14,8 @@
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 namespace tfs {
@@ -87,19 +89,28 @@ __device__ inline Q4<double> load_q4(const double *p) {
     return Q4<double>{a.x, a.y, b.x, b.y};
 }
 
-template <typename XT>
-__device__ inline const XT *xplane(const AtomsView &at);
-template <>
-__device__ inline const float *xplane<float>(const AtomsView &at) { return at.x32; }
-template <>
-__device__ inline const double *xplane<double>(const AtomsView &at) { return at.x64; }
+// Data plane and weight table of the sum type XT; PP is the parameter block,
+// possibly in the constant address space.
+template <typename XT, typename PP>
+__device__ inline const XT *xplane(PP &p) {
+    if constexpr (sizeof(XT) == 4) return p.at.x32;
+    else return p.at.x64;
+}
+template <typename XT, typename PP>
+__device__ inline const XT *wplane(PP &p) {
+    if constexpr (sizeof(XT) == 4) return p.g32;
+    else return p.g64;
+}
 
-template <typename XT>
-__device__ inline const XT *wplane(const ExpValuParams &p);
-template <>
-__device__ inline const float *wplane<float>(const ExpValuParams &p) { return p.g32; }
-template <>
-__device__ inline const double *wplane<double>(const ExpValuParams &p) { return p.g64; }
+// A parameter block that the kernel never writes, read with scalar loads
+// from the constant address space wherever a field is used.
+template <typename T>
+using ConstParams = const __attribute__((address_space(4))) T;
+
+template <typename T>
+__device__ inline ConstParams<T> &const_params(const T *p) {
+    return *reinterpret_cast<ConstParams<T> *>(reinterpret_cast<uintptr_t>(p));
+}
 
 // ---------------------------------------------------------------------------
 // Exponential-window sums and finalize, VALU form.
@@ -196,26 +207,18 @@ struct ExpAcc {
     }
 };
 
-template <typename XT, int R, int BG, bool ABC_ONLY = false>
-__global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
-    __shared__ ExpSmem<XT, R, BG> sm;
+// One (64-row tile, R-tau block, BG-bin group) task of the exponential map:
+// q indexes p.blk_list.  Every thread of the workgroup calls it.
+template <typename XT, int R, int BG, bool ABC_ONLY = false, typename PP>
+__device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
+                                                               ExpSmem<XT, R, BG> &sm, int q,
+                                                               int row_tile, int bin_group) {
     const int tid = threadIdx.x;
     const int lane = tid & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-
-    // XCD-aware task order: workgroup b runs on XCD b % 8.  Blocks of tau
-    // (sorted largest band first) are dealt round-robin to the XCDs and all
-    // row tiles of a block stay on one XCD, so its weight table is fetched
-    // into one L2 only.
-    const int bid = blockIdx.x;
-    const int xcd = bid & 7;
-    const int slot = bid >> 3;
-    const int q = (slot / p.n_row_tiles) * 8 + xcd;
-    if (q >= p.n_list) return;
-    const int row_tile = slot % p.n_row_tiles;
     const int nb = p.blk_list[q];
     const int tile = nb * p.n_row_tiles + row_tile;
-    const int bin0 = blockIdx.y * BG;
+    const int bin0 = bin_group * BG;
     const int n_bins = p.at.n_bins;
     const int K = p.at.K;
 
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
     const int64_t off = p.blk_off[nb];
     const XT *__restrict__ gw_base = wplane<XT>(p) + off;
     const double *__restrict__ gq_base = p.gsq + off;
-    const XT *__restrict__ xg = xplane<XT>(p.at);
+    const XT *__restrict__ xg = xplane<XT>(p);
     const double *__restrict__ abc = p.at.abc;
 
     ExpAcc<XT, R, BG, ABC_ONLY> acc;
@@ -409,17 +412,31 @@ __global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
     }
 }
 
+template <typename XT, int R, int BG, bool ABC_ONLY = false>
+__global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
+    __shared__ ExpSmem<XT, R, BG> sm;
+    // XCD-aware task order: workgroup b runs on XCD b % 8.  Blocks of tau
+    // (sorted largest band first) are dealt round-robin to the XCDs and all
+    // row tiles of a block stay on one XCD, so its weight table is fetched
+    // into one L2 only.
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7;
+    const int slot = bid >> 3;
+    const int q = (slot / p.n_row_tiles) * 8 + xcd;
+    if (q >= p.n_list) return;
+    exp_tile<XT, R, BG, ABC_ONLY>(p, sm, q, slot % p.n_row_tiles, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // Exponential weight tables g_n[d] = exp(-d T / tau_n) for d < lcol[n],
 // blocked [block][d][R] and zero-padded to the block's longest band.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void weights_kernel(WeightParams p) {
-    const int nb = blockIdx.y;
+template <typename PP>
+__device__ inline void weights_block(PP &p, int nb, int chunk, int n_chunks) {
     const int R = p.R;
     const int64_t cnt = (int64_t)p.lblk[nb] * R;
     const int64_t off = p.blk_off[nb];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < cnt;
-         i += (int64_t)gridDim.x * 256) {
+    for (int64_t i = (int64_t)chunk * 256 + threadIdx.x; i < cnt; i += (int64_t)n_chunks * 256) {
         const int64_t d = i / R;
         const int r = (int)(i - d * R);
         const int n = nb * R + r;
@@ -430,6 +447,15 @@ __global__ __launch_bounds__(256) void weights_kernel(WeightParams p) {
         p.gsq[off + i] = g * g;
         if (p.want64) p.g64[off + i] = g;
     }
+}
+
+__global__ __launch_bounds__(256) void weights_kernel(WeightParams p) {
+    weights_block(p, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void weights_batch_kernel(WeightBatchParams p) {
+    const int e = blockIdx.x;
+    weights_block(const_params(p.jobs + p.job[e]), p.blk[e], blockIdx.y, gridDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -472,13 +498,13 @@ __device__ inline DD dd_add(DD x, DD y) {
     return DD{t.h, x.l + y.l + t.l};
 }
 
-__global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(const double *__restrict__ in,
-                                                               int64_t stride, double *__restrict__ out,
-                                                               int32_t K, int32_t C) {
-    __shared__ DD tot[kScanWaves][64];
+__device__ __attribute__((always_inline)) inline void scan_chunk(const double *__restrict__ in,
+                                                                 int64_t stride, double *__restrict__ out,
+                                                                 int32_t K, int32_t C, int chunk,
+                                                                 DD (*tot)[64]) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int c = blockIdx.x * 64 + lane;
+    const int c = chunk * 64 + lane;
     const int seg = (K + kScanWaves - 1) / kScanWaves;
     const int kb = min(K, wave * seg);
     const int ke = min(K, kb + seg);
@@ -503,17 +529,30 @@ __global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(const double *__r
     }
 }
 
+__global__ __launch_bounds__(kScanWaves * 64) void scan_kernel(const double *__restrict__ in,
+                                                               int64_t stride, double *__restrict__ out,
+                                                               int32_t K, int32_t C) {
+    __shared__ DD tot[kScanWaves][64];
+    scan_chunk(in, stride, out, K, C, blockIdx.x, tot);
+}
+
+__global__ __launch_bounds__(kScanWaves * 64) void scan_batch_kernel(const ScanJob *jobs) {
+    __shared__ DD tot[kScanWaves][64];
+    const ScanJob j = jobs[blockIdx.x];
+    scan_chunk(j.in, j.stride, j.out, j.K, j.C, j.chunk, tot);
+}
+
 // ---------------------------------------------------------------------------
 // Rectangular-window cells: window sums as prefix differences, finalize,
 // optional map, per-tile reduction.  Block = 4 rows x 64 taus of one bin.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void rect_kernel(RectParams p) {
-    __shared__ Red wred[kWaves];
+template <typename PP>
+__device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red *wred,
+                                                                 int bx, int by, int bin) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int n = blockIdx.x * 64 + lane;
-    const int m = blockIdx.y * kWaves + wave;
-    const int bin = blockIdx.z;
+    const int n = bx * 64 + lane;
+    const int m = by * kWaves + wave;
     const bool ok = n < p.n_tau && m < p.n_t0;
     const int nn = min(n, p.n_tau - 1);
     const int mm = min(m, p.n_t0 - 1);
@@ -548,19 +587,24 @@ __global__ __launch_bounds__(256) void rect_kernel(RectParams p) {
     if (threadIdx.x == 0) {
         Red t = wred[0];
         for (int w = 1; w < kWaves; ++w) t = red_combine(t, wred[w]);
-        Partial &o = p.part[(size_t)bin * p.n_tiles + blockIdx.y * p.n_tiles_n + blockIdx.x];
+        Partial &o = p.part[(size_t)bin * p.n_tiles + by * p.n_tiles_n + bx];
         o.fmax = t.f;
         o.s = t.s;
         o.idx = t.i;
     }
 }
 
+__global__ __launch_bounds__(256) void rect_kernel(RectParams p) {
+    __shared__ Red wred[kWaves];
+    rect_block(p, wred, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ---------------------------------------------------------------------------
 // Per-map merge of tile partials in a fixed order -> max 2F, argmax, logB.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void merge_kernel(MergeParams p) {
-    __shared__ Red sred[256];
-    const int map = blockIdx.x;
+template <typename PP>
+__device__ __attribute__((always_inline)) inline void merge_map(PP &p, int map,
+                                                                Red *sred) {
     const Partial *part = p.part + (size_t)map * p.n_tiles;
     Red r = red_empty();
     for (int t = threadIdx.x; t < p.n_tiles; t += 256) {
@@ -580,6 +624,113 @@ __global__ __launch_bounds__(256) void merge_kernel(MergeParams p) {
         o.logB = t.f + log(t.s) - log((double)p.n_cells);
         o.idx = t.i;
         p.out[map] = o;
+    }
+}
+
+__global__ __launch_bounds__(256) void merge_kernel(MergeParams p) {
+    __shared__ Red sred[256];
+    merge_map(p, blockIdx.x, sred);
+}
+
+__global__ __launch_bounds__(256) void merge_batch_kernel(MergeBatchParams p) {
+    __shared__ Red sred[256];
+    const int e = blockIdx.x;
+    merge_map(const_params(p.jobs + p.job[e]), p.map[e], sred);
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *dst, int32_t n, int32_t value) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) dst[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent fused kernel of an uneven batch.  Each workgroup takes the next
+// tile of the shared list (largest expected cost first) until the list is
+// exhausted, so that maps of very different sizes and both window types
+// keep every CU busy in one launch.  Every workgroup leaves once the counter
+// has passed the end of the list.
+// ---------------------------------------------------------------------------
+template <int V>
+struct FusedSmem {
+    static constexpr size_t exp_bytes =
+        V == kShapeD41   ? sizeof(ExpSmem<double, 4, 1>)
+        : V == kShapeF81 ? sizeof(ExpSmem<float, 8, 1>)
+        : V == kShapeF42 ? sizeof(ExpSmem<float, 4, 2>)
+        : V == kShapeF44 ? sizeof(ExpSmem<float, 4, 4>)
+                         : (sizeof(ExpSmem<float, 4, 4>) > sizeof(ExpSmem<double, 4, 1>)
+                                ? sizeof(ExpSmem<float, 4, 4>)
+                                : sizeof(ExpSmem<double, 4, 1>));
+    static constexpr size_t bytes = exp_bytes > sizeof(Red) * kWaves ? exp_bytes : sizeof(Red) * kWaves;
+};
+
+// Loads a descriptor that the kernel never writes, whose address is the same
+// in every lane, and keeps it in scalar registers.
+template <typename T>
+__device__ __attribute__((always_inline)) inline T load_uniform(const T *src) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized descriptor");
+    T out;
+    const int *s = reinterpret_cast<const int *>(src);
+    int *d = reinterpret_cast<int *>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
+    return out;
+}
+
+template <int SHAPE, typename PP>
+__device__ __attribute__((always_inline)) inline void fused_exp(PP &p, char *smem,
+                                                                const BatchTile &t) {
+    if constexpr (SHAPE == kShapeD41)
+        exp_tile<double, 4, 1>(p, *reinterpret_cast<ExpSmem<double, 4, 1> *>(smem), t.x, t.y, t.z);
+    else if constexpr (SHAPE == kShapeF81)
+        exp_tile<float, 8, 1>(p, *reinterpret_cast<ExpSmem<float, 8, 1> *>(smem), t.x, t.y, t.z);
+    else if constexpr (SHAPE == kShapeF42)
+        exp_tile<float, 4, 2>(p, *reinterpret_cast<ExpSmem<float, 4, 2> *>(smem), t.x, t.y, t.z);
+    else
+        exp_tile<float, 4, 4>(p, *reinterpret_cast<ExpSmem<float, 4, 4> *>(smem), t.x, t.y, t.z);
+}
+
+// waves per SIMD each variant is built for (those of the stand-alone
+// exponential kernel of the same shape)
+template <int V>
+constexpr int fused_waves() {
+    return V == kShapeF81 ? 4 : V == kShapeF44 ? 3 : V == kShapeMixed ? 3 : 5;
+}
+
+template <int V>
+__global__ __launch_bounds__(kThreads, fused_waves<V>()) void fused_kernel(FusedParams p) {
+    __shared__ __attribute__((aligned(16))) char smem[FusedSmem<V>::bytes];
+    __shared__ int s_next;
+#pragma unroll 1
+    for (;;) {
+        __syncthreads();   // the previous tile is finished with smem and s_next
+        if (threadIdx.x == 0) s_next = atomicAdd(p.counter, 1);
+        __syncthreads();
+        const int ti = __builtin_amdgcn_readfirstlane(s_next);
+        if (ti >= p.n_tiles) break;
+        const BatchTile t = load_uniform(p.tiles + ti);   // one tile, held in scalar registers
+        if (t.kind == 1) {
+            auto &rp = const_params(p.rect_jobs + t.job);
+            Red *wred = reinterpret_cast<Red *>(smem);
+            const int nby = (rp.n_t0 + kWaves - 1) / kWaves;
+#pragma unroll 1
+            for (int i = 0; i < kRectRowBlocks; ++i) {
+                const int by = t.y * kRectRowBlocks + i;
+                if (by >= nby) break;
+                if (i > 0) __syncthreads();   // wred of the previous block has been read
+                rect_block(rp, wred, t.x, by, t.z);
+            }
+            continue;
+        }
+        auto &ep = const_params(p.exp_jobs + t.job);
+        if constexpr (V == kShapeMixed) {
+            switch (t.shape) {
+            case kShapeD41: fused_exp<kShapeD41>(ep, smem, t); break;
+            case kShapeF81: fused_exp<kShapeF81>(ep, smem, t); break;
+            case kShapeF42: fused_exp<kShapeF42>(ep, smem, t); break;
+            default: fused_exp<kShapeF44>(ep, smem, t); break;
+            }
+        } else {
+            fused_exp<V>(ep, smem, t);
+        }
     }
 }
 
@@ -696,6 +847,71 @@ hipError_t launch_rect(const RectParams &p, hipStream_t s) {
 
 hipError_t launch_merge(const MergeParams &p, hipStream_t s) {
     hipLaunchKernelGGL(merge_kernel, dim3((unsigned)p.n_maps), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights_batch(const WeightBatchParams &p, hipStream_t s) {
+    if (p.n_entries <= 0) return hipSuccess;
+    if (p.chunks < 1 || p.chunks > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(weights_batch_kernel, dim3((unsigned)p.n_entries, (unsigned)p.chunks), dim3(256), 0,
+                       s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_batch(const ScanJob *jobs, int32_t n_jobs, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_batch_kernel, dim3((unsigned)n_jobs), dim3(kScanWaves * 64), 0, s, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_batch(const MergeBatchParams &p, hipStream_t s) {
+    if (p.n_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(merge_batch_kernel, dim3((unsigned)p.n_entries), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *dst, int32_t n, int32_t value, hipStream_t s) {
+    const int g = std::max(1, std::min((n + 255) / 256, 1024));
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)g), dim3(256), 0, s, dst, n, value);
+    return hipGetLastError();
+}
+
+namespace {
+template <int V>
+const void *fused_fn() {
+    return reinterpret_cast<const void *>(&fused_kernel<V>);
+}
+const void *fused_variant(int v) {
+    switch (v) {
+    case kShapeD41: return fused_fn<kShapeD41>();
+    case kShapeF81: return fused_fn<kShapeF81>();
+    case kShapeF42: return fused_fn<kShapeF42>();
+    case kShapeF44: return fused_fn<kShapeF44>();
+    case kShapeMixed: return fused_fn<kShapeMixed>();
+    default: return nullptr;
+    }
+}
+}  // namespace
+
+int fused_groups_per_cu(int variant) {
+    const void *fn = fused_variant(variant);
+    if (!fn) return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kThreads, 0) != hipSuccess) return 0;
+    return n;
+}
+
+hipError_t launch_fused(const FusedParams &p, int variant, int n_groups, hipStream_t s) {
+    if (p.n_tiles <= 0) return hipSuccess;
+    if (n_groups < 1) return hipErrorInvalidValue;
+    switch (variant) {
+    case kShapeD41: hipLaunchKernelGGL(fused_kernel<kShapeD41>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
+    case kShapeF81: hipLaunchKernelGGL(fused_kernel<kShapeF81>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
+    case kShapeF42: hipLaunchKernelGGL(fused_kernel<kShapeF42>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
+    case kShapeF44: hipLaunchKernelGGL(fused_kernel<kShapeF44>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
+    case kShapeMixed: hipLaunchKernelGGL(fused_kernel<kShapeMixed>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -241,6 +241,7 @@ struct Job {
     std::vector<int32_t> lcol, lblk, order;
     std::vector<int64_t> blk_off;
     int R = 0, BG = 0, NB = 0, n_row_tiles = 0, n_tiles = 0, n_tiles_n = 0;
+    int force_R = 0, force_BG = 0;   // exponential VALU tile shape chosen by the caller
     int64_t wtot = 0, max_blk = 0;
     bool use_recur = false;    // RECUR64: exponential sums by the t0 recurrence
     int32_t recur_stride = 0, recur_k0 = 0, recur_bg = 1;
@@ -330,6 +331,10 @@ void plan_job(Job &j) {
     } else if (is_exp) {
         const int prec = (j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64) ? 0 : 1;
         tfs::exp_valu_config(prec, at.n_bins, &j.R, &j.BG);
+        if (j.force_R) {
+            j.R = j.force_R;
+            j.BG = j.force_BG;
+        }
         if (j.use_mfma) {
             j.R = kMfmaTaus;
             j.BG = 1;
@@ -493,6 +498,12 @@ struct tfstat_ctx {
     std::condition_variable cv;
     bool stop = false;
     bool worker_started = false;
+
+    // uneven batches: their own stream (graphs cannot capture the null
+    // stream) and the autotuner's choices by batch shape signature
+    hipStream_t batch_stream = nullptr;
+    int n_cu = 0;
+    std::map<std::string, std::pair<int, int>> tuned;   // signature -> (variant, groups per CU)
 };
 
 namespace {
@@ -542,6 +553,95 @@ T *ws_ptr(Job &j, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(j.ws) + off);
 }
 
+// Host image of the job's planning tables (the first tables_bytes of its
+// workspace).
+void fill_tables(const Job &j, char *h) {
+    const int n_t0 = (int)j.win.t0.size();
+    const int n_tau = (int)j.win.tau.size();
+    std::memcpy(h + j.off_rows, j.rows.data(), sizeof(tfs::RowPlan) * n_t0);
+    std::memcpy(h + j.off_tau, j.win.tau.data(), sizeof(int64_t) * n_tau);
+    std::memcpy(h + j.off_lcol, j.lcol.data(), sizeof(int32_t) * n_tau);
+    if (j.win.type == TFSTAT_WIN_EXP && !j.use_recur) {
+        std::memcpy(h + j.off_lblk, j.lblk.data(), sizeof(int32_t) * j.NB);
+        std::memcpy(h + j.off_boff, j.blk_off.data(), sizeof(int64_t) * j.NB);
+        std::memcpy(h + j.off_order, j.order.data(), sizeof(int32_t) * j.NB);
+        if (j.use_mfma) {
+            std::memcpy(h + j.off_lg, j.lg.data(), sizeof(int32_t) * j.NB);
+            std::memcpy(h + j.off_gshoff, j.gsh_off.data(), sizeof(int64_t) * j.NB);
+        }
+    }
+}
+
+bool wants64(const Job &j) { return j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64; }
+
+tfs::WeightParams weight_params(Job &j) {
+    tfs::WeightParams wp{};
+    wp.n_tau = (int32_t)j.win.tau.size();
+    wp.n_blocks = j.NB;
+    wp.R = j.R;
+    wp.want64 = wants64(j);
+    wp.t_sft = j.at->t_sft;
+    wp.tau = ws_ptr<int64_t>(j, j.off_tau);
+    wp.lcol = ws_ptr<int32_t>(j, j.off_lcol);
+    wp.lblk = ws_ptr<int32_t>(j, j.off_lblk);
+    wp.blk_off = ws_ptr<int64_t>(j, j.off_boff);
+    wp.g32 = ws_ptr<float>(j, j.off_g32);
+    wp.gsq = ws_ptr<double>(j, j.off_gsq);
+    wp.g64 = wp.want64 ? ws_ptr<double>(j, j.off_g64) : nullptr;
+    return wp;
+}
+
+tfs::ExpValuParams exp_params(Job &j) {
+    tfs::ExpValuParams p{};
+    p.at = j.at->view();
+    p.n_t0 = (int32_t)j.win.t0.size();
+    p.n_tau = (int32_t)j.win.tau.size();
+    p.n_row_tiles = j.n_row_tiles;
+    p.n_list = j.n_valu;
+    p.n_tiles = j.n_tiles;
+    p.rows = ws_ptr<tfs::RowPlan>(j, j.off_rows);
+    p.tau = ws_ptr<int64_t>(j, j.off_tau);
+    p.lcol = ws_ptr<int32_t>(j, j.off_lcol);
+    p.lblk = ws_ptr<int32_t>(j, j.off_lblk);
+    p.blk_off = ws_ptr<int64_t>(j, j.off_boff);
+    p.blk_list = ws_ptr<int32_t>(j, j.off_order);
+    p.g32 = ws_ptr<float>(j, j.off_g32);
+    p.g64 = wants64(j) ? ws_ptr<double>(j, j.off_g64) : nullptr;
+    p.gsq = ws_ptr<double>(j, j.off_gsq);
+    p.twoF = j.twoF;
+    p.part = ws_ptr<tfs::Partial>(j, j.off_part);
+    p.abc_out = nullptr;
+    return p;
+}
+
+tfs::RectParams rect_params(Job &j) {
+    tfs::RectParams p{};
+    p.K = j.at->K;
+    p.n_bins = j.at->n_bins;
+    p.n_t0 = (int32_t)j.win.t0.size();
+    p.n_tau = (int32_t)j.win.tau.size();
+    p.t_sft = j.at->t_sft;
+    p.n_tiles_n = j.n_tiles_n;
+    p.n_tiles = j.n_tiles;
+    p.rows = ws_ptr<tfs::RowPlan>(j, j.off_rows);
+    p.tau = ws_ptr<int64_t>(j, j.off_tau);
+    p.pabc = ws_ptr<double>(j, j.off_pabc);
+    p.px = ws_ptr<double>(j, j.off_px);
+    p.twoF = j.twoF;
+    p.part = ws_ptr<tfs::Partial>(j, j.off_part);
+    return p;
+}
+
+tfs::MergeParams merge_params(Job &j) {
+    tfs::MergeParams mp{};
+    mp.n_tiles = j.n_tiles;
+    mp.n_maps = j.at->n_bins;
+    mp.n_cells = (int64_t)j.win.t0.size() * (int64_t)j.win.tau.size();
+    mp.part = ws_ptr<tfs::Partial>(j, j.off_part);
+    mp.out = ws_ptr<tfs::BinResultDev>(j, j.off_res);
+    return mp;
+}
+
 // Enqueues every step of the map on stream s (tables upload, kernels,
 // results download into pinned memory).  The workspace must be allocated.
 void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
@@ -552,23 +652,10 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
     const size_t res_bytes = sizeof(tfs::BinResultDev) * at.n_bins;
     if (!j.pin) j.pin = ctx->pinned.get(std::max(j.tables_bytes, res_bytes), &j.pin_bytes);
     char *h = static_cast<char *>(j.pin);
-    std::memcpy(h + j.off_rows, j.rows.data(), sizeof(tfs::RowPlan) * n_t0);
-    std::memcpy(h + j.off_tau, j.win.tau.data(), sizeof(int64_t) * n_tau);
-    std::memcpy(h + j.off_lcol, j.lcol.data(), sizeof(int32_t) * n_tau);
-    if (is_exp && !j.use_recur) {
-        std::memcpy(h + j.off_lblk, j.lblk.data(), sizeof(int32_t) * j.NB);
-        std::memcpy(h + j.off_boff, j.blk_off.data(), sizeof(int64_t) * j.NB);
-        std::memcpy(h + j.off_order, j.order.data(), sizeof(int32_t) * j.NB);
-        if (j.use_mfma) {
-            std::memcpy(h + j.off_lg, j.lg.data(), sizeof(int32_t) * j.NB);
-            std::memcpy(h + j.off_gshoff, j.gsh_off.data(), sizeof(int64_t) * j.NB);
-        }
-    }
+    fill_tables(j, h);
     hip_check(hipMemcpyAsync(j.ws, h, j.tables_bytes, hipMemcpyHostToDevice, s), "upload tables");
 
-    const auto *rows = ws_ptr<tfs::RowPlan>(j, j.off_rows);
     const auto *tau = ws_ptr<int64_t>(j, j.off_tau);
-    const auto *lcol = ws_ptr<int32_t>(j, j.off_lcol);
     auto *part = ws_ptr<tfs::Partial>(j, j.off_part);
     auto *res = ws_ptr<tfs::BinResultDev>(j, j.off_res);
 
@@ -593,46 +680,15 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         hip_check(tfs::launch_exp_recur(rp, j.recur_bg, s), "exp recurrence kernel");
         record_kernel(ctx, j, TFSTAT_K_RECUR, s, false);
     } else if (is_exp) {
-        tfs::WeightParams wp{};
-        wp.n_tau = n_tau;
-        wp.n_blocks = j.NB;
-        wp.R = j.R;
-        wp.want64 = j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64;
-        wp.t_sft = at.t_sft;
-        wp.tau = tau;
-        wp.lcol = lcol;
-        wp.lblk = ws_ptr<int32_t>(j, j.off_lblk);
-        wp.blk_off = ws_ptr<int64_t>(j, j.off_boff);
-        wp.g32 = ws_ptr<float>(j, j.off_g32);
-        wp.gsq = ws_ptr<double>(j, j.off_gsq);
-        wp.g64 = wp.want64 ? ws_ptr<double>(j, j.off_g64) : nullptr;
+        tfs::WeightParams wp = weight_params(j);
         record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, true);
         hip_check(tfs::launch_weights(wp, j.max_blk, s), "weights kernel");
         record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, false);
 
-        tfs::ExpValuParams p{};
-        p.at = at.view();
-        p.n_t0 = n_t0;
-        p.n_tau = n_tau;
-        p.n_row_tiles = j.n_row_tiles;
-        p.n_list = j.n_valu;
-        p.n_tiles = j.n_tiles;
-        p.rows = rows;
-        p.tau = tau;
-        p.lcol = lcol;
-        p.lblk = wp.lblk;
-        p.blk_off = wp.blk_off;
-        p.blk_list = ws_ptr<int32_t>(j, j.off_order);
-        p.g32 = wp.g32;
-        p.g64 = wp.g64;
-        p.gsq = wp.gsq;
-        p.twoF = j.twoF;
-        p.part = part;
-        p.abc_out = nullptr;
+        tfs::ExpValuParams p = exp_params(j);
         if (j.n_valu > 0) {
             record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
-            hip_check(tfs::launch_exp_valu(p, (j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64) ? 0 : 1,
-                                           j.R, j.BG, s),
+            hip_check(tfs::launch_exp_valu(p, wants64(j) ? 0 : 1, j.R, j.BG, s),
                       "exp kernel");
             record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
         }
@@ -696,39 +752,20 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         hip_check(tfs::launch_scan(at.x64, 4 * (int64_t)at.n_bins, px, at.K, 4 * at.n_bins, s),
                   "scan kernel");
         record_kernel(ctx, j, TFSTAT_K_SCAN, s, false);
-        tfs::RectParams p{};
-        p.K = at.K;
-        p.n_bins = at.n_bins;
-        p.n_t0 = n_t0;
-        p.n_tau = n_tau;
-        p.t_sft = at.t_sft;
-        p.n_tiles_n = j.n_tiles_n;
-        p.n_tiles = j.n_tiles;
-        p.rows = rows;
-        p.tau = tau;
-        p.pabc = pabc;
-        p.px = px;
-        p.twoF = j.twoF;
-        p.part = part;
+        tfs::RectParams p = rect_params(j);
         record_kernel(ctx, j, TFSTAT_K_RECT, s, true);
         hip_check(tfs::launch_rect(p, s), "rect kernel");
         record_kernel(ctx, j, TFSTAT_K_RECT, s, false);
     }
-    tfs::MergeParams mp{};
-    mp.n_tiles = j.n_tiles;
-    mp.n_maps = at.n_bins;
-    mp.n_cells = (int64_t)n_t0 * n_tau;
-    mp.part = part;
-    mp.out = res;
+    tfs::MergeParams mp = merge_params(j);
     record_kernel(ctx, j, TFSTAT_K_MERGE, s, true);
     hip_check(tfs::launch_merge(mp, s), "merge kernel");
     record_kernel(ctx, j, TFSTAT_K_MERGE, s, false);
     hip_check(hipMemcpyAsync(j.pin, res, res_bytes, hipMemcpyDeviceToHost, s), "download results");
 }
 
-void finish_job(tfstat_ctx *ctx, Job &j, tfstat_bin_result *out) {
-    collect_timing(ctx, j);
-    const auto *r = static_cast<const tfs::BinResultDev *>(j.pin);
+// Per-bin results of a job from the device reduction records r.
+void convert_results(const Job &j, const tfs::BinResultDev *r, tfstat_bin_result *out) {
     const int64_t n_tau = (int64_t)j.win.tau.size();
     for (int b = 0; b < j.at->n_bins; ++b) {
         tfstat_bin_result o{};
@@ -741,6 +778,11 @@ void finish_job(tfstat_ctx *ctx, Job &j, tfstat_bin_result *out) {
         o.tau = j.win.tau[o.n];
         out[b] = o;
     }
+}
+
+void finish_job(tfstat_ctx *ctx, Job &j, tfstat_bin_result *out) {
+    collect_timing(ctx, j);
+    convert_results(j, static_cast<const tfs::BinResultDev *>(j.pin), out);
 }
 
 // bf16 hi / lo planes of the data atoms for the matrix-core path; built
@@ -898,6 +940,324 @@ int guarded(F &&f) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Uneven batch: all maps in one workspace, one shared tile list, one
+// persistent fused launch, replayed as a captured HIP graph.
+// ---------------------------------------------------------------------------
+struct tfstat_batch {
+    int prec = TFSTAT_PREC_FP32;
+    int variant = 0;
+    int groups = 0;
+    std::vector<std::unique_ptr<Job>> jobs;
+    std::vector<int32_t> res_off;   // first result of each map
+    int n_results = 0;
+    int n_tiles = 0;
+    void *ws = nullptr;
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
+    tfs::FusedParams fp{};
+    tfs::WeightBatchParams wbp{};
+    const tfs::ScanJob *scan_jobs = nullptr;
+    int n_scan = 0;
+    tfs::MergeBatchParams mbp{};
+    tfs::BinResultDev *res_dev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;    // around each graph launch
+    hipEvent_t evf0 = nullptr, evf1 = nullptr;  // recorded in the graph around the fused launch
+    double tune_ms = 0.0, last_ms = 0.0, last_fused_ms = 0.0;
+    bool holds_atoms = false;
+};
+
+namespace {
+
+// Tile shape of a map in the mixed variant: the widest bin group its bins fill.
+int mixed_shape(int prec, int n_bins) {
+    if (prec == TFSTAT_PREC_FP64) return tfs::kShapeD41;
+    if (n_bins >= 4) return tfs::kShapeF44;
+    if (n_bins >= 2) return tfs::kShapeF42;
+    return tfs::kShapeF81;
+}
+
+void batch_drop_graph(tfstat_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+void batch_release(tfstat_ctx *ctx, tfstat_batch *b) {
+    batch_drop_graph(b);
+    for (hipEvent_t *e : {&b->ev0, &b->ev1, &b->evf0, &b->evf1}) {
+        if (*e) ctx->events.put(*e);
+        *e = nullptr;
+    }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (b->ws) ctx->arena.release(b->ws);
+    b->ws = nullptr;
+    if (b->pin) ctx->pinned.put(b->pin, b->pin_bytes);
+    b->pin = nullptr;
+    if (b->holds_atoms)
+        for (auto &j : b->jobs) j->at->busy -= 1;
+    b->holds_atoms = false;
+}
+
+struct TileCost {
+    tfs::BatchTile t;
+    double cost;
+};
+
+// Plans every map with the variant's tile shapes, lays out one workspace,
+// uploads every table and descriptor.  The graph is captured separately.
+void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms_id *ids,
+                 const tfstat_window *wins) {
+    const int prec = b->prec;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        for (int32_t i = 0; i < n; ++i) {
+            auto j = std::make_unique<Job>();
+            j->at = find_atoms(ctx, ids[i]);
+            b->jobs.push_back(std::move(j));
+        }
+        for (auto &j : b->jobs) j->at->busy += 1;
+        b->holds_atoms = true;
+    }
+    std::vector<int> shape(n, -1), eidx(n, -1), ridx(n, -1);
+    int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0;
+    int32_t max_chunks = 1;
+    b->res_off.assign(n, 0);
+    b->n_results = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        Job &j = *b->jobs[i];
+        j.win = copy_window(&wins[i]);
+        j.prec = prec;
+        if (j.win.type == TFSTAT_WIN_EXP) {
+            const int sh = b->variant == tfs::kShapeMixed ? mixed_shape(prec, j.at->n_bins) : b->variant;
+            int sp = 0, R = 0, BG = 0;
+            tfs::shape_dims(sh, &sp, &R, &BG);
+            if ((sp == 0) != (prec == TFSTAT_PREC_FP64))
+                raise(TFSTAT_E_INVAL, "tile shape does not match the precision");
+            j.force_R = R;
+            j.force_BG = BG;
+            shape[i] = sh;
+            eidx[i] = n_exp++;
+        } else {
+            ridx[i] = n_rect++;
+        }
+        plan_job(j);
+        if (j.win.type == TFSTAT_WIN_EXP) {
+            n_went += j.NB;
+            max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
+        } else {
+            n_scan += 1 + (4 * j.at->n_bins + 63) / 64;
+        }
+        b->res_off[i] = b->n_results;
+        b->n_results += j.at->n_bins;
+    }
+
+    // shared tile list, largest expected cost first (per-lane FMA counts)
+    std::vector<TileCost> tiles;
+    for (int32_t i = 0; i < n; ++i) {
+        Job &j = *b->jobs[i];
+        if (eidx[i] >= 0) {
+            const int groups = (j.at->n_bins + j.BG - 1) / j.BG;
+            for (int q = 0; q < j.n_valu; ++q) {
+                const double cost = (double)(j.lblk[j.order[q]] + 1) * j.R * (3 + 4 * j.BG);
+                for (int rt = 0; rt < j.n_row_tiles; ++rt)
+                    for (int gidx = 0; gidx < groups; ++gidx)
+                        tiles.push_back({tfs::BatchTile{0, eidx[i], q, rt, gidx, shape[i]}, cost});
+            }
+        } else {
+            const int nby = ((int)j.win.t0.size() + 3) / 4;
+            const int ny = (nby + tfs::kRectRowBlocks - 1) / tfs::kRectRowBlocks;
+            const double cost = 60.0 * tfs::kRectRowBlocks;
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < j.n_tiles_n; ++x)
+                    for (int bin = 0; bin < j.at->n_bins; ++bin)
+                        tiles.push_back({tfs::BatchTile{1, ridx[i], x, y, bin, 0}, cost});
+        }
+    }
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const TileCost &a, const TileCost &c) { return a.cost > c.cost; });
+    if (tiles.size() > (size_t)INT32_MAX / 2) raise(TFSTAT_E_INVAL, "batch has too many tiles");
+    b->n_tiles = (int)tiles.size();
+
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at_ = o;
+        o = round_up(o + std::max<size_t>(bytes, 1), 256);
+        return at_;
+    };
+    std::vector<size_t> job_off(n);
+    for (int32_t i = 0; i < n; ++i) job_off[i] = take(b->jobs[i]->ws_bytes);
+    const size_t desc_begin = o;
+    const size_t off_ep = take(sizeof(tfs::ExpValuParams) * n_exp);
+    const size_t off_rp = take(sizeof(tfs::RectParams) * n_rect);
+    const size_t off_wp = take(sizeof(tfs::WeightParams) * n_exp);
+    const size_t off_wjob = take(sizeof(int32_t) * n_went);
+    const size_t off_wblk = take(sizeof(int32_t) * n_went);
+    const size_t off_scan = take(sizeof(tfs::ScanJob) * n_scan);
+    const size_t off_mp = take(sizeof(tfs::MergeParams) * n);
+    const size_t off_mjob = take(sizeof(int32_t) * b->n_results);
+    const size_t off_mmap = take(sizeof(int32_t) * b->n_results);
+    const size_t off_tiles = take(sizeof(tfs::BatchTile) * tiles.size());
+    const size_t desc_end = o;
+    const size_t off_counter = take(sizeof(int32_t));
+    const size_t off_res = take(sizeof(tfs::BinResultDev) * b->n_results);
+    const size_t ws_bytes = o;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        b->ws = ctx->arena.alloc(ws_bytes);
+    }
+    if (!b->ws) raise(TFSTAT_E_NOMEM, "arena cannot hold the batch workspace");
+    char *ws = static_cast<char *>(b->ws);
+    for (int32_t i = 0; i < n; ++i) b->jobs[i]->ws = ws + job_off[i];
+
+    // host image of every table and descriptor
+    size_t tables_total = 0;
+    for (auto &j : b->jobs) tables_total += round_up(j->tables_bytes, 256);
+    const size_t desc_bytes = desc_end - desc_begin;
+    b->pin = ctx->pinned.get(std::max(tables_total + desc_bytes, sizeof(tfs::BinResultDev) * b->n_results),
+                             &b->pin_bytes);
+    char *h = static_cast<char *>(b->pin);
+    char *hd = h + tables_total;          // descriptors, at ws offset desc_begin
+    auto hptr = [&](size_t off) { return hd + (off - desc_begin); };
+    auto dptr = [&](size_t off) { return ws + off; };
+    auto *ep = reinterpret_cast<tfs::ExpValuParams *>(hptr(off_ep));
+    auto *rp = reinterpret_cast<tfs::RectParams *>(hptr(off_rp));
+    auto *wp = reinterpret_cast<tfs::WeightParams *>(hptr(off_wp));
+    auto *wjob = reinterpret_cast<int32_t *>(hptr(off_wjob));
+    auto *wblk = reinterpret_cast<int32_t *>(hptr(off_wblk));
+    auto *scan = reinterpret_cast<tfs::ScanJob *>(hptr(off_scan));
+    auto *mp = reinterpret_cast<tfs::MergeParams *>(hptr(off_mp));
+    auto *mjob = reinterpret_cast<int32_t *>(hptr(off_mjob));
+    auto *mmap = reinterpret_cast<int32_t *>(hptr(off_mmap));
+    auto *tl = reinterpret_cast<tfs::BatchTile *>(hptr(off_tiles));
+    int we = 0, se = 0, me = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        Job &j = *b->jobs[i];
+        if (eidx[i] >= 0) {
+            ep[eidx[i]] = exp_params(j);
+            wp[eidx[i]] = weight_params(j);
+            for (int nb = 0; nb < j.NB; ++nb) {
+                wjob[we] = eidx[i];
+                wblk[we] = nb;
+                ++we;
+            }
+        } else {
+            rp[ridx[i]] = rect_params(j);
+            double *pabc = ws_ptr<double>(j, j.off_pabc);
+            double *px = ws_ptr<double>(j, j.off_px);
+            scan[se++] = tfs::ScanJob{j.at->abc, pabc, 4, j.at->K, 4, 0, 0};
+            const int32_t C = 4 * j.at->n_bins;
+            for (int c = 0; c < (C + 63) / 64; ++c)
+                scan[se++] = tfs::ScanJob{j.at->x64, px, (int64_t)C, j.at->K, C, c, 0};
+        }
+        mp[i] = merge_params(j);
+        mp[i].out = reinterpret_cast<tfs::BinResultDev *>(dptr(off_res)) + b->res_off[i];
+        for (int bin = 0; bin < j.at->n_bins; ++bin) {
+            mjob[me] = i;
+            mmap[me] = bin;
+            ++me;
+        }
+    }
+    for (size_t t = 0; t < tiles.size(); ++t) tl[t] = tiles[t].t;
+
+    b->fp.exp_jobs = reinterpret_cast<const tfs::ExpValuParams *>(dptr(off_ep));
+    b->fp.rect_jobs = reinterpret_cast<const tfs::RectParams *>(dptr(off_rp));
+    b->fp.tiles = reinterpret_cast<const tfs::BatchTile *>(dptr(off_tiles));
+    b->fp.n_tiles = b->n_tiles;
+    b->fp.counter = reinterpret_cast<int32_t *>(dptr(off_counter));
+    b->wbp.jobs = reinterpret_cast<const tfs::WeightParams *>(dptr(off_wp));
+    b->wbp.job = reinterpret_cast<const int32_t *>(dptr(off_wjob));
+    b->wbp.blk = reinterpret_cast<const int32_t *>(dptr(off_wblk));
+    b->wbp.n_entries = n_went;
+    b->wbp.chunks = max_chunks;
+    b->scan_jobs = reinterpret_cast<const tfs::ScanJob *>(dptr(off_scan));
+    b->n_scan = n_scan;
+    b->mbp.jobs = reinterpret_cast<const tfs::MergeParams *>(dptr(off_mp));
+    b->mbp.job = reinterpret_cast<const int32_t *>(dptr(off_mjob));
+    b->mbp.map = reinterpret_cast<const int32_t *>(dptr(off_mmap));
+    b->mbp.n_entries = b->n_results;
+    b->res_dev = reinterpret_cast<tfs::BinResultDev *>(dptr(off_res));
+
+    hipStream_t s = ctx->batch_stream;
+    size_t ho = 0;
+    for (auto &j : b->jobs) {
+        fill_tables(*j, h + ho);
+        hip_check(hipMemcpyAsync(j->ws, h + ho, j->tables_bytes, hipMemcpyHostToDevice, s), "upload tables");
+        ho += round_up(j->tables_bytes, 256);
+    }
+    hip_check(hipMemcpyAsync(ws + desc_begin, hd, desc_bytes, hipMemcpyHostToDevice, s), "upload descriptors");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (hipEvent_t *e : {&b->ev0, &b->ev1, &b->evf0, &b->evf1})
+        if (!*e) *e = ctx->events.get();
+}
+
+// Captures one run of the batch as a graph: counter reset, weight tables,
+// prefix sums, the persistent fused launch, merges, results to host.
+void batch_capture(tfstat_ctx *ctx, tfstat_batch *b) {
+    batch_drop_graph(b);
+    hipStream_t s = ctx->batch_stream;
+    hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t e = tfs::launch_fill_i32(b->fp.counter, 1, 0, s);
+    if (e == hipSuccess) e = tfs::launch_weights_batch(b->wbp, s);
+    if (e == hipSuccess) e = tfs::launch_scan_batch(b->scan_jobs, b->n_scan, s);
+    if (e == hipSuccess) e = hipEventRecord(b->evf0, s);
+    if (e == hipSuccess) e = tfs::launch_fused(b->fp, b->variant, b->groups, s);
+    if (e == hipSuccess) e = hipEventRecord(b->evf1, s);
+    if (e == hipSuccess) e = tfs::launch_merge_batch(b->mbp, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->pin, b->res_dev, sizeof(tfs::BinResultDev) * b->n_results,
+                           hipMemcpyDeviceToHost, s);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        hip_check(e != hipSuccess ? e : ec, "batch graph capture");
+    }
+    b->graph = g;
+    hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
+void batch_launch(tfstat_ctx *ctx, tfstat_batch *b) {
+    hipStream_t s = ctx->batch_stream;
+    hip_check(hipEventRecord(b->ev0, s), "hipEventRecord");
+    hip_check(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
+    hip_check(hipEventRecord(b->ev1, s), "hipEventRecord");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, b->ev0, b->ev1), "hipEventElapsedTime");
+    b->last_ms = ms;
+    float fms = 0.f;
+    hip_check(hipEventElapsedTime(&fms, b->evf0, b->evf1), "hipEventElapsedTime");
+    b->last_fused_ms = fms;
+}
+
+std::string batch_signature(tfstat_ctx *ctx, int32_t n, const tfstat_atoms_id *ids,
+                            const tfstat_window *wins, int prec) {
+    std::string sig = std::to_string(prec);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    for (int32_t i = 0; i < n; ++i) {
+        const AtomsSet *at = find_atoms(ctx, ids[i]);
+        sig += "|" + std::to_string(wins[i].type) + "," + std::to_string(at->K) + "," +
+               std::to_string(at->n_bins) + "," + std::to_string(wins[i].n_t0) + "," +
+               std::to_string(wins[i].n_tau);
+    }
+    return sig;
+}
+
+void ensure_batch_stream(tfstat_ctx *ctx) {
+    if (ctx->batch_stream) return;
+    hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+    hip_check(hipStreamCreateWithFlags(&ctx->batch_stream, hipStreamNonBlocking), "hipStreamCreate");
+    hip_check(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device),
+              "hipDeviceGetAttribute");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -936,6 +1296,10 @@ int tfstat_ctx_destroy(tfstat_ctx *ctx) {
     if (ctx->worker.joinable()) ctx->worker.join();
     for (int s = 0; s < tfstat_ctx::kSlots; ++s)
         if (ctx->slots[s]) (void)hipStreamDestroy(ctx->slots[s]);
+    if (ctx->batch_stream) {
+        (void)hipStreamSynchronize(ctx->batch_stream);
+        (void)hipStreamDestroy(ctx->batch_stream);
+    }
     (void)hipStreamSynchronize(ctx->stream);
     delete ctx;
     return TFSTAT_OK;
@@ -1226,6 +1590,130 @@ int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t) {
         if (it == ctx->tickets.end()) raise(TFSTAT_E_NOTFOUND, "unknown or retired ticket");
         it->second.cancel_requested = true;
         ctx->cv.notify_all();
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *ids,
+                        const tfstat_window *wins, int32_t precision, int32_t tune,
+                        tfstat_batch **out) {
+    return guarded([&] {
+        if (!ctx || !ids || !wins || !out) raise(TFSTAT_E_INVAL, "null argument");
+        if (n_maps < 1) raise(TFSTAT_E_INVAL, "n_maps must be >= 1");
+        if (precision != TFSTAT_PREC_FP32 && precision != TFSTAT_PREC_FP64)
+            raise(TFSTAT_E_INVAL, "a batch runs in FP32 or FP64");
+        if (tune != 0 && tune != 1) raise(TFSTAT_E_INVAL, "tune must be 0 or 1");
+        ensure_batch_stream(ctx);
+        const std::string sig = batch_signature(ctx, n_maps, ids, wins, precision);
+        const std::vector<int> variants = precision == TFSTAT_PREC_FP64
+                                              ? std::vector<int>{tfs::kShapeD41}
+                                              : std::vector<int>{tfs::kShapeF81, tfs::kShapeF42,
+                                                                 tfs::kShapeF44, tfs::kShapeMixed};
+        double tune_ms = 0.0;
+        int variant = precision == TFSTAT_PREC_FP64 ? tfs::kShapeD41 : tfs::kShapeMixed;
+        int per_cu = 0;
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            auto it = ctx->tuned.find(sig);
+            if (it != ctx->tuned.end()) {
+                variant = it->second.first;
+                per_cu = it->second.second;
+                found = true;
+            }
+        }
+        if (tune == 1 && !found) {
+            // Autotuner: every tile shape x every persistent width that fits;
+            // the fastest of three graph replays after one warm-up counts.
+            const auto t_start = std::chrono::steady_clock::now();
+            double best = 1e300;
+            for (int v : variants) {
+                const int occ = tfs::fused_groups_per_cu(v);
+                if (occ < 1) continue;
+                tfstat_batch cand;
+                cand.prec = precision;
+                cand.variant = v;
+                try {
+                    batch_build(ctx, &cand, n_maps, ids, wins);
+                    for (int g = 1; g <= occ; ++g) {
+                        cand.groups = g * ctx->n_cu;
+                        batch_capture(ctx, &cand);
+                        batch_launch(ctx, &cand);
+                        double t = 1e300;
+                        for (int r = 0; r < 3; ++r) {
+                            batch_launch(ctx, &cand);
+                            t = std::min(t, cand.last_ms);
+                        }
+                        if (t < best) {
+                            best = t;
+                            variant = v;
+                            per_cu = g;
+                        }
+                    }
+                } catch (const Failure &f) {
+                    batch_release(ctx, &cand);
+                    if (f.code != TFSTAT_E_NOMEM) throw;
+                    continue;   // a shape whose tables do not fit is not a candidate
+                }
+                batch_release(ctx, &cand);
+            }
+            if (per_cu < 1) raise(TFSTAT_E_NOMEM, "no tile shape fits the arena");
+            tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+            std::lock_guard<std::mutex> g(ctx->mu);
+            ctx->tuned[sig] = {variant, per_cu};
+        }
+        if (per_cu < 1) per_cu = tfs::fused_groups_per_cu(variant);
+        if (per_cu < 1) raise(TFSTAT_E_DEVICE, "fused kernel does not fit on a CU");
+        auto b = std::make_unique<tfstat_batch>();
+        b->prec = precision;
+        b->variant = variant;
+        b->groups = per_cu * ctx->n_cu;
+        b->tune_ms = tune_ms;
+        try {
+            batch_build(ctx, b.get(), n_maps, ids, wins);
+            batch_capture(ctx, b.get());
+        } catch (...) {
+            batch_release(ctx, b.get());
+            throw;
+        }
+        *out = b.release();
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_batch_run(tfstat_ctx *ctx, tfstat_batch *b, tfstat_bin_result *res_host) {
+    return guarded([&] {
+        if (!ctx || !b || !res_host) raise(TFSTAT_E_INVAL, "null argument");
+        if (!b->exec) raise(TFSTAT_E_INVAL, "batch has no graph");
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        batch_launch(ctx, b);
+        const auto *r = static_cast<const tfs::BinResultDev *>(b->pin);
+        for (size_t i = 0; i < b->jobs.size(); ++i)
+            convert_results(*b->jobs[i], r + b->res_off[i], res_host + b->res_off[i]);
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_batch_stats_read(const tfstat_batch *b, tfstat_batch_stats *out) {
+    return guarded([&] {
+        if (!b || !out) raise(TFSTAT_E_INVAL, "null argument");
+        out->variant = b->variant;
+        out->groups = b->groups;
+        out->n_tiles = b->n_tiles;
+        out->n_results = b->n_results;
+        out->tune_ms = b->tune_ms;
+        out->last_ms = b->last_ms;
+        out->last_fused_ms = b->last_fused_ms;
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_batch_destroy(tfstat_ctx *ctx, tfstat_batch *b) {
+    return guarded([&] {
+        if (!ctx || !b) raise(TFSTAT_E_INVAL, "null argument");
+        if (ctx->batch_stream) (void)hipStreamSynchronize(ctx->batch_stream);
+        batch_release(ctx, b);
+        delete b;
         return (int)TFSTAT_OK;
     });
 }

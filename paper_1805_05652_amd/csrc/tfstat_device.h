@@ -164,6 +164,75 @@ struct MergeParams {
     BinResultDev *out;        // [n_maps]
 };
 
+// ---------------------------------------------------------------------------
+// Uneven batch: many maps (different candidates, grids, bins and window
+// types) in one persistent launch that draws tiles from a shared list.
+// ---------------------------------------------------------------------------
+
+// Tile shapes of the exponential VALU form: (sum type, taus per lane R, bins
+// per group BG).
+enum ExpShape : int32_t {
+    kShapeD41 = 0,   // FP64 sums, R = 4, BG = 1
+    kShapeF81 = 1,   // FP32 F_a/F_b, R = 8, BG = 1
+    kShapeF42 = 2,   // FP32, R = 4, BG = 2
+    kShapeF44 = 3,   // FP32, R = 4, BG = 4
+    kShapeCount = 4,
+    kShapeMixed = 4  // fused-kernel variant: each map keeps its own shape
+};
+inline void shape_dims(int shape, int *prec, int *R, int *BG) {
+    static const int t[4][3] = {{0, 4, 1}, {1, 8, 1}, {1, 4, 2}, {1, 4, 4}};
+    *prec = t[shape][0];
+    *R = t[shape][1];
+    *BG = t[shape][2];
+}
+
+constexpr int kRectRowBlocks = 4;   // 4-row rect blocks per batch tile (16 rows)
+
+struct BatchTile {
+    int32_t kind;    // 0: exponential, 1: rectangular
+    int32_t job;     // index into FusedParams::exp_jobs or ::rect_jobs
+    int32_t x;       // exp: position in blk_list; rect: tau tile (64 taus)
+    int32_t y;       // exp: 64-row tile; rect: first 4-row block / kRectRowBlocks
+    int32_t z;       // exp: bin group; rect: bin
+    int32_t shape;   // exp: ExpShape of the job
+};
+
+struct FusedParams {
+    const ExpValuParams *exp_jobs;
+    const RectParams *rect_jobs;
+    const BatchTile *tiles;   // largest expected cost first
+    int32_t n_tiles;
+    int32_t pad;
+    int32_t *counter;         // next tile; zeroed before every launch
+};
+
+// Weight tables of many maps: entry i is block blk[i] of job job[i].
+struct WeightBatchParams {
+    const WeightParams *jobs;
+    const int32_t *job;
+    const int32_t *blk;
+    int32_t n_entries;
+    int32_t chunks;           // grid.x: 256-element chunks per block
+};
+
+// Compensated prefix sums of many channel sets: entry i scans 64 channels.
+struct ScanJob {
+    const double *in;
+    double *out;
+    int64_t stride;
+    int32_t K, C;
+    int32_t chunk;            // first channel / 64
+    int32_t pad;
+};
+
+struct MergeBatchParams {
+    const MergeParams *jobs;
+    const int32_t *job;       // [n_entries]
+    const int32_t *map;       // [n_entries]
+    int32_t n_entries;
+    int32_t pad;
+};
+
 struct MapReduceParams {
     const float *twoF;        // [n_maps][n_cells]
     int64_t n_cells;
@@ -215,6 +284,15 @@ hipError_t launch_scan(const double *in, int64_t in_row_stride, double *out,
 hipError_t launch_rect(const RectParams &p, hipStream_t s);
 hipError_t launch_merge(const MergeParams &p, hipStream_t s);
 hipError_t launch_map_reduce(const MapReduceParams &p, hipStream_t s);
+hipError_t launch_weights_batch(const WeightBatchParams &p, hipStream_t s);
+hipError_t launch_scan_batch(const ScanJob *jobs, int32_t n_jobs, hipStream_t s);
+hipError_t launch_merge_batch(const MergeBatchParams &p, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *dst, int32_t n, int32_t value, hipStream_t s);
+// variant: an ExpShape (every exp job in the batch has that shape) or
+// kShapeMixed; n_groups workgroups loop over the tile list.
+hipError_t launch_fused(const FusedParams &p, int variant, int n_groups, hipStream_t s);
+// Most workgroups of the fused kernel variant that fit on one CU at once.
+int fused_groups_per_cu(int variant);
 
 // Supported VALU tile shapes: tau columns per block R and bins per lane BG
 // for a precision and bin count.

@@ -49,6 +49,10 @@ int main(void) {
   printf("tfstat_bin_result %zu\n", sizeof(tfstat_bin_result));
   F(tfstat_bin_result, max2F); F(tfstat_bin_result, logB); F(tfstat_bin_result, t0);
   F(tfstat_bin_result, tau); F(tfstat_bin_result, m); F(tfstat_bin_result, n);
+  printf("tfstat_batch_stats %zu\n", sizeof(tfstat_batch_stats));
+  F(tfstat_batch_stats, variant); F(tfstat_batch_stats, groups); F(tfstat_batch_stats, n_tiles);
+  F(tfstat_batch_stats, n_results); F(tfstat_batch_stats, tune_ms); F(tfstat_batch_stats, last_ms);
+  F(tfstat_batch_stats, last_fused_ms);
   return 0;
 }
 ''')
@@ -58,7 +62,7 @@ int main(void) {
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
     py = {"tfstat_window": _abi.Window, "tfstat_atoms_desc": _abi.AtomsDesc,
-          "tfstat_bin_result": _abi.BinResult}
+          "tfstat_bin_result": _abi.BinResult, "tfstat_batch_stats": _abi.BatchStats}
     for key, val in got.items():
         if "." in key:
             s, f = key.split(".")

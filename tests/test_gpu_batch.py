@@ -1,0 +1,178 @@
+"""GPU parity of the uneven batch (tfstat_batch_*): many maps of different
+candidates, grids, bin counts and window types in one captured graph with
+one persistent fused launch.
+
+Each map of a batch is checked two ways:
+  * against the FP64 CPU oracle (per-bin max 2F, argmax, logB) with the
+    tolerances of the single-map tests (2F 1e-4 relative in FP32 and 1e-9 in
+    FP64, logB 1e-3 absolute, argmax exact or a near-tie);
+  * against tfstat_fmap of the same map: the batch's default variant keeps
+    each map's own tile shape, so its results are bit-identical.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tfsynth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-4, "fp64": 1e-9}
+
+
+def _case(msg):
+    print("case:", msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1805_05652_amd as tf
+    c = tf.Context(0, arena_bytes=3 << 30)
+    yield c
+    c.close()
+
+
+def small_candidates(n=8, seed_base=7100):
+    """Uneven candidates at sizes the oracle maps in well under a second."""
+    return [tfsynth.candidate(i, seed_base=seed_base, max_slots=600, max_grid=150, max_bins=6)
+            for i in range(n)]
+
+
+def check_against_oracle(res, atoms, win, tol):
+    ref = oracle.fmap_atoms(atoms, win)
+    mx, am, lb = oracle.reduce(ref)
+    assert len(res) == atoms.n_bins
+    for b, r in enumerate(res):
+        assert abs(r["logB"] - lb[b]) <= 1e-3, (b, r["logB"], lb[b])
+        assert abs(r["max2F"] - mx[b]) <= tol * max(mx[b], 1.0), (b, r["max2F"], mx[b])
+        idx = r["m"] * win.n_tau + r["n"]
+        assert idx == am[b] or ref[b].ravel()[idx] >= (1 - 1e-4) * mx[b], (b, idx, am[b])
+        assert r["t0"] == win.t0[r["m"]] and r["tau"] == win.tau[r["n"]]
+
+
+def same_results(a, b):
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        assert (x["max2F"], x["logB"], x["m"], x["n"]) == (y["max2F"], y["logB"], y["m"], y["n"]), (x, y)
+
+
+def upload_all(ctx, cands):
+    return [ctx.upload_atoms(a) for a, _ in cands]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_small_batch_against_oracle_and_fmap(ctx, prec):
+    _case("small uneven batch " + prec)
+    cands = small_candidates()
+    kinds = {w.kind for _, w in cands}
+    assert kinds == {"rect", "exp"}
+    ids = upload_all(ctx, cands)
+    try:
+        with ctx.batch(list(zip(ids, [w for _, w in cands])), prec) as b:
+            st = b.stats()
+            assert st["variant"] == ("mixed" if prec == "fp32" else "fp64_r4")
+            assert st["n_results"] == sum(a.n_bins for a, _ in cands)
+            got = b.run()
+        for (atoms, win), aid, res in zip(cands, ids, got):
+            check_against_oracle(res, atoms, win, TOL[prec])
+            single, _ = ctx.fmap(aid, win, prec)
+            same_results(res, single)
+    finally:
+        for aid in ids:
+            ctx.free(aid)
+
+
+def test_graph_replays_with_eager_work_between(ctx):
+    """Every replay of the captured graph gives the first run's results, with
+    the library's own eager launches and synchronisations in between."""
+    _case("batch graph replays")
+    cands = small_candidates(6, seed_base=7200)
+    ids = upload_all(ctx, cands)
+    try:
+        with ctx.batch(list(zip(ids, [w for _, w in cands])), "fp32") as b:
+            first = b.run()
+            for rep in range(4):
+                ctx.fmap(ids[rep % len(ids)], cands[rep % len(ids)][1], "fp32")
+                again = b.run()
+                for x, y in zip(first, again):
+                    same_results(x, y)
+    finally:
+        for aid in ids:
+            ctx.free(aid)
+
+
+def test_autotuned_batch(ctx):
+    """The autotuner times every tile shape and width and keeps one; the
+    chosen plan matches the oracle, and a batch of the same shape reuses the
+    choice without tuning again."""
+    _case("autotuned batch")
+    cands = small_candidates(6, seed_base=7300)
+    ids = upload_all(ctx, cands)
+    items = list(zip(ids, [w for _, w in cands]))
+    try:
+        with ctx.batch(items, "fp32", tune=True) as b:
+            st = b.stats()
+            assert st["tune_ms"] > 0.0
+            assert st["variant"] in ("fp32_r8", "fp32_r4_b2", "fp32_r4_b4", "mixed")
+            assert st["groups"] >= 1
+            got = b.run()
+        for (atoms, win), res in zip(cands, got):
+            check_against_oracle(res, atoms, win, TOL["fp32"])
+        with ctx.batch(items, "fp32", tune=True) as b2:
+            st2 = b2.stats()
+            assert st2["tune_ms"] == 0.0
+            assert (st2["variant"], st2["groups"]) == (st["variant"], st["groups"])
+    finally:
+        for aid in ids:
+            ctx.free(aid)
+
+
+def test_batch_holds_atoms_and_rejects_bad_input(ctx):
+    import paper_1805_05652_amd as tf
+    _case("batch errors")
+    cands = small_candidates(2, seed_base=7400)
+    ids = upload_all(ctx, cands)
+    items = list(zip(ids, [w for _, w in cands]))
+    b = ctx.batch(items, "fp32")
+    with pytest.raises(tf.TfstatError) as e:
+        ctx.free(ids[0])
+    assert e.value.code == tf._abi.E_BUSY
+    b.close()
+    with pytest.raises(tf.TfstatError) as e:
+        ctx.batch(items, "bf16x3")
+    assert e.value.code == tf._abi.E_INVAL
+    with pytest.raises(tf.TfstatError) as e:
+        ctx.batch([(987654, cands[0][1])], "fp32")
+    assert e.value.code == tf._abi.E_NOTFOUND
+    for aid in ids:
+        ctx.free(aid)
+
+
+def test_full_uneven_batch_64_candidates():
+    """The 64-candidate uneven batch at full size, in the launch
+    configuration the benchmark times (autotuned): every map equals the
+    single-map path within the FP32 tolerance (bit-identical when the tuner
+    keeps each map's own shape), and the four smallest maps match the oracle."""
+    import paper_1805_05652_amd as tf
+    _case("full uneven batch, 64 candidates")
+    cands = [tfsynth.candidate(i) for i in range(64)]
+    c = tf.Context(0, arena_bytes=16 << 30)
+    try:
+        ids = [c.upload_atoms(a) for a, _ in cands]
+        with c.batch(list(zip(ids, [w for _, w in cands])), "fp32", tune=True) as b:
+            got = b.run()
+            mixed = b.stats()["variant"] == "mixed"
+        for (atoms, win), aid, res in zip(cands, ids, got):
+            single, _ = c.fmap(aid, win, "fp32")
+            if mixed:
+                same_results(res, single)
+            else:
+                for x, y in zip(res, single):
+                    assert abs(x["max2F"] - y["max2F"]) <= 2e-4 * max(y["max2F"], 1.0)
+                    assert abs(x["logB"] - y["logB"]) <= 2e-3
+        size = [w.n_t0 * w.n_tau * a.n_slots * a.n_bins for a, w in cands]
+        for i in np.argsort(size)[:4]:
+            atoms, win = cands[i]
+            check_against_oracle(got[i], atoms, win, TOL["fp32"])
+    finally:
+        c.close()
