@@ -47,6 +47,10 @@ def _load():
     lib.tfo_cell_sums.restype = i32
     lib.tfo_reduce.argtypes = [P, i32, i64, P, P, P]
     lib.tfo_reduce.restype = i32
+    lib.tfo_fmap_shape.argtypes = [P, i32, i64, i64] + lib.tfo_fmap.argtypes[1:]
+    lib.tfo_fmap_shape.restype = i32
+    lib.tfo_cells_shape.argtypes = [P, i32, i64, i64] + lib.tfo_cells.argtypes[1:]
+    lib.tfo_cells_shape.restype = i32
     _lib = lib
     return lib
 
@@ -96,6 +100,45 @@ def fmap(kind, ts, a2, b2, ab, fa, fb, t0, tau, n_threads: int = 0) -> np.ndarra
     rc = lib.tfo_fmap(_kind(kind), ts.shape[0], _ptr(ts), _ptr(a2), _ptr(b2), _ptr(ab),
                       nb, _ptr(fa), _ptr(fb), t0.shape[0], _ptr(t0), tau.shape[0],
                       _ptr(tau), int(n_threads), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments")
+    return out
+
+
+def fmap_shape(shape, support, ts, a2, b2, ab, fa, fb, t0, tau, n_threads: int = 0) -> np.ndarray:
+    """Full 2F map for a general window shape: `shape` holds samples of
+    s(x) evenly spaced over x in [0, num/den], support = (num, den); the window
+    covers [t0, t0 + floor(tau * num / den))."""
+    lib = _load()
+    ts, a2, b2, ab, fa, fb = _atoms_args(ts, a2, b2, ab, fa, fb)
+    t0, tau = _i64(t0), _i64(tau)
+    sh = _f64(shape)
+    nb = fa.shape[0]
+    out = np.empty((nb, t0.shape[0], tau.shape[0]), dtype=np.float64)
+    rc = lib.tfo_fmap_shape(_ptr(sh), sh.shape[0], int(support[0]), int(support[1]),
+                            ts.shape[0], _ptr(ts), _ptr(a2), _ptr(b2), _ptr(ab),
+                            nb, _ptr(fa), _ptr(fb), t0.shape[0], _ptr(t0), tau.shape[0],
+                            _ptr(tau), int(n_threads), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle: invalid arguments")
+    return out
+
+
+def cells_shape(shape, support, ts, a2, b2, ab, fa, fb, t0, tau, m_idx, n_idx,
+                n_threads: int = 0) -> np.ndarray:
+    """2F at selected cells for a general window shape, float64 [n_bins, n_sel]."""
+    lib = _load()
+    ts, a2, b2, ab, fa, fb = _atoms_args(ts, a2, b2, ab, fa, fb)
+    t0, tau = _i64(t0), _i64(tau)
+    sh = _f64(shape)
+    mi = np.ascontiguousarray(m_idx, dtype=np.int32)
+    ni = np.ascontiguousarray(n_idx, dtype=np.int32)
+    nb = fa.shape[0]
+    out = np.empty((nb, mi.shape[0]), dtype=np.float64)
+    rc = lib.tfo_cells_shape(_ptr(sh), sh.shape[0], int(support[0]), int(support[1]),
+                             ts.shape[0], _ptr(ts), _ptr(a2), _ptr(b2), _ptr(ab),
+                             nb, _ptr(fa), _ptr(fb), t0.shape[0], _ptr(t0), tau.shape[0],
+                             _ptr(tau), mi.shape[0], _ptr(mi), _ptr(ni), int(n_threads), _ptr(out))
     if rc != 0:
         raise ValueError("oracle: invalid arguments")
     return out
@@ -153,6 +196,9 @@ def reduce(twoF: np.ndarray):
 
 def fmap_atoms(atoms, win, n_threads: int = 0) -> np.ndarray:
     """Convenience: full map from generator objects (tfsynth.Atoms, Window)."""
+    if win.kind == "shape":
+        return fmap_shape(win.shape, win.support, atoms.timestamps, atoms.a2, atoms.b2, atoms.ab,
+                          atoms.fa, atoms.fb, win.t0, win.tau, n_threads)
     return fmap(win.kind, atoms.timestamps, atoms.a2, atoms.b2, atoms.ab,
                 atoms.fa, atoms.fb, win.t0, win.tau, n_threads)
 

@@ -438,3 +438,88 @@ def test_loud_injection_found():
     res = oracle.results(atoms, win, twoF)[0]
     assert res["max2F"] > 150
     assert abs(res["t0"] - t0) <= 2 * T and abs(res["tau"] - tau) <= 3 * T
+
+
+# ---------------------------------------------------------------------------
+# General window shapes (section 5: other window functions follow the
+# exponential window's setup)
+# ---------------------------------------------------------------------------
+
+def _shape_map(atoms, win):
+    return oracle.fmap_atoms(atoms, win)
+
+
+def test_shape_constant_is_rect():
+    """A constant shape over [0, 1) tau is the rectangular window, exactly."""
+    atoms = tfsynth.make_atoms(41, 60, 0.1, n_bins=2)
+    base = tfsynth.regular_window("rect", -T // 2, T // 3, 70, T - 5, 700, 40)
+    rect = oracle.fmap_atoms(atoms, base)
+    shp = tfsynth.shape_window(base, np.ones(2), (1, 1))
+    assert np.array_equal(_shape_map(atoms, shp), rect)
+
+
+def _shape_brute(atoms, t0, tau, weight_fn, end):
+    ts = atoms.timestamps
+    inside = (ts >= t0) & (ts < end)
+    w = np.where(inside, weight_fn((ts - t0) / tau), 0.0)
+    return w
+
+
+@pytest.mark.parametrize("support,tau", [((2, 1), 3 * T + 7), ((5, 2), 3 * T + 1), ((5, 2), 2 * T)])
+def test_shape_linear_ramp_brute_force(support, tau):
+    """A linear ramp s(x) = 1 - x / S over [0, S) tau, sampled at its ends
+    and midpoint (linear interpolation is exact for it), against numerical
+    maximisation of the likelihood with weights taken from the definition,
+    including the integer window end floor(tau * num / den)."""
+    num, den = support
+    S = num / den
+    atoms = tfsynth.make_atoms(43, 14, 0.0, n_bins=1,
+                               injections=[tfsynth.Injection(0, "rect", 2 * T, 6 * T, 1.2)])
+    base = tfsynth.list_window("rect", np.array([0, T, 2 * T + 300], dtype=np.int64),
+                               np.array([tau], dtype=np.int64))
+    win = tfsynth.shape_window(base, np.array([1.0, 0.5, 0.0]), support)
+    got = _shape_map(atoms, win)
+    for m, t0 in enumerate(base.t0):
+        end = int(t0) + tau * num // den
+        w = _shape_brute(atoms, int(t0), tau, lambda x: 1.0 - x / S, end)
+        if (w > 0).sum() < 2:
+            assert got[0, m, 0] == 0.0
+            continue
+        bf = _brute_force_2F_weights(atoms, 0, w)
+        assert got[0, m, 0] == pytest.approx(bf, rel=1e-6, abs=1e-8)
+
+
+def _brute_force_2F_weights(atoms, bin_, w):
+    fa = atoms.fa[bin_, :, 0] + 1j * atoms.fa[bin_, :, 1]
+    fb = atoms.fb[bin_, :, 0] + 1j * atoms.fb[bin_, :, 1]
+
+    def neg_loglr(p):
+        al = p[0] + 1j * p[1]
+        be = p[2] + 1j * p[3]
+        cross = 2 * w * np.real(np.conj(al) * fa + np.conj(be) * fb)
+        power = w * w * (abs(al) ** 2 * atoms.a2 + abs(be) ** 2 * atoms.b2
+                         + 2 * np.real(np.conj(al) * be) * atoms.ab)
+        return -(cross - power).sum()
+
+    best = None
+    for start in ([0, 0, 0, 0], [1, -1, 0.5, 0.2]):
+        r = optimize.minimize(neg_loglr, np.array(start, float), method="BFGS",
+                              options=dict(gtol=1e-12, maxiter=2000))
+        if best is None or r.fun < best.fun:
+            best = r
+    return -2 * best.fun
+
+
+def test_shape_sampled_exponential_approaches_exp_window():
+    """exp(-x) sampled finely over [0, 3] with support 3: linear
+    interpolation is within h^2/8 of the exponential (h = 1e-4), so the map
+    agrees with the exponential window's to about 1e-8 relative."""
+    atoms = tfsynth.make_atoms(47, 200, 0.1, n_bins=2,
+                               injections=[tfsynth.Injection(0, "exp", 20 * T, 15 * T, 0.8)])
+    base = tfsynth.regular_window("exp", 0, 2 * T, 60, 2 * T, 3 * T + 11, 25)
+    x = np.linspace(0.0, 3.0, 30001)
+    shp = tfsynth.shape_window(base, np.exp(-x), (3, 1))
+    ref = oracle.fmap_atoms(atoms, base)
+    got = _shape_map(atoms, shp)
+    assert np.all((got == 0) == (ref == 0))
+    assert np.max(np.abs(got - ref) / np.maximum(ref, 1.0)) < 1e-6

@@ -87,6 +87,10 @@ class Window:
     # Set when the grid is regular, so callers may pass (min, step, count).
     t0_regular: Optional[tuple] = None
     tau_regular: Optional[tuple] = None
+    # kind "shape": samples of the window shape s(x), x = (t - t0) / tau,
+    # evenly spaced over [0, num/den]; support = (num, den)
+    shape: Optional[np.ndarray] = None
+    support: tuple = (1, 1)
 
     @property
     def n_t0(self) -> int:
@@ -109,6 +113,13 @@ def list_window(kind: str, t0: Sequence[int], tau: Sequence[int]) -> Window:
     t0 = np.asarray(t0, dtype=np.int64)
     tau = np.asarray(tau, dtype=np.int64)
     return Window(kind, t0, tau)
+
+
+def shape_window(base: Window, shape, support=(1, 1)) -> Window:
+    """The grid of `base` with a general window shape: samples of s(x),
+    x = (t - t0) / tau, evenly spaced over [0, num/den], support = (num, den)."""
+    return Window("shape", base.t0, base.tau, base.t0_regular, base.tau_regular,
+                  np.ascontiguousarray(shape, dtype=np.float64), (int(support[0]), int(support[1])))
 
 
 def slot_timestamps(rng: np.random.Generator, n_slots: int, gap_frac: float,
