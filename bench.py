@@ -226,14 +226,17 @@ def bench_batch(args, tf, torch):
     for _ in range(args.warmup):
         batch.run()
     torch.cuda.synchronize()
-    fused = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res = batch.run()
-        fused.append(batch.stats()["last_fused_ms"])
     t1 = time.perf_counter()
     st = batch.stats()
     ms = (t1 - t0) * 1e3 / args.steps
+    # the fused kernel alone, timed with HIP events on its stream (direct launches)
+    fused = []
+    for _ in range(3):
+        timed = batch.run(timed=True)
+        fused.append(batch.stats()["last_fused_ms"])
     # one map per call: the same maps, sequentially, plain launches
     for aid, w in items[:4]:
         ctx.fmap(aid, w, args.prec)
@@ -243,6 +246,7 @@ def bench_batch(args, tf, torch):
     torch.cuda.synchronize()
     seq_ms = (time.perf_counter() - ts) * 1e3
     same = all(r1 == r2 for a, b in zip(res, seq) for r1, r2 in zip(a, b))
+    same = same and timed == res
     fused_ms = float(np.mean(fused))
     # algorithmic flops of the fused kernel: 4 FMA per exp cell*SFT*bin, 3 FP64
     # FMA (A, B, C) per exp cell*SFT, about 30 FP64 flops per rect cell*bin
@@ -284,6 +288,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="exp1bin",
                     choices=["exp1bin", "exp256", "rect", "rect256", "batch"])
     ap.add_argument("--no-tune", action="store_true", help="batch: default tile shapes")
+    ap.add_argument("--no-alternatives", action="store_true",
+                    help="skip timing the recurrence form of the same map")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3", "recur64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-map", action="store_true",
@@ -413,6 +419,18 @@ def main(argv=None):
         "kernels_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in prof.items()},
         "result_bin0": res[0],
     }
+    if win.kind == "exp" and args.prec == "fp32" and not args.no_alternatives:
+        # the same map by the O(1)-per-cell recurrence (all FP64), for context
+        for _ in range(2):
+            ctx.fmap(aid, win, "recur64", out=twoF)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rres, _ = ctx.fmap(aid, win, "recur64", out=twoF)
+        torch.cuda.synchronize()
+        rms = (time.perf_counter() - t0) * 1e3 / args.steps
+        out["alternatives"] = {"recur64": {"ms_per_step": rms, "value": present / (rms * 1e-3),
+                                           "max2F_bin0": rres[0]["max2F"], "logB_bin0": rres[0]["logB"]}}
     ctx.free(aid)
     if args.serve_seconds > 0:
         out["serving"] = serving(ctx, rate_hz=args.serve_rate, duration_s=args.serve_seconds,

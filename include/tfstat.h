@@ -66,7 +66,10 @@ typedef enum {
 
 typedef enum {
     TFSTAT_WIN_RECT = 0,      /* eq. winrect */
-    TFSTAT_WIN_EXP = 1        /* eq. winexp, cut off at 3 tau */
+    TFSTAT_WIN_EXP = 1,       /* eq. winexp, cut off at 3 tau */
+    TFSTAT_WIN_SHAPE = 2      /* any shape s((t - t0)/tau) given as samples (section 5:
+                                 other window functions follow the exponential
+                                 window's kernels); see tfstat_window */
 } tfstat_window_type;
 
 /*
@@ -100,6 +103,17 @@ typedef enum {
  * t0_list[m] when t0_list is non-null, else t0_min + m * dt0 (dt0 >= 1);
  * likewise for tau.  Both sequences must be strictly increasing and every
  * tau must be >= 1; otherwise TFSTAT_E_GRID.
+ *
+ * Shape windows (type TFSTAT_WIN_SHAPE): the weight of an SFT starting at t
+ * is s(x), x = (t - t0) / tau, for t in [t0, t0 + floor(tau * support_num /
+ * support_den)) and 0 elsewhere; s is linear between the n_shape samples
+ * shape[i] = s(i * S / (n_shape - 1)), S = support_num / support_den.  The
+ * sums run through the exponential window's kernels with the samples in
+ * place of the exponential.  Every t0 must sit at the same offset from the
+ * SFT start grid (t0 - t_first = const mod t_sft; e.g. t0 on SFT starts),
+ * else TFSTAT_E_GRID; 2 <= n_shape <= 65536; 1 <= support_num, support_den
+ * <= 1024; tau <= 2^50; samples finite.  RECUR64 does not apply to shapes
+ * (TFSTAT_E_INVAL).  For other types the shape fields are ignored.
  */
 typedef struct {
     int32_t type;             /* tfstat_window_type */
@@ -110,6 +124,10 @@ typedef struct {
     int64_t tau_min, dtau;
     const int64_t *t0_list;   /* optional, [n_t0] host memory */
     const int64_t *tau_list;  /* optional, [n_tau] host memory */
+    const double *shape;      /* shape windows: [n_shape] samples, host memory */
+    int32_t n_shape;
+    int32_t support_num, support_den;
+    int32_t reserved2;        /* must be 0 */
 } tfstat_window;
 
 /*
@@ -241,14 +259,16 @@ int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t);
 typedef struct tfstat_batch tfstat_batch;
 
 typedef struct {
-    int32_t variant;          /* fused-kernel tile shape: 0 FP64 R4, 1 FP32 R8, 2 FP32 R4 x 2 bins,
-                                 3 FP32 R4 x 4 bins, 4 per-map shape by its bin count */
+    int32_t variant;          /* fused-kernel build: tile shape (0 FP64 R4, 1 FP32 R8, 2 FP32 R4 x 2 bins,
+                                 3 FP32 R4 x 4 bins, 4 per-map shape by its bin count), plus 5
+                                 when built for one wave per SIMD fewer than the
+                                 stand-alone kernel (more registers per wave) */
     int32_t groups;           /* persistent workgroups of the fused launch */
     int32_t n_tiles;          /* tiles in the shared list */
     int32_t n_results;        /* sum of n_bins over the maps */
     double tune_ms;           /* host time spent tuning (0 if not tuned here) */
-    double last_ms;           /* device time of the last run (graph, HIP events) */
-    double last_fused_ms;     /* device time of its persistent fused launch */
+    double last_ms;           /* device time of the last run (HIP events) */
+    double last_fused_ms;     /* device time of the fused launch in the last timed run */
 } tfstat_batch_stats;
 
 int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *ids,
@@ -256,8 +276,12 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
                         tfstat_batch **out);
 
 /* Runs the batch (synchronous).  res_host receives n_results entries: the
- * n_bins results of map 0, then those of map 1, and so on. */
-int tfstat_batch_run(tfstat_ctx *ctx, tfstat_batch *b, tfstat_bin_result *res_host);
+ * n_bins results of map 0, then those of map 1, and so on.  timed = 0
+ * replays the captured graph; timed = 1 launches the same steps directly
+ * with HIP events around the persistent fused launch (its time goes to
+ * last_fused_ms; results are identical). */
+int tfstat_batch_run(tfstat_ctx *ctx, tfstat_batch *b, int32_t timed,
+                     tfstat_bin_result *res_host);
 
 int tfstat_batch_stats_read(const tfstat_batch *b, tfstat_batch_stats *out);
 

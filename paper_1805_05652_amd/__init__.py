@@ -21,7 +21,7 @@ from ._abi import TfstatError  # noqa: F401
 
 PRECISIONS = {"fp64": _abi.PREC_FP64, "fp32": _abi.PREC_FP32, "bf16x3": _abi.PREC_BF16X3,
               "recur64": _abi.PREC_RECUR64}
-WINDOWS = {"rect": _abi.WIN_RECT, "exp": _abi.WIN_EXP}
+WINDOWS = {"rect": _abi.WIN_RECT, "exp": _abi.WIN_EXP, "shape": _abi.WIN_SHAPE}
 
 
 def _prec(p) -> int:
@@ -33,9 +33,10 @@ def _prec(p) -> int:
 class _WindowArgs:
     """Keeps the window struct and its backing arrays alive for a call."""
 
-    def __init__(self, kind, t0, tau, t0_regular=None, tau_regular=None):
+    def __init__(self, kind, t0, tau, t0_regular=None, tau_regular=None, shape=None, support=(1, 1)):
         self.t0 = np.ascontiguousarray(t0, dtype=np.int64)
         self.tau = np.ascontiguousarray(tau, dtype=np.int64)
+        self.shape = None if shape is None else np.ascontiguousarray(shape, dtype=np.float64)
         w = _abi.Window()
         w.type = WINDOWS[kind] if isinstance(kind, str) else int(kind)
         w.n_t0 = int(self.t0.shape[0])
@@ -51,12 +52,17 @@ class _WindowArgs:
             w.tau_list = None
         else:
             w.tau_list = self.tau.ctypes.data
+        if self.shape is not None:
+            w.shape = self.shape.ctypes.data
+            w.n_shape = int(self.shape.shape[0])
+            w.support_num, w.support_den = int(support[0]), int(support[1])
         self.struct = w
 
     @classmethod
     def from_window(cls, win):
         return cls(win.kind, win.t0, win.tau, getattr(win, "t0_regular", None),
-                   getattr(win, "tau_regular", None))
+                   getattr(win, "tau_regular", None), getattr(win, "shape", None),
+                   getattr(win, "support", (1, 1)))
 
 
 def _results(arr) -> List[dict]:
@@ -235,10 +241,11 @@ class Batch:
         _abi.check(self._lib.tfstat_batch_create(ctx._ctx, len(items), ids, wins, _prec(precision),
                                                  1 if tune else 0, ctypes.byref(self._h)))
 
-    def run(self) -> List[List[dict]]:
-        """Runs the batch; per map, the list of its per-bin result dicts."""
+    def run(self, timed: bool = False) -> List[List[dict]]:
+        """Runs the batch (graph replay, or direct launches timing the fused
+        kernel when timed); per map, the list of its per-bin result dicts."""
         res = (_abi.BinResult * sum(self._bins))()
-        _abi.check(self._lib.tfstat_batch_run(self._ctx._ctx, self._h, res))
+        _abi.check(self._lib.tfstat_batch_run(self._ctx._ctx, self._h, 1 if timed else 0, res))
         out, o = [], 0
         for nb in self._bins:
             out.append(_results(res[o:o + nb]))

@@ -18,7 +18,7 @@ STATUS_NAMES = {
     -6: "E_NOTFOUND", -7: "E_CANCELLED",
 }
 
-WIN_RECT, WIN_EXP = 0, 1
+WIN_RECT, WIN_EXP, WIN_SHAPE = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_RECUR64 = 0, 1, 2, 3
 
 K_UPLOAD, K_WEIGHTS, K_EXP, K_SCAN, K_RECT, K_MERGE, K_MFMA, K_ABC, K_RECUR = range(9)
@@ -37,6 +37,11 @@ class Window(ctypes.Structure):
         ("dtau", ctypes.c_int64),
         ("t0_list", ctypes.c_void_p),
         ("tau_list", ctypes.c_void_p),
+        ("shape", ctypes.c_void_p),
+        ("n_shape", ctypes.c_int32),
+        ("support_num", ctypes.c_int32),
+        ("support_den", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -78,6 +83,7 @@ class BatchStats(ctypes.Structure):
 
 
 BATCH_VARIANTS = ["fp64_r4", "fp32_r8", "fp32_r4_b2", "fp32_r4_b4", "mixed"]
+BATCH_VARIANTS = BATCH_VARIANTS + [v + "_lowocc" for v in BATCH_VARIANTS]
 
 
 # Every symbol the header declares, with (restype, argtypes).
@@ -99,7 +105,7 @@ SIGNATURES = {
     "tfstat_cancel": (ctypes.c_int, [_P, _U64]),
     "tfstat_batch_create": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_U64), ctypes.POINTER(Window), _I32,
                                            _I32, ctypes.POINTER(_P)]),
-    "tfstat_batch_run": (ctypes.c_int, [_P, _P, ctypes.POINTER(BinResult)]),
+    "tfstat_batch_run": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(BinResult)]),
     "tfstat_batch_stats_read": (ctypes.c_int, [_P, ctypes.POINTER(BatchStats)]),
     "tfstat_batch_destroy": (ctypes.c_int, [_P, _P]),
     "tfstat_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),

@@ -25,9 +25,17 @@ namespace {
 constexpr int kLanes = 64;
 constexpr int kWaves = 4;
 constexpr int kThreads = kLanes * kWaves;
-constexpr int kDC = 256;          // band slots staged per round
-constexpr int kSpreadMax = 256;   // max k0 spread of a 64-row tile for LDS staging
-constexpr int kStage = kSpreadMax + kDC;
+constexpr int kDC = 256;          // band slots staged per round (at most)
+constexpr int kMinDC = 64;        // fewest band slots per round worth staging
+
+// Slots one LDS stage holds: a 64-row tile whose rows span `spread` slots
+// stages spread + dn slots per round, dn = min(kDC, stage - spread) >= kMinDC.
+// The FP32 one-bin shape keeps 4 workgroups per CU (40 KB of LDS each) with
+// a 1008-slot stage.
+template <typename XT, int BG>
+constexpr int stage_len() {
+    return (sizeof(XT) == 4 && BG == 1) ? 1008 : 512;
+}
 
 // ---------------------------------------------------------------------------
 // Reduction state: (F max, sum exp(F - fmax), first index of the max).
@@ -127,10 +135,10 @@ template <typename XT, int R, int BG>
 struct ExpSmem {
     union {
         struct {
-            double a2[kStage];
-            double b2[kStage];
-            double ab[kStage];
-            Q4<XT> x[BG][kStage];
+            double a2[stage_len<XT, BG>()];
+            double b2[stage_len<XT, BG>()];
+            double ab[stage_len<XT, BG>()];
+            Q4<XT> x[BG][stage_len<XT, BG>()];
         } stage;
         struct {
             double abc[1][R][3][kLanes];
@@ -241,10 +249,12 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
     ExpAcc<XT, R, BG, ABC_ONLY> acc;
     acc.zero();
 
-    if (spread <= kSpreadMax) {
+    constexpr int kStageLen = stage_len<XT, BG>();
+    if (spread <= kStageLen - kMinDC) {
         const int my = rp.k0 - k_lo;
-        for (int d0 = 0; d0 < dwg; d0 += kDC) {
-            const int dn = min(kDC, dwg - d0);
+        const int dc = min(kDC, kStageLen - spread);
+        for (int d0 = 0; d0 < dwg; d0 += dc) {
+            const int dn = min(dc, dwg - d0);
             const int width = spread + dn;
             __syncthreads();
             for (int i = tid; i < width; i += kThreads) {
@@ -287,23 +297,42 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
             }
         }
     } else {
-        // Rows too far apart to stage one band: read through the caches.
+        // Rows too far apart to stage one band: each lane reads its own
+        // slots through the caches, kU slots' loads in flight before their
+        // sums (the order of the sums is unchanged).
         const int per = (max(dwg, 0) + kWaves - 1) / kWaves;
         const int ds = wave * per;
         const int de = min(dwg, ds + per);
-        for (int d = ds; d < de; ++d) {
+        auto load_slot = [&](int d, double &a2, double &b2, double &ab, Q4<XT> *x) {
             const int k = rp.k0 + d;
             const int kk = ((unsigned)k < (unsigned)K) ? k : K;   // row K is zero
             const double2 v = *reinterpret_cast<const double2 *>(abc + (size_t)kk * 4);
-            const double ab = abc[(size_t)kk * 4 + 2];
-            Q4<XT> x[BG];
+            a2 = v.x;
+            b2 = v.y;
+            ab = abc[(size_t)kk * 4 + 2];
             if constexpr (!ABC_ONLY) {
 #pragma unroll
                 for (int b = 0; b < BG; ++b)
                     x[b] = (bin0 + b < n_bins) ? load_q4(xg + ((size_t)kk * n_bins + bin0 + b) * 4)
                                                : Q4<XT>{XT(0), XT(0), XT(0), XT(0)};
             }
-            acc.step(gw_base + (size_t)d * R, gq_base + (size_t)d * R, v.x, v.y, ab, x);
+        };
+        constexpr int kU = (BG == 1 && sizeof(XT) == 4) ? 4 : 2;
+        int d = ds;
+        for (; d + kU <= de; d += kU) {
+            double a2[kU], b2[kU], ab[kU];
+            Q4<XT> x[kU][BG];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) load_slot(d + u, a2[u], b2[u], ab[u], x[u]);
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                acc.step(gw_base + (size_t)(d + u) * R, gq_base + (size_t)(d + u) * R, a2[u], b2[u], ab[u], x[u]);
+        }
+        for (; d < de; ++d) {
+            double a2, b2, ab;
+            Q4<XT> x[BG];
+            load_slot(d, a2, b2, ab, x);
+            acc.step(gw_base + (size_t)d * R, gq_base + (size_t)d * R, a2, b2, ab, x);
         }
     }
 
@@ -347,8 +376,9 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
                 f[b][c] = ABC_ONLY ? 0.0 : (double)sm.u.comb.f[0][r][b][c][lane];
         // The table holds the shortest band over all rows of the grid; a row
         // whose band reaches further (smaller delta) adds its last terms
-        // here, in FP64, with weights exp(-d T / tau).
-        const int64_t dend = min(lmn, (int64_t)K - rp.k0);
+        // here, in FP64, with weights exp(-d T / tau).  (Shape windows have
+        // one delta for all rows, hence no such terms.)
+        const int64_t dend = p.scale_rows ? min(lmn, (int64_t)K - rp.k0) : 0;
         for (int64_t d = lc; d < dend; ++d) {
             const int64_t k = (int64_t)rp.k0 + d;
             if (k < 0) continue;
@@ -367,7 +397,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
                 f[b][3] += gd * (double)x.w;
             }
         }
-        if (rp.delta != 0) {
+        if (p.scale_rows && rp.delta != 0) {
             const double s = exp(-(double)rp.delta / (double)tau);
             const double s2 = s * s;
             A *= s2; B *= s2; C *= s2;
@@ -412,8 +442,14 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
     }
 }
 
+// Waves per SIMD each exponential tile shape is built for.
+template <typename XT, int R, int BG, bool ABC_ONLY>
+constexpr int exp_waves() {
+    return ABC_ONLY ? 5 : (sizeof(XT) == 8 ? 5 : (R == 8 ? 4 : (BG == 4 ? 3 : 5)));
+}
+
 template <typename XT, int R, int BG, bool ABC_ONLY = false>
-__global__ __launch_bounds__(kThreads) void exp_valu_kernel(ExpValuParams p) {
+__global__ __launch_bounds__(kThreads, (exp_waves<XT, R, BG, ABC_ONLY>())) void exp_valu_kernel(ExpValuParams p) {
     __shared__ ExpSmem<XT, R, BG> sm;
     // XCD-aware task order: workgroup b runs on XCD b % 8.  Blocks of tau
     // (sorted largest band first) are dealt round-robin to the XCDs and all
@@ -441,8 +477,19 @@ __device__ inline void weights_block(PP &p, int nb, int chunk, int n_chunks) {
         const int r = (int)(i - d * R);
         const int n = nb * R + r;
         double g = 0.0;
-        if (n < p.n_tau && d < p.lcol[n])
-            g = exp(-(double)(d * p.t_sft) / (double)p.tau[n]);
+        if (n < p.n_tau && d < p.lcol[n]) {
+            if (p.shape == nullptr) {
+                g = exp(-(double)(d * p.t_sft) / (double)p.tau[n]);
+            } else {
+                // s(x) at x = (delta + d T) / tau, linear between the samples
+                const double u = ((double)(p.delta + d * p.t_sft) / (double)p.tau[n]) *
+                                 ((double)(p.n_shape - 1) * (double)p.shape_den / (double)p.shape_num);
+                int64_t i = (int64_t)floor(u);
+                i = i < 0 ? 0 : (i > p.n_shape - 2 ? p.n_shape - 2 : i);
+                const double f = u - (double)i;
+                g = p.shape[i] + f * (p.shape[i + 1] - p.shape[i]);
+            }
+        }
         p.g32[off + i] = (float)g;
         p.gsq[off + i] = g * g;
         if (p.want64) p.g64[off + i] = g;
@@ -509,9 +556,20 @@ __device__ __attribute__((always_inline)) inline void scan_chunk(const double *_
     const int kb = min(K, wave * seg);
     const int ke = min(K, kb + seg);
     const size_t row = 2 * (size_t)C;
+    // kSU slots' loads are issued before their (sequential) sums
+    constexpr int kSU = 8;
     DD sum{0.0, 0.0};
-    if (c < C)
-        for (int k = kb; k < ke; ++k) sum = dd_add(sum, in[(size_t)k * stride + c]);
+    if (c < C) {
+        int k = kb;
+        for (; k + kSU <= ke; k += kSU) {
+            double v[kSU];
+#pragma unroll
+            for (int u = 0; u < kSU; ++u) v[u] = in[(size_t)(k + u) * stride + c];
+#pragma unroll
+            for (int u = 0; u < kSU; ++u) sum = dd_add(sum, v[u]);
+        }
+        for (; k < ke; ++k) sum = dd_add(sum, in[(size_t)k * stride + c]);
+    }
     tot[wave][lane] = sum;
     __syncthreads();
     DD run{0.0, 0.0};
@@ -521,7 +579,19 @@ __device__ __attribute__((always_inline)) inline void scan_chunk(const double *_
             out[c] = 0.0;
             out[C + c] = 0.0;
         }
-        for (int k = kb; k < ke; ++k) {
+        int k = kb;
+        for (; k + kSU <= ke; k += kSU) {
+            double v[kSU];
+#pragma unroll
+            for (int u = 0; u < kSU; ++u) v[u] = in[(size_t)(k + u) * stride + c];
+#pragma unroll
+            for (int u = 0; u < kSU; ++u) {
+                run = dd_add(run, v[u]);
+                out[(size_t)(k + u + 1) * row + c] = run.h;
+                out[(size_t)(k + u + 1) * row + C + c] = run.l;
+            }
+        }
+        for (; k < ke; ++k) {
             run = dd_add(run, in[(size_t)k * stride + c]);
             out[(size_t)(k + 1) * row + c] = run.h;
             out[(size_t)(k + 1) * row + C + c] = run.l;
@@ -688,15 +758,16 @@ __device__ __attribute__((always_inline)) inline void fused_exp(PP &p, char *sme
         exp_tile<float, 4, 4>(p, *reinterpret_cast<ExpSmem<float, 4, 4> *>(smem), t.x, t.y, t.z);
 }
 
-// waves per SIMD each variant is built for (those of the stand-alone
-// exponential kernel of the same shape)
-template <int V>
+// Waves per SIMD each variant is built for: those of the stand-alone
+// exponential kernel of the same shape (M = 0), or one fewer, which leaves
+// the compiler more registers per wave (M = 1).
+template <int V, int M>
 constexpr int fused_waves() {
-    return V == kShapeF81 ? 4 : V == kShapeF44 ? 3 : V == kShapeMixed ? 3 : 5;
+    return (V == kShapeF81 ? 4 : V == kShapeF44 ? 3 : V == kShapeMixed ? 3 : 5) - M;
 }
 
-template <int V>
-__global__ __launch_bounds__(kThreads, fused_waves<V>()) void fused_kernel(FusedParams p) {
+template <int V, int M>
+__global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(FusedParams p) {
     __shared__ __attribute__((aligned(16))) char smem[FusedSmem<V>::bytes];
     __shared__ int s_next;
 #pragma unroll 1
@@ -877,19 +948,29 @@ hipError_t launch_fill_i32(int32_t *dst, int32_t n, int32_t value, hipStream_t s
 }
 
 namespace {
-template <int V>
+// variant = shape + kShapeCount1 * M, shape in [0, kShapeMixed], M in {0, 1}
+constexpr int kShapeCount1 = kShapeMixed + 1;
+
+template <int V, int M>
 const void *fused_fn() {
-    return reinterpret_cast<const void *>(&fused_kernel<V>);
+    return reinterpret_cast<const void *>(&fused_kernel<V, M>);
 }
-const void *fused_variant(int v) {
+
+template <int M>
+const void *fused_variant_m(int v) {
     switch (v) {
-    case kShapeD41: return fused_fn<kShapeD41>();
-    case kShapeF81: return fused_fn<kShapeF81>();
-    case kShapeF42: return fused_fn<kShapeF42>();
-    case kShapeF44: return fused_fn<kShapeF44>();
-    case kShapeMixed: return fused_fn<kShapeMixed>();
+    case kShapeD41: return fused_fn<kShapeD41, M>();
+    case kShapeF81: return fused_fn<kShapeF81, M>();
+    case kShapeF42: return fused_fn<kShapeF42, M>();
+    case kShapeF44: return fused_fn<kShapeF44, M>();
+    case kShapeMixed: return fused_fn<kShapeMixed, M>();
     default: return nullptr;
     }
+}
+
+const void *fused_variant(int variant) {
+    if (variant < 0 || variant >= 2 * kShapeCount1) return nullptr;
+    return variant < kShapeCount1 ? fused_variant_m<0>(variant) : fused_variant_m<1>(variant - kShapeCount1);
 }
 }  // namespace
 
@@ -904,15 +985,10 @@ int fused_groups_per_cu(int variant) {
 hipError_t launch_fused(const FusedParams &p, int variant, int n_groups, hipStream_t s) {
     if (p.n_tiles <= 0) return hipSuccess;
     if (n_groups < 1) return hipErrorInvalidValue;
-    switch (variant) {
-    case kShapeD41: hipLaunchKernelGGL(fused_kernel<kShapeD41>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
-    case kShapeF81: hipLaunchKernelGGL(fused_kernel<kShapeF81>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
-    case kShapeF42: hipLaunchKernelGGL(fused_kernel<kShapeF42>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
-    case kShapeF44: hipLaunchKernelGGL(fused_kernel<kShapeF44>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
-    case kShapeMixed: hipLaunchKernelGGL(fused_kernel<kShapeMixed>, dim3(n_groups), dim3(kThreads), 0, s, p); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const void *fn = fused_variant(variant);
+    if (!fn) return hipErrorInvalidValue;
+    void *args[] = {const_cast<FusedParams *>(&p)};
+    return hipLaunchKernel(fn, dim3(n_groups), dim3(kThreads), args, 0, s);
 }
 
 hipError_t launch_map_reduce(const MapReduceParams &p, hipStream_t s) {

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -187,13 +188,18 @@ struct AtomsSet {
 struct WindowOwned {
     int32_t type = 0;
     std::vector<int64_t> t0, tau;
+    std::vector<double> shape;          // shape windows: samples of s(x)
+    int32_t num = 1, den = 1;           // their support [0, num/den] in units of tau
 };
+
+// Banded windows run the exponential window's kernels.
+inline bool banded(int32_t type) { return type == TFSTAT_WIN_EXP || type == TFSTAT_WIN_SHAPE; }
 
 WindowOwned copy_window(const tfstat_window *w) {
     if (!w) raise(TFSTAT_E_INVAL, "window is null");
-    if (w->type != TFSTAT_WIN_RECT && w->type != TFSTAT_WIN_EXP)
+    if (w->type != TFSTAT_WIN_RECT && w->type != TFSTAT_WIN_EXP && w->type != TFSTAT_WIN_SHAPE)
         raise(TFSTAT_E_INVAL, "unknown window type");
-    if (w->reserved != 0) raise(TFSTAT_E_INVAL, "window.reserved must be 0");
+    if (w->reserved != 0 || w->reserved2 != 0) raise(TFSTAT_E_INVAL, "window.reserved fields must be 0");
     if (w->n_t0 < 1 || w->n_tau < 1) raise(TFSTAT_E_GRID, "n_t0 and n_tau must be >= 1");
     WindowOwned o;
     o.type = w->type;
@@ -217,6 +223,19 @@ WindowOwned copy_window(const tfstat_window *w) {
         if (o.tau[i] < 1) raise(TFSTAT_E_GRID, "tau values must be >= 1");
         if (o.tau[i] > ((int64_t)1 << 58)) raise(TFSTAT_E_GRID, "tau too large");
         if (i && o.tau[i] <= o.tau[i - 1]) raise(TFSTAT_E_GRID, "tau grid must be strictly increasing");
+    }
+    if (w->type == TFSTAT_WIN_SHAPE) {
+        if (!w->shape || w->n_shape < 2 || w->n_shape > 65536)
+            raise(TFSTAT_E_INVAL, "shape windows need 2..65536 samples");
+        if (w->support_num < 1 || w->support_num > 1024 || w->support_den < 1 || w->support_den > 1024)
+            raise(TFSTAT_E_INVAL, "shape support num/den must be in 1..1024");
+        o.shape.assign(w->shape, w->shape + w->n_shape);
+        for (double v : o.shape)
+            if (!std::isfinite(v)) raise(TFSTAT_E_INVAL, "shape samples must be finite");
+        o.num = w->support_num;
+        o.den = w->support_den;
+        for (int64_t t : o.tau)
+            if (t > ((int64_t)1 << 50)) raise(TFSTAT_E_GRID, "tau too large for a shape window");
     }
     return o;
 }
@@ -259,7 +278,7 @@ struct Job {
     size_t off_rows = 0, off_tau = 0, off_lcol = 0, off_lblk = 0, off_boff = 0, off_order = 0,
            tables_bytes = 0;
     size_t off_g32 = 0, off_gsq = 0, off_g64 = 0, off_pabc = 0, off_px = 0, off_part = 0,
-           off_res = 0, off_abc = 0, off_lg = 0, off_gshoff = 0, off_gsh = 0;
+           off_res = 0, off_abc = 0, off_lg = 0, off_gshoff = 0, off_gsh = 0, off_shape = 0;
 
     // timing
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timed;
@@ -285,7 +304,14 @@ void plan_job(Job &j) {
         j.rows[m].delta = (int32_t)delta;
         k0_min = std::min(k0_min, k0);
     }
-    const bool is_exp = j.win.type == TFSTAT_WIN_EXP;
+    const bool is_exp = banded(j.win.type);
+    const bool is_shape = j.win.type == TFSTAT_WIN_SHAPE;
+    if (is_shape) {
+        if (j.prec == TFSTAT_PREC_RECUR64) raise(TFSTAT_E_INVAL, "RECUR64 applies to exponential windows only");
+        for (int m = 1; m < n_t0; ++m)
+            if (j.rows[m].delta != j.rows[0].delta)
+                raise(TFSTAT_E_GRID, "shape windows need every t0 at one offset from the SFT start grid");
+    }
     // Table length per tau: the shortest band over all rows (the row with
     // the largest delta), capped where no row can reach data any more.
     // Rows with longer bands add their extra terms in the finalize step.
@@ -294,7 +320,8 @@ void plan_job(Job &j) {
     j.lcol.assign(n_tau, 0);
     const int64_t cap = std::max<int64_t>(0, (int64_t)at.K - k0_min);
     for (int n = 0; n < n_tau; ++n) {
-        const int64_t span = is_exp ? 3 * j.win.tau[n] : j.win.tau[n];
+        const int64_t span = is_shape ? j.win.tau[n] * j.win.num / j.win.den
+                             : (is_exp ? 3 * j.win.tau[n] : j.win.tau[n]);
         const int64_t shortest = span > delta_max ? ceil_div(span - delta_max, T) : 0;
         j.lcol[n] = (int32_t)std::min(shortest, cap);
     }
@@ -302,7 +329,7 @@ void plan_job(Job &j) {
     // Recurrence path: RECUR64 on a regular t0 grid whose step is a whole
     // number of slots (then every row has the same delta).
     j.use_recur = false;
-    if (is_exp && j.prec == TFSTAT_PREC_RECUR64) {
+    if (j.win.type == TFSTAT_WIN_EXP && j.prec == TFSTAT_PREC_RECUR64) {
         bool ok = true;
         int64_t step = n_t0 > 1 ? j.win.t0[1] - j.win.t0[0] : T;
         for (int m = 1; m < n_t0 && ok; ++m) ok = j.win.t0[m] - j.win.t0[m - 1] == step;
@@ -410,6 +437,7 @@ void plan_job(Job &j) {
             j.off_lg = take(sizeof(int32_t) * j.NB);
             j.off_gshoff = take(sizeof(int64_t) * j.NB);
         }
+        if (is_shape) j.off_shape = take(sizeof(double) * j.win.shape.size());
     }
     j.tables_bytes = o;
     if (is_exp && j.use_recur) {
@@ -561,7 +589,9 @@ void fill_tables(const Job &j, char *h) {
     std::memcpy(h + j.off_rows, j.rows.data(), sizeof(tfs::RowPlan) * n_t0);
     std::memcpy(h + j.off_tau, j.win.tau.data(), sizeof(int64_t) * n_tau);
     std::memcpy(h + j.off_lcol, j.lcol.data(), sizeof(int32_t) * n_tau);
-    if (j.win.type == TFSTAT_WIN_EXP && !j.use_recur) {
+    if (banded(j.win.type) && !j.use_recur) {
+        if (j.win.type == TFSTAT_WIN_SHAPE)
+            std::memcpy(h + j.off_shape, j.win.shape.data(), sizeof(double) * j.win.shape.size());
         std::memcpy(h + j.off_lblk, j.lblk.data(), sizeof(int32_t) * j.NB);
         std::memcpy(h + j.off_boff, j.blk_off.data(), sizeof(int64_t) * j.NB);
         std::memcpy(h + j.off_order, j.order.data(), sizeof(int32_t) * j.NB);
@@ -588,6 +618,13 @@ tfs::WeightParams weight_params(Job &j) {
     wp.g32 = ws_ptr<float>(j, j.off_g32);
     wp.gsq = ws_ptr<double>(j, j.off_gsq);
     wp.g64 = wp.want64 ? ws_ptr<double>(j, j.off_g64) : nullptr;
+    if (j.win.type == TFSTAT_WIN_SHAPE) {
+        wp.shape = ws_ptr<double>(j, j.off_shape);
+        wp.n_shape = (int32_t)j.win.shape.size();
+        wp.shape_num = j.win.num;
+        wp.shape_den = j.win.den;
+        wp.delta = j.rows[0].delta;
+    }
     return wp;
 }
 
@@ -611,6 +648,7 @@ tfs::ExpValuParams exp_params(Job &j) {
     p.twoF = j.twoF;
     p.part = ws_ptr<tfs::Partial>(j, j.off_part);
     p.abc_out = nullptr;
+    p.scale_rows = j.win.type == TFSTAT_WIN_EXP ? 1 : 0;
     return p;
 }
 
@@ -648,7 +686,7 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
     const AtomsSet &at = *j.at;
     const int n_t0 = (int)j.win.t0.size();
     const int n_tau = (int)j.win.tau.size();
-    const bool is_exp = j.win.type == TFSTAT_WIN_EXP;
+    const bool is_exp = banded(j.win.type);
     const size_t res_bytes = sizeof(tfs::BinResultDev) * at.n_bins;
     if (!j.pin) j.pin = ctx->pinned.get(std::max(j.tables_bytes, res_bytes), &j.pin_bytes);
     char *h = static_cast<char *>(j.pin);
@@ -714,7 +752,9 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
             q.n_blocks = j.n_mfma;
             q.n_tiles = j.n_tiles;
             q.k0_first = j.rows[0].k0;
-            q.delta = j.rows[0].delta;
+            // the row scale exp(-delta / tau) of exponential windows; shape
+            // windows carry their offset in the tables
+            q.delta = j.win.type == TFSTAT_WIN_EXP ? j.rows[0].delta : 0;
             q.tau = tau;
             q.lblk = wp.lblk;
             q.blk_off = wp.blk_off;
@@ -1030,8 +1070,9 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
         Job &j = *b->jobs[i];
         j.win = copy_window(&wins[i]);
         j.prec = prec;
-        if (j.win.type == TFSTAT_WIN_EXP) {
-            const int sh = b->variant == tfs::kShapeMixed ? mixed_shape(prec, j.at->n_bins) : b->variant;
+        if (banded(j.win.type)) {
+            const int vs = tfs::fused_shape(b->variant);
+            const int sh = vs == tfs::kShapeMixed ? mixed_shape(prec, j.at->n_bins) : vs;
             int sp = 0, R = 0, BG = 0;
             tfs::shape_dims(sh, &sp, &R, &BG);
             if ((sp == 0) != (prec == TFSTAT_PREC_FP64))
@@ -1044,7 +1085,7 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
             ridx[i] = n_rect++;
         }
         plan_job(j);
-        if (j.win.type == TFSTAT_WIN_EXP) {
+        if (banded(j.win.type)) {
             n_went += j.NB;
             max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
         } else {
@@ -1194,22 +1235,29 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
         if (!*e) *e = ctx->events.get();
 }
 
-// Captures one run of the batch as a graph: counter reset, weight tables,
-// prefix sums, the persistent fused launch, merges, results to host.
-void batch_capture(tfstat_ctx *ctx, tfstat_batch *b) {
-    batch_drop_graph(b);
-    hipStream_t s = ctx->batch_stream;
-    hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+// One run of the batch on stream s: counter reset, weight tables, prefix
+// sums, the persistent fused launch (bracketed by evf0/evf1 when timed),
+// merges, results to host.
+hipError_t batch_enqueue(tfstat_batch *b, hipStream_t s, bool timed) {
     hipError_t e = tfs::launch_fill_i32(b->fp.counter, 1, 0, s);
     if (e == hipSuccess) e = tfs::launch_weights_batch(b->wbp, s);
     if (e == hipSuccess) e = tfs::launch_scan_batch(b->scan_jobs, b->n_scan, s);
-    if (e == hipSuccess) e = hipEventRecord(b->evf0, s);
+    if (e == hipSuccess && timed) e = hipEventRecord(b->evf0, s);
     if (e == hipSuccess) e = tfs::launch_fused(b->fp, b->variant, b->groups, s);
-    if (e == hipSuccess) e = hipEventRecord(b->evf1, s);
+    if (e == hipSuccess && timed) e = hipEventRecord(b->evf1, s);
     if (e == hipSuccess) e = tfs::launch_merge_batch(b->mbp, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->pin, b->res_dev, sizeof(tfs::BinResultDev) * b->n_results,
                            hipMemcpyDeviceToHost, s);
+    return e;
+}
+
+// Captures one run of the batch as a graph.
+void batch_capture(tfstat_ctx *ctx, tfstat_batch *b) {
+    batch_drop_graph(b);
+    hipStream_t s = ctx->batch_stream;
+    hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    const hipError_t e = batch_enqueue(b, s, false);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &g);
     if (e != hipSuccess || ec != hipSuccess) {
@@ -1218,6 +1266,21 @@ void batch_capture(tfstat_ctx *ctx, tfstat_batch *b) {
     }
     b->graph = g;
     hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
+// The same run launched directly (not from the graph), timing the fused
+// launch with HIP events.
+void batch_run_timed(tfstat_ctx *ctx, tfstat_batch *b) {
+    hipStream_t s = ctx->batch_stream;
+    hip_check(hipEventRecord(b->ev0, s), "hipEventRecord");
+    hip_check(batch_enqueue(b, s, true), "batch launch");
+    hip_check(hipEventRecord(b->ev1, s), "hipEventRecord");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    float ms = 0.f, fms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, b->ev0, b->ev1), "hipEventElapsedTime");
+    hip_check(hipEventElapsedTime(&fms, b->evf0, b->evf1), "hipEventElapsedTime");
+    b->last_ms = ms;
+    b->last_fused_ms = fms;
 }
 
 void batch_launch(tfstat_ctx *ctx, tfstat_batch *b) {
@@ -1229,9 +1292,6 @@ void batch_launch(tfstat_ctx *ctx, tfstat_batch *b) {
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, b->ev0, b->ev1), "hipEventElapsedTime");
     b->last_ms = ms;
-    float fms = 0.f;
-    hip_check(hipEventElapsedTime(&fms, b->evf0, b->evf1), "hipEventElapsedTime");
-    b->last_fused_ms = fms;
 }
 
 std::string batch_signature(tfstat_ctx *ctx, int32_t n, const tfstat_atoms_id *ids,
@@ -1605,10 +1665,16 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
         if (tune != 0 && tune != 1) raise(TFSTAT_E_INVAL, "tune must be 0 or 1");
         ensure_batch_stream(ctx);
         const std::string sig = batch_signature(ctx, n_maps, ids, wins, precision);
-        const std::vector<int> variants = precision == TFSTAT_PREC_FP64
-                                              ? std::vector<int>{tfs::kShapeD41}
-                                              : std::vector<int>{tfs::kShapeF81, tfs::kShapeF42,
-                                                                 tfs::kShapeF44, tfs::kShapeMixed};
+        std::vector<int> variants;
+        for (int m = 0; m < 2; ++m) {
+            const int base = m * (tfs::kShapeMixed + 1);
+            if (precision == TFSTAT_PREC_FP64) {
+                variants.push_back(base + tfs::kShapeD41);
+            } else {
+                for (int sh : {tfs::kShapeF81, tfs::kShapeF42, tfs::kShapeF44, tfs::kShapeMixed})
+                    variants.push_back(base + sh);
+            }
+        }
         double tune_ms = 0.0;
         int variant = precision == TFSTAT_PREC_FP64 ? tfs::kShapeD41 : tfs::kShapeMixed;
         int per_cu = 0;
@@ -1681,12 +1747,15 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
     });
 }
 
-int tfstat_batch_run(tfstat_ctx *ctx, tfstat_batch *b, tfstat_bin_result *res_host) {
+int tfstat_batch_run(tfstat_ctx *ctx, tfstat_batch *b, int32_t timed, tfstat_bin_result *res_host) {
     return guarded([&] {
         if (!ctx || !b || !res_host) raise(TFSTAT_E_INVAL, "null argument");
         if (!b->exec) raise(TFSTAT_E_INVAL, "batch has no graph");
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
-        batch_launch(ctx, b);
+        if (timed)
+            batch_run_timed(ctx, b);
+        else
+            batch_launch(ctx, b);
         const auto *r = static_cast<const tfs::BinResultDev *>(b->pin);
         for (size_t i = 0; i < b->jobs.size(); ++i)
             convert_results(*b->jobs[i], r + b->res_off[i], res_host + b->res_off[i]);

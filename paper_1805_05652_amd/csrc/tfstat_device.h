@@ -67,7 +67,8 @@ struct ExpValuParams {
     Partial *part;            // [n_bins][n_tiles]
     double *abc_out;          // A/B/C-only mode: [n_t0][abc_pitch][3] (scaled, exact band)
     int32_t abc_pitch;        // cells per row of abc_out (n_tau rounded up to 8)
-    int32_t pad1;
+    int32_t scale_rows;       // 1: exponential window (row scale exp(-delta/tau) and band
+                              // tails); 0: shape window (one delta, tables hold it)
 };
 
 // Exponential-window F_a, F_b on bf16 matrix cores for grids whose t0 rows
@@ -127,6 +128,9 @@ struct RecurParams {
     Partial *part;
 };
 
+// Weight tables [blk][d][R] of a banded window: exponential g[d] =
+// exp(-d T / tau), or a shape window g[d] = s((delta + d T) / tau) with s
+// linear between samples.
 struct WeightParams {
     int32_t n_tau;
     int32_t n_blocks;
@@ -140,6 +144,10 @@ struct WeightParams {
     float *g32;
     double *g64;
     double *gsq;
+    const double *shape;      // null: exponential window
+    int32_t n_shape;
+    int32_t shape_num, shape_den;   // support of the samples: [0, num/den] tau
+    int32_t delta;            // common offset t_{k0} - t0 of the rows (shape windows)
 };
 
 struct RectParams {
@@ -288,8 +296,12 @@ hipError_t launch_weights_batch(const WeightBatchParams &p, hipStream_t s);
 hipError_t launch_scan_batch(const ScanJob *jobs, int32_t n_jobs, hipStream_t s);
 hipError_t launch_merge_batch(const MergeBatchParams &p, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t n, int32_t value, hipStream_t s);
-// variant: an ExpShape (every exp job in the batch has that shape) or
-// kShapeMixed; n_groups workgroups loop over the tile list.
+// variant = shape + (kShapeMixed + 1) * m: shape is an ExpShape (every exp
+// job in the batch has that shape) or kShapeMixed; m = 0 builds for the
+// stand-alone kernel's waves per SIMD, m = 1 for one fewer.  n_groups
+// workgroups loop over the tile list.
+constexpr int kFusedVariants = 2 * (kShapeMixed + 1);
+inline int fused_shape(int variant) { return variant % (kShapeMixed + 1); }
 hipError_t launch_fused(const FusedParams &p, int variant, int n_groups, hipStream_t s);
 // Most workgroups of the fused kernel variant that fit on one CU at once.
 int fused_groups_per_cu(int variant);

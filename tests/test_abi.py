@@ -43,6 +43,8 @@ int main(void) {
   F(tfstat_window, type); F(tfstat_window, n_t0); F(tfstat_window, n_tau);
   F(tfstat_window, t0_min); F(tfstat_window, dt0); F(tfstat_window, tau_min);
   F(tfstat_window, dtau); F(tfstat_window, t0_list); F(tfstat_window, tau_list);
+  F(tfstat_window, shape); F(tfstat_window, n_shape); F(tfstat_window, support_num);
+  F(tfstat_window, support_den); F(tfstat_window, reserved2);
   printf("tfstat_atoms_desc %zu\n", sizeof(tfstat_atoms_desc));
   F(tfstat_atoms_desc, n_sft); F(tfstat_atoms_desc, n_bins); F(tfstat_atoms_desc, t_sft);
   F(tfstat_atoms_desc, timestamps); F(tfstat_atoms_desc, a2); F(tfstat_atoms_desc, fb);

@@ -120,6 +120,17 @@ def test_exp_sparse_rows_read_through_cache(ctx):
     run_and_check(ctx, atoms, win, "fp64")
 
 
+@pytest.mark.parametrize("step,n_bins", [(13, 1), (16, 1), (5, 2), (7, 5)])
+def test_exp_row_spread_staging_limits(ctx, step, n_bins):
+    """64-row tiles spanning 819 and 1008 slots (one bin: staged in shorter
+    rounds, then read through the caches) and 315 and 441 slots (two and five
+    bins: staged in shorter rounds); ragged band ends."""
+    _case("exp row spread step %d bins %d" % (step, n_bins))
+    atoms = tfsynth.make_atoms(311 + step, 1500, 0.1, n_bins=n_bins)
+    win = tfsynth.regular_window("exp", 3 * T + 40, step * T, 100, 2 * T, 9 * T + 17, 40)
+    run_and_check(ctx, atoms, win, "fp32")
+
+
 def test_exp_long_bands_many_chunks(ctx):
     """Bands longer than several LDS chunks and truncated at the data end."""
     _case("exp long bands")
@@ -454,3 +465,65 @@ def test_arena_too_small():
             small.fmap(aid, win, "fp32")
         assert e.value.code == _abi.E_NOMEM
         small.free(aid)
+
+
+# ---------------------------------------------------------------------------
+# General window shapes through the exponential window's kernels
+# ---------------------------------------------------------------------------
+
+def _bump_window(base):
+    # an asymmetric rise-and-decay shape, s(x) = x exp(1 - x) on [0, 4]
+    x = np.linspace(0.0, 4.0, 257)
+    return tfsynth.shape_window(base, x * np.exp(1.0 - x), (4, 1))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16x3"])
+def test_shape_window_against_oracle(ctx, prec):
+    """t0 100 s after each SFT start (one common offset), ragged taus, bins
+    spanning a partial 16-bin column tile for the matrix-core path."""
+    _case("shape window " + prec)
+    n_bins = 19 if prec == "bf16x3" else 3
+    atoms = tfsynth.make_atoms(501, 420, 0.1, n_bins=n_bins,
+                               injections=[tfsynth.Injection(1, "exp", 60 * T, 20 * T, 1.0)])
+    rng = np.random.default_rng(7)
+    tau = np.unique(np.concatenate([[T // 3, 2 * T], rng.integers(2 * T, 120 * T, size=45)]))
+    base = tfsynth.list_window("exp", 100 + T * np.arange(-3, 150, dtype=np.int64), tau)
+    run_and_check(ctx, atoms, _bump_window(base), prec)
+
+
+def test_shape_window_constant_equals_rect(ctx):
+    """A constant shape with support 1 gives the rectangular window's map."""
+    _case("shape constant vs rect")
+    atoms = tfsynth.make_atoms(503, 150, 0.1, n_bins=2)
+    base = tfsynth.regular_window("rect", 0, T, 120, T, 700, 90)
+    aid = ctx.upload_atoms(atoms)
+    try:
+        _, rect = ctx.fmap(aid, base, "fp64", want_map=True)
+        _, shp = ctx.fmap(aid, tfsynth.shape_window(base, np.ones(5), (1, 1)), "fp64", want_map=True)
+        ref = oracle.fmap_atoms(atoms, base)
+        check_map(rect.cpu().numpy(), ref, TOL["fp64"])
+        check_map(shp.cpu().numpy(), ref, TOL["fp64"])
+    finally:
+        ctx.free(aid)
+
+
+def test_shape_window_errors(ctx):
+    import paper_1805_05652_amd as tf
+    _case("shape window errors")
+    atoms = tfsynth.make_atoms(505, 100, 0.0)
+    aid = ctx.upload_atoms(atoms)
+    try:
+        uneven = tfsynth.shape_window(tfsynth.list_window("exp", [0, T + 5], [3 * T]), np.ones(3))
+        with pytest.raises(tf.TfstatError) as e:
+            ctx.fmap(aid, uneven, "fp32")
+        assert e.value.code == tf._abi.E_GRID
+        ok = tfsynth.shape_window(tfsynth.list_window("exp", [0, T], [3 * T]), np.ones(3))
+        with pytest.raises(tf.TfstatError) as e:
+            ctx.fmap(aid, ok, "recur64")
+        assert e.value.code == tf._abi.E_INVAL
+        bad = tfsynth.shape_window(tfsynth.list_window("exp", [0, T], [3 * T]), np.array([1.0, np.nan]))
+        with pytest.raises(tf.TfstatError) as e:
+            ctx.fmap(aid, bad, "fp32")
+        assert e.value.code == tf._abi.E_INVAL
+    finally:
+        ctx.free(aid)
