@@ -205,14 +205,17 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
     const int bin = col_tile * 16 + lrow; // B / C column -> bin
     const bool bin_ok = bin < p.n_bins;
 
-    const unsigned short *bh_base = p.xhi + (size_t)bin * p.kp + 8 * kg;
-    const unsigned short *bl_base = p.xlo + (size_t)bin * p.kp + 8 * kg;
+    // planes [4][kp / 32][bins16][32]: lane's 8 slots of step kb for its bin
+    const unsigned short *bh_base = p.xhi + (size_t)bin * 32 + 8 * kg;
+    const unsigned short *bl_base = p.xlo + (size_t)bin * 32 + 8 * kg;
     const size_t comp_stride = (size_t)p.bins16 * p.kp;
+    const size_t step_stride = (size_t)p.bins16 * 32;
     auto load_b = [&](int kb, u32x4 *h, u32x4 *l) {
+        const size_t so = (size_t)(kb >> 5) * step_stride;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            h[c] = *reinterpret_cast<const u32x4 *>(bh_base + c * comp_stride + kb);
-            l[c] = *reinterpret_cast<const u32x4 *>(bl_base + c * comp_stride + kb);
+            h[c] = *reinterpret_cast<const u32x4 *>(bh_base + c * comp_stride + so);
+            l[c] = *reinterpret_cast<const u32x4 *>(bl_base + c * comp_stride + so);
         }
     };
 
@@ -424,16 +427,21 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
     }
 }
 
-// bf16 hi / lo planes [4][bins16][kp] from the FP32 atoms x32 [K+1][bins][4].
+// bf16 hi / lo planes from the FP32 atoms x32 [K+1][bins][4], laid out
+// [4 components][kp / 32 steps][bins16][32 slots]: the B operand of one K
+// step for 16 bins is one contiguous kilobyte.
 __global__ __launch_bounds__(256) void build_planes_kernel(const float *x32, int32_t K, int32_t n_bins,
                                                            int32_t bins16, int32_t kp,
                                                            unsigned short *xhi, unsigned short *xlo) {
     const int64_t total = (int64_t)4 * bins16 * kp;
+    const int64_t per_c = (int64_t)bins16 * kp;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-        const int64_t k = i % kp;
-        const int64_t cb = i / kp;
-        const int bin = (int)(cb % bins16);
-        const int c = (int)(cb / bins16);
+        const int c = (int)(i / per_c);
+        const int64_t r = i - c * per_c;
+        const int64_t step = r / ((int64_t)bins16 * 32);
+        const int64_t r2 = r - step * bins16 * 32;
+        const int bin = (int)(r2 / 32);
+        const int64_t k = step * 32 + (r2 % 32);
         float x = 0.f;
         if (k < K && bin < n_bins) x = x32[((size_t)k * n_bins + bin) * 4 + c];
         const unsigned int pk = split_pack(x);

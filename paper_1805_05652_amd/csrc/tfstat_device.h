@@ -91,7 +91,7 @@ struct ExpMfmaParams {
     const int32_t *lg;        // [blocks] length of each shifted table
     const int64_t *gsh_off;   // [blocks] element offset of the block's shifted tables
     const unsigned short *gsh;  // shifted bf16 tables [blk][t 8][part 2][shift 8][lg]
-    const unsigned short *xhi, *xlo;  // [4][bins16][kp] bf16 planes
+    const unsigned short *xhi, *xlo;  // bf16 planes [4][kp / 32][bins16][32]
     const double *abc_cell;   // [n_t0][abc_pitch][3]
     int32_t abc_pitch;        // n_tau rounded up to 8 (rows start 16-byte aligned)
     int32_t pad2;
