@@ -142,6 +142,7 @@ __device__ inline void copy16_to_lds(const void *src, void *dst_wave_base) {
 #define TFS_MFMA_APREFETCH 1   // 1: weights read from LDS one K step ahead
 #endif
 
+
 __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaParams p) {
     // two weight windows: flat 16-byte chunks, row (t, part, shift) by row
     // two weight-window buffers as two objects, so that the compiler can see

@@ -273,7 +273,9 @@ hipError_t launch_shift_tables(const ShiftTableParams &p, int64_t max_entries, h
 #define TFS_MFMA_SHIFTS 4        // shifted weight copies: 4 (8-byte reads) or 8 (16-byte reads)
 #endif
 #ifndef TFS_MFMA_TWPAD
-#define TFS_MFMA_TWPAD 80        // window width beyond SK (>= 72, multiple of 8; sets the LDS pitch)
+#define TFS_MFMA_TWPAD 96        // window width beyond SK (>= 72, multiple of 8; sets the LDS pitch:
+                                 // SK + 96 = 352 entries spreads the 64 lanes' reads of the four
+                                 // shifted copies over all 64 LDS banks)
 #endif
 constexpr int kMfmaSK = TFS_MFMA_SK;
 constexpr int kMfmaShifts = TFS_MFMA_SHIFTS;
