@@ -82,6 +82,25 @@ def test_small_batch_against_oracle_and_fmap(ctx, prec):
             ctx.free(aid)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_sparse_row_batch(ctx, prec):
+    """Candidates with few t0 rows over long data (64-row tiles that span
+    more slots than an LDS stage holds) mixed with rect maps."""
+    _case("sparse-row batch " + prec)
+    cands = [tfsynth.candidate(i, seed_base=7600, max_slots=4000, max_grid=120, max_bins=6) for i in range(6)]
+    ids = upload_all(ctx, cands)
+    try:
+        with ctx.batch(list(zip(ids, [w for _, w in cands])), prec) as b:
+            got = b.run()
+        for (atoms, win), aid, res in zip(cands, ids, got):
+            check_against_oracle(res, atoms, win, TOL[prec])
+            single, _ = ctx.fmap(aid, win, prec)
+            same_results(res, single)
+    finally:
+        for aid in ids:
+            ctx.free(aid)
+
+
 def test_graph_replays_with_eager_work_between(ctx):
     """Every replay of the captured graph gives the first run's results, with
     the library's own eager launches and synchronisations in between."""

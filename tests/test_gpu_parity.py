@@ -131,6 +131,20 @@ def test_exp_row_spread_staging_limits(ctx, step, n_bins):
     run_and_check(ctx, atoms, win, "fp32")
 
 
+@pytest.mark.parametrize("prec,n_bins,kind", [("fp32", 1, "exp"), ("fp32", 3, "exp"), ("fp32", 6, "exp"),
+                                              ("fp64", 2, "exp"), ("fp32", 5, "shape")])
+def test_exp_rows_far_apart(ctx, prec, n_bins, kind):
+    """t0 rows 23 slots apart with an offset (a 64-row tile spans 1449 slots,
+    more than an LDS stage holds), ragged row and tau counts, windows past the
+    data end, bins that leave a partial bin group; also a shape window."""
+    _case("exp rows far apart %s %d %s" % (prec, n_bins, kind))
+    atoms = tfsynth.make_atoms(331 + n_bins, 2200, 0.15, n_bins=n_bins,
+                               injections=[tfsynth.Injection(0, "exp", 500 * T, 80 * T, 1.0)])
+    base = tfsynth.regular_window("exp", 7 * T + 300, 23 * T, 90, 2 * T, 11 * T + 13, 130)
+    win = _bump_window(base) if kind == "shape" else base
+    run_and_check(ctx, atoms, win, prec)
+
+
 def test_exp_long_bands_many_chunks(ctx):
     """Bands longer than several LDS chunks and truncated at the data end."""
     _case("exp long bands")
