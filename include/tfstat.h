@@ -234,6 +234,17 @@ int tfstat_poll(tfstat_ctx *ctx, tfstat_ticket t, tfstat_bin_result *res_host,
 int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t);
 
 /*
+ * Serving admission.  Whenever one of the context's stream slots is free,
+ * the requests at the head of the queue are admitted together: up to
+ * max_batch of them (default 16), as many as the arena holds, run as one
+ * batch with one persistent fused launch over all their tiles (FP32 and FP64
+ * requests; matrix-core and recurrence requests run alone).  max_batch = 1
+ * admits one request per slot.  Results never depend on the batching.
+ * Errors: E_INVAL (max_batch outside 1..1024).
+ */
+int tfstat_serve_config(tfstat_ctx *ctx, int32_t max_batch);
+
+/*
  * Uneven batch: many maps -- different resident atoms, grids, numbers of
  * bins and window types -- computed together (the per-map work of section 3,
  * for the many candidates and frequency bins of section 5).  A batch is

@@ -201,6 +201,10 @@ class Context:
     def cancel(self, ticket: int):
         _abi.check(self._lib.tfstat_cancel(self._ctx, ctypes.c_uint64(ticket)))
 
+    def serve_config(self, max_batch: int):
+        """Requests admitted together into one fused batch, at most."""
+        _abi.check(self._lib.tfstat_serve_config(self._ctx, int(max_batch)))
+
     # -- uneven batch ----------------------------------------------------------------
     def batch(self, items, precision="fp32", tune: bool = False) -> "Batch":
         """Plans a batch of maps: items is a sequence of (atoms_id, window)."""

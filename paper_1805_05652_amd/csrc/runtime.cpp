@@ -521,7 +521,10 @@ struct tfstat_ctx {
     std::deque<uint64_t> queue;
     uint64_t next_ticket = 1;
     hipStream_t slots[kSlots] = {nullptr};
-    uint64_t slot_ticket[kSlots] = {0};
+    std::vector<uint64_t> slot_tickets[kSlots];          // requests running on each slot
+    std::unique_ptr<tfstat_batch> slot_batch[kSlots];   // their fused batch, if batched
+    hipEvent_t slot_done[kSlots] = {nullptr};
+    int serve_max_batch = 16;                           // requests fused into one launch at most
     std::thread worker;
     std::condition_variable cv;
     bool stop = false;
@@ -860,110 +863,6 @@ AtomsSet *find_atoms(tfstat_ctx *ctx, tfstat_atoms_id id) {
     return it->second.get();
 }
 
-// ---------------------------------------------------------------------------
-// Serving loop: admits queued requests FIFO as stream slots and arena memory
-// free up, runs them concurrently on the slot streams, completes tickets.
-// ---------------------------------------------------------------------------
-void worker_loop(tfstat_ctx *ctx) {
-    (void)hipSetDevice(ctx->device);
-    std::unique_lock<std::mutex> lk(ctx->mu);
-    while (true) {
-        bool progressed = false;
-        // completions
-        for (int s = 0; s < tfstat_ctx::kSlots; ++s) {
-            const uint64_t id = ctx->slot_ticket[s];
-            if (!id) continue;
-            auto &t = ctx->tickets[id];
-            const hipError_t q = hipEventQuery(t.job->done);
-            if (q == hipErrorNotReady) continue;
-            if (q == hipSuccess) {
-                t.res.resize(t.job->at->n_bins);
-                lk.unlock();
-                finish_job(ctx, *t.job, t.res.data());
-                lk.lock();
-                t.state = t.cancel_requested ? tfstat_ctx::Ticket::CANCELLED : tfstat_ctx::Ticket::DONE;
-            } else {
-                t.state = tfstat_ctx::Ticket::FAILED;
-                t.err = TFSTAT_E_DEVICE;
-                t.msg = std::string("request failed on the device: ") + hipGetErrorString(q);
-            }
-            ctx->events.put(t.job->done);
-            t.job->done = nullptr;
-            t.job->at->busy -= 1;
-            release_job(ctx, *t.job);
-            ctx->slot_ticket[s] = 0;
-            progressed = true;
-        }
-        // admissions
-        while (!ctx->queue.empty()) {
-            int slot = -1;
-            for (int s = 0; s < tfstat_ctx::kSlots; ++s)
-                if (!ctx->slot_ticket[s]) {
-                    slot = s;
-                    break;
-                }
-            if (slot < 0) break;
-            const uint64_t id = ctx->queue.front();
-            auto it = ctx->tickets.find(id);
-            if (it == ctx->tickets.end() || it->second.cancel_requested) {
-                if (it != ctx->tickets.end()) {
-                    it->second.state = tfstat_ctx::Ticket::CANCELLED;
-                    if (it->second.job) it->second.job->at->busy -= 1;
-                }
-                ctx->queue.pop_front();
-                progressed = true;
-                continue;
-            }
-            auto &t = it->second;
-            if (!alloc_job(ctx, *t.job)) break;  // wait for memory
-            ctx->queue.pop_front();
-            try {
-                enqueue_job(ctx, *t.job, ctx->slots[slot]);
-                t.job->done = ctx->events.get();
-                hip_check(hipEventRecord(t.job->done, ctx->slots[slot]), "hipEventRecord");
-                t.state = tfstat_ctx::Ticket::RUNNING;
-                t.slot = slot;
-                ctx->slot_ticket[slot] = id;
-            } catch (const Failure &f) {
-                t.state = tfstat_ctx::Ticket::FAILED;
-                t.err = f.code;
-                t.msg = f.msg;
-                t.job->at->busy -= 1;
-                release_job(ctx, *t.job);
-            }
-            progressed = true;
-        }
-        bool running = false;
-        for (int s = 0; s < tfstat_ctx::kSlots; ++s) running |= ctx->slot_ticket[s] != 0;
-        if (ctx->stop && !running && ctx->queue.empty()) break;
-        if (ctx->stop && !running) {
-            // drain: cancel what never started
-            for (uint64_t id : ctx->queue) {
-                auto it = ctx->tickets.find(id);
-                if (it != ctx->tickets.end()) {
-                    it->second.state = tfstat_ctx::Ticket::CANCELLED;
-                    it->second.job->at->busy -= 1;
-                }
-            }
-            ctx->queue.clear();
-            break;
-        }
-        if (!running && ctx->queue.empty()) {
-            ctx->cv.wait(lk);
-        } else if (!progressed) {
-            ctx->cv.wait_for(lk, std::chrono::microseconds(20));
-        }
-    }
-}
-
-void ensure_worker(tfstat_ctx *ctx) {
-    if (ctx->worker_started) return;
-    for (int s = 0; s < tfstat_ctx::kSlots; ++s)
-        hip_check(hipStreamCreateWithFlags(&ctx->slots[s], hipStreamNonBlocking), "hipStreamCreate");
-    ctx->worker = std::thread(worker_loop, ctx);
-    ctx->worker_started = true;
-}
-
 template <typename F>
 int guarded(F &&f) {
     try {
@@ -987,7 +886,8 @@ struct tfstat_batch {
     int prec = TFSTAT_PREC_FP32;
     int variant = 0;
     int groups = 0;
-    std::vector<std::unique_ptr<Job>> jobs;
+    std::vector<std::unique_ptr<Job>> owned;   // maps planned by the batch itself
+    std::vector<Job *> jobs;                   // every map of the batch, in result order
     std::vector<int32_t> res_off;   // first result of each map
     int n_results = 0;
     int n_tiles = 0;
@@ -1037,7 +937,7 @@ void batch_release(tfstat_ctx *ctx, tfstat_batch *b) {
     if (b->pin) ctx->pinned.put(b->pin, b->pin_bytes);
     b->pin = nullptr;
     if (b->holds_atoms)
-        for (auto &j : b->jobs) j->at->busy -= 1;
+        for (Job *j : b->jobs) j->at->busy -= 1;
     b->holds_atoms = false;
 }
 
@@ -1046,21 +946,21 @@ struct TileCost {
     double cost;
 };
 
-// Plans every map with the variant's tile shapes, lays out one workspace,
-// uploads every table and descriptor.  The graph is captured separately.
-void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms_id *ids,
-                 const tfstat_window *wins) {
-    const int prec = b->prec;
-    {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        for (int32_t i = 0; i < n; ++i) {
-            auto j = std::make_unique<Job>();
-            j->at = find_atoms(ctx, ids[i]);
-            b->jobs.push_back(std::move(j));
-        }
-        for (auto &j : b->jobs) j->at->busy += 1;
-        b->holds_atoms = true;
-    }
+// Tile shape of a planned exponential map (from its precision and R, BG).
+int job_shape(const Job &j) {
+    if (j.prec == TFSTAT_PREC_FP64) return tfs::kShapeD41;
+    if (j.R == 8) return tfs::kShapeF81;
+    return j.BG == 2 ? tfs::kShapeF42 : tfs::kShapeF44;
+}
+
+// Lays out one workspace for the planned maps b->jobs (plain FP32 or FP64
+// exponential maps of the batch's variant, or rectangular maps), builds the
+// shared tile list and every descriptor, and uploads them on stream s (then
+// waits for the stream when sync).  Returns false, with nothing allocated,
+// when the arena cannot hold the workspace.  have_lock: the caller holds
+// ctx->mu.
+bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bool have_lock) {
+    const int32_t n = (int32_t)b->jobs.size();
     std::vector<int> shape(n, -1), eidx(n, -1), ridx(n, -1);
     int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0;
     int32_t max_chunks = 1;
@@ -1068,27 +968,13 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
     b->n_results = 0;
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
-        j.win = copy_window(&wins[i]);
-        j.prec = prec;
         if (banded(j.win.type)) {
-            const int vs = tfs::fused_shape(b->variant);
-            const int sh = vs == tfs::kShapeMixed ? mixed_shape(prec, j.at->n_bins) : vs;
-            int sp = 0, R = 0, BG = 0;
-            tfs::shape_dims(sh, &sp, &R, &BG);
-            if ((sp == 0) != (prec == TFSTAT_PREC_FP64))
-                raise(TFSTAT_E_INVAL, "tile shape does not match the precision");
-            j.force_R = R;
-            j.force_BG = BG;
-            shape[i] = sh;
+            shape[i] = job_shape(j);
             eidx[i] = n_exp++;
-        } else {
-            ridx[i] = n_rect++;
-        }
-        plan_job(j);
-        if (banded(j.win.type)) {
             n_went += j.NB;
             max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
         } else {
+            ridx[i] = n_rect++;
             n_scan += 1 + (4 * j.at->n_bins + 63) / 64;
         }
         b->res_off[i] = b->n_results;
@@ -1146,11 +1032,13 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
     const size_t off_counter = take(sizeof(int32_t));
     const size_t off_res = take(sizeof(tfs::BinResultDev) * b->n_results);
     const size_t ws_bytes = o;
-    {
+    if (have_lock) {
+        b->ws = ctx->arena.alloc(ws_bytes);
+    } else {
         std::lock_guard<std::mutex> g(ctx->mu);
         b->ws = ctx->arena.alloc(ws_bytes);
     }
-    if (!b->ws) raise(TFSTAT_E_NOMEM, "arena cannot hold the batch workspace");
+    if (!b->ws) return false;
     char *ws = static_cast<char *>(b->ws);
     for (int32_t i = 0; i < n; ++i) b->jobs[i]->ws = ws + job_off[i];
 
@@ -1222,7 +1110,6 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
     b->mbp.n_entries = b->n_results;
     b->res_dev = reinterpret_cast<tfs::BinResultDev *>(dptr(off_res));
 
-    hipStream_t s = ctx->batch_stream;
     size_t ho = 0;
     for (auto &j : b->jobs) {
         fill_tables(*j, h + ho);
@@ -1230,9 +1117,47 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
         ho += round_up(j->tables_bytes, 256);
     }
     hip_check(hipMemcpyAsync(ws + desc_begin, hd, desc_bytes, hipMemcpyHostToDevice, s), "upload descriptors");
-    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (sync) hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     for (hipEvent_t *e : {&b->ev0, &b->ev1, &b->evf0, &b->evf1})
         if (!*e) *e = ctx->events.get();
+    return true;
+}
+
+// Plans every map with the variant's tile shapes; then lays the batch out.
+void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms_id *ids,
+                 const tfstat_window *wins) {
+    const int prec = b->prec;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        for (int32_t i = 0; i < n; ++i) {
+            auto j = std::make_unique<Job>();
+            j->at = find_atoms(ctx, ids[i]);
+            b->owned.push_back(std::move(j));
+        }
+        for (auto &j : b->owned) {
+            j->at->busy += 1;
+            b->jobs.push_back(j.get());
+        }
+        b->holds_atoms = true;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        Job &j = *b->jobs[i];
+        j.win = copy_window(&wins[i]);
+        j.prec = prec;
+        if (banded(j.win.type)) {
+            const int vs = tfs::fused_shape(b->variant);
+            const int sh = vs == tfs::kShapeMixed ? mixed_shape(prec, j.at->n_bins) : vs;
+            int sp = 0, R = 0, BG = 0;
+            tfs::shape_dims(sh, &sp, &R, &BG);
+            if ((sp == 0) != (prec == TFSTAT_PREC_FP64))
+                raise(TFSTAT_E_INVAL, "tile shape does not match the precision");
+            j.force_R = R;
+            j.force_BG = BG;
+        }
+        plan_job(j);
+    }
+    if (!batch_layout(ctx, b, ctx->batch_stream, true, false))
+        raise(TFSTAT_E_NOMEM, "arena cannot hold the batch workspace");
 }
 
 // One run of the batch on stream s: counter reset, weight tables, prefix
@@ -1313,6 +1238,204 @@ void ensure_batch_stream(tfstat_ctx *ctx) {
     hip_check(hipStreamCreateWithFlags(&ctx->batch_stream, hipStreamNonBlocking), "hipStreamCreate");
     hip_check(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device),
               "hipDeviceGetAttribute");
+}
+
+// ---------------------------------------------------------------------------
+// Serving loop (continuous batching).  Whenever a stream slot is free, the
+// requests at the head of the queue are admitted together -- up to
+// serve_max_batch of them, as many as the arena can hold -- and run as one
+// fused batch (one persistent launch over all their tiles) on that slot;
+// requests that the fused kernel does not cover (matrix-core and recurrence
+// precisions) run alone.  Up to kSlots admissions are in flight at once, so
+// requests arriving while others run overlap with them on the device.  A
+// request's results do not depend on what it was batched with.
+// ---------------------------------------------------------------------------
+bool fusable(const Job &j) {
+    return (j.prec == TFSTAT_PREC_FP32 || j.prec == TFSTAT_PREC_FP64) && !j.use_mfma && !j.use_recur;
+}
+
+void worker_loop(tfstat_ctx *ctx) {
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    while (true) {
+        bool progressed = false;
+        // completions
+        for (int s = 0; s < tfstat_ctx::kSlots; ++s) {
+            if (ctx->slot_tickets[s].empty()) continue;
+            const hipError_t q = hipEventQuery(ctx->slot_done[s]);
+            if (q == hipErrorNotReady) continue;
+            std::unique_ptr<tfstat_batch> b = std::move(ctx->slot_batch[s]);
+            const std::vector<uint64_t> ids = std::move(ctx->slot_tickets[s]);
+            ctx->slot_tickets[s].clear();
+            for (size_t i = 0; i < ids.size(); ++i) {
+                auto &t = ctx->tickets[ids[i]];
+                if (q == hipSuccess) {
+                    t.res.resize(t.job->at->n_bins);
+                    if (b) {
+                        convert_results(*t.job, static_cast<const tfs::BinResultDev *>(b->pin) + b->res_off[i],
+                                        t.res.data());
+                    } else {
+                        lk.unlock();
+                        finish_job(ctx, *t.job, t.res.data());
+                        lk.lock();
+                    }
+                    t.state = t.cancel_requested ? tfstat_ctx::Ticket::CANCELLED : tfstat_ctx::Ticket::DONE;
+                } else {
+                    t.state = tfstat_ctx::Ticket::FAILED;
+                    t.err = TFSTAT_E_DEVICE;
+                    t.msg = std::string("request failed on the device: ") + hipGetErrorString(q);
+                }
+                t.job->at->busy -= 1;
+                if (b)
+                    t.job->ws = nullptr;   // inside the batch workspace
+                else
+                    release_job(ctx, *t.job);
+            }
+            ctx->events.put(ctx->slot_done[s]);
+            ctx->slot_done[s] = nullptr;
+            if (b) {
+                lk.unlock();
+                batch_release(ctx, b.get());
+                lk.lock();
+            }
+            progressed = true;
+        }
+        // admissions
+        while (!ctx->queue.empty()) {
+            int slot = -1;
+            for (int s = 0; s < tfstat_ctx::kSlots; ++s)
+                if (ctx->slot_tickets[s].empty()) {
+                    slot = s;
+                    break;
+                }
+            if (slot < 0) break;
+            const uint64_t id = ctx->queue.front();
+            auto it = ctx->tickets.find(id);
+            if (it == ctx->tickets.end() || it->second.cancel_requested) {
+                if (it != ctx->tickets.end()) {
+                    it->second.state = tfstat_ctx::Ticket::CANCELLED;
+                    if (it->second.job) it->second.job->at->busy -= 1;
+                }
+                ctx->queue.pop_front();
+                progressed = true;
+                continue;
+            }
+            auto &t = it->second;
+            if (ctx->serve_max_batch > 1 && fusable(*t.job)) {
+                // the longest run of compatible requests at the head of the queue
+                std::vector<uint64_t> ids;
+                for (uint64_t qid : ctx->queue) {
+                    if ((int)ids.size() >= ctx->serve_max_batch) break;
+                    auto qt = ctx->tickets.find(qid);
+                    if (qt == ctx->tickets.end() || qt->second.cancel_requested || !fusable(*qt->second.job) ||
+                        qt->second.job->prec != t.job->prec)
+                        break;
+                    ids.push_back(qid);
+                }
+                auto b = std::make_unique<tfstat_batch>();
+                b->prec = t.job->prec;
+                b->variant = tfs::kShapeMixed;
+                b->groups = std::max(1, tfs::fused_groups_per_cu(tfs::kShapeMixed)) * ctx->n_cu;
+                bool placed = false, popped = false;
+                try {
+                    while (!ids.empty()) {
+                        b->jobs.clear();
+                        for (uint64_t qid : ids) b->jobs.push_back(ctx->tickets[qid].job.get());
+                        if (batch_layout(ctx, b.get(), ctx->slots[slot], false, true)) {
+                            placed = true;
+                            break;
+                        }
+                        ids.pop_back();   // smaller batch
+                    }
+                    if (!placed) break;   // wait for memory
+                    for (size_t i = 0; i < ids.size(); ++i) ctx->queue.pop_front();
+                    popped = true;
+                    hip_check(batch_enqueue(b.get(), ctx->slots[slot], false), "batch launch");
+                    ctx->slot_done[slot] = ctx->events.get();
+                    hip_check(hipEventRecord(ctx->slot_done[slot], ctx->slots[slot]), "hipEventRecord");
+                    for (uint64_t qid : ids) {
+                        auto &qt = ctx->tickets[qid];
+                        qt.state = tfstat_ctx::Ticket::RUNNING;
+                        qt.slot = slot;
+                    }
+                    ctx->slot_tickets[slot] = ids;
+                    ctx->slot_batch[slot] = std::move(b);
+                } catch (const Failure &f) {
+                    // the requests fail; the loop goes on with the rest
+                    if (ids.empty()) ids.push_back(id);
+                    if (!popped)
+                        for (size_t i = 0; i < ids.size() && !ctx->queue.empty(); ++i) ctx->queue.pop_front();
+                    for (uint64_t qid : ids) {
+                        auto &qt = ctx->tickets[qid];
+                        qt.state = tfstat_ctx::Ticket::FAILED;
+                        qt.err = f.code;
+                        qt.msg = f.msg;
+                        qt.job->at->busy -= 1;
+                        qt.job->ws = nullptr;
+                    }
+                    if (ctx->slot_done[slot]) {
+                        ctx->events.put(ctx->slot_done[slot]);
+                        ctx->slot_done[slot] = nullptr;
+                    }
+                    lk.unlock();
+                    batch_release(ctx, b.get());
+                    lk.lock();
+                }
+                progressed = true;
+                continue;
+            }
+            if (!alloc_job(ctx, *t.job)) break;  // wait for memory
+            ctx->queue.pop_front();
+            try {
+                enqueue_job(ctx, *t.job, ctx->slots[slot]);
+                ctx->slot_done[slot] = ctx->events.get();
+                hip_check(hipEventRecord(ctx->slot_done[slot], ctx->slots[slot]), "hipEventRecord");
+                t.state = tfstat_ctx::Ticket::RUNNING;
+                t.slot = slot;
+                ctx->slot_tickets[slot] = {id};
+            } catch (const Failure &f) {
+                t.state = tfstat_ctx::Ticket::FAILED;
+                t.err = f.code;
+                t.msg = f.msg;
+                t.job->at->busy -= 1;
+                release_job(ctx, *t.job);
+                if (ctx->slot_done[slot]) {
+                    ctx->events.put(ctx->slot_done[slot]);
+                    ctx->slot_done[slot] = nullptr;
+                }
+            }
+            progressed = true;
+        }
+        bool running = false;
+        for (int s = 0; s < tfstat_ctx::kSlots; ++s) running |= !ctx->slot_tickets[s].empty();
+        if (ctx->stop && !running && ctx->queue.empty()) break;
+        if (ctx->stop && !running) {
+            // drain: cancel what never started
+            for (uint64_t id : ctx->queue) {
+                auto it = ctx->tickets.find(id);
+                if (it != ctx->tickets.end()) {
+                    it->second.state = tfstat_ctx::Ticket::CANCELLED;
+                    it->second.job->at->busy -= 1;
+                }
+            }
+            ctx->queue.clear();
+            break;
+        }
+        if (!running && ctx->queue.empty()) {
+            ctx->cv.wait(lk);
+        } else if (!progressed) {
+            ctx->cv.wait_for(lk, std::chrono::microseconds(20));
+        }
+    }
+}
+
+void ensure_worker(tfstat_ctx *ctx) {
+    if (ctx->worker_started) return;
+    ensure_batch_stream(ctx);
+    for (int s = 0; s < tfstat_ctx::kSlots; ++s)
+        hip_check(hipStreamCreateWithFlags(&ctx->slots[s], hipStreamNonBlocking), "hipStreamCreate");
+    ctx->worker = std::thread(worker_loop, ctx);
+    ctx->worker_started = true;
 }
 
 }  // namespace
@@ -1783,6 +1906,16 @@ int tfstat_batch_destroy(tfstat_ctx *ctx, tfstat_batch *b) {
         if (ctx->batch_stream) (void)hipStreamSynchronize(ctx->batch_stream);
         batch_release(ctx, b);
         delete b;
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_serve_config(tfstat_ctx *ctx, int32_t max_batch) {
+    return guarded([&] {
+        if (!ctx) raise(TFSTAT_E_INVAL, "ctx is null");
+        if (max_batch < 1 || max_batch > 1024) raise(TFSTAT_E_INVAL, "max_batch must be in 1..1024");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->serve_max_batch = max_batch;
         return (int)TFSTAT_OK;
     });
 }

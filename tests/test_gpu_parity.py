@@ -395,17 +395,23 @@ def test_deterministic_repeat(ctx):
 # Serving: results alone and in a concurrent mix are identical
 # ---------------------------------------------------------------------------
 
-def test_submit_poll_mix_invariance(ctx):
+@pytest.mark.parametrize("max_batch,precs", [(16, ("fp32",)), (1, ("fp32",)), (5, ("fp32", "fp64", "bf16x3"))])
+def test_submit_poll_mix_invariance(ctx, max_batch, precs):
+    """Twelve uneven requests in flight at once give exactly the results of
+    each alone: batched admission (up to 16 or 5 fused), one request per
+    slot, and a mix of precisions of which only some can be fused."""
     import time
-    _case("serving mix")
+    _case("serving mix max_batch %d %s" % (max_batch, precs))
     reqs = []
     for i in range(12):
         atoms, win = tfsynth.candidate(i, max_slots=3000, max_grid=400, max_bins=6)
         reqs.append((atoms, win))
+    prec = [precs[i % len(precs)] for i in range(len(reqs))]
     ids = [ctx.upload_atoms(a) for a, _ in reqs]
+    ctx.serve_config(max_batch)
     try:
-        alone = [ctx.fmap(aid, w, "fp32")[0] for aid, (_, w) in zip(ids, reqs)]
-        tickets = [ctx.submit(aid, w, "fp32") for aid, (_, w) in zip(ids, reqs)]
+        alone = [ctx.fmap(aid, w, p)[0] for aid, (_, w), p in zip(ids, reqs, prec)]
+        tickets = [ctx.submit(aid, w, p) for aid, (_, w), p in zip(ids, reqs, prec)]
         pending = dict(enumerate(tickets))
         got = {}
         t_end = time.time() + 60
@@ -422,8 +428,9 @@ def test_submit_poll_mix_invariance(ctx):
         # spot-check parity of a few against the oracle
         for i in (0, 1):
             atoms, win = reqs[i]
-            check_results(got[i], oracle.fmap_atoms(atoms, win), win, 1e-4)
+            check_results(got[i], oracle.fmap_atoms(atoms, win), win, TOL[prec[i]])
     finally:
+        ctx.serve_config(16)
         for aid in ids:
             ctx.free(aid)
 
