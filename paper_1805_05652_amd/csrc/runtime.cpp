@@ -941,11 +941,6 @@ void batch_release(tfstat_ctx *ctx, tfstat_batch *b) {
     b->holds_atoms = false;
 }
 
-struct TileCost {
-    tfs::BatchTile t;
-    double cost;
-};
-
 // Tile shape of a planned exponential map (from its precision and R, BG).
 int job_shape(const Job &j) {
     if (j.prec == TFSTAT_PREC_FP64) return tfs::kShapeD41;
@@ -981,31 +976,50 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
         b->n_results += j.at->n_bins;
     }
 
-    // shared tile list, largest expected cost first (per-lane FMA counts)
-    std::vector<TileCost> tiles;
+    // shared tile list, largest expected cost first (per-lane FMA counts):
+    // tiles of one (map, tau block) cost the same, so the groups are sorted
+    // and then expanded; rect tiles (all alike and short) go last
+    struct Group {
+        int32_t map, q;
+        double cost;
+    };
+    std::vector<Group> groups_e;
+    size_t n_tiles_total = 0;
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
         if (eidx[i] >= 0) {
-            const int groups = (j.at->n_bins + j.BG - 1) / j.BG;
-            for (int q = 0; q < j.n_valu; ++q) {
-                const double cost = (double)(j.lblk[j.order[q]] + 1) * j.R * (3 + 4 * j.BG);
-                for (int rt = 0; rt < j.n_row_tiles; ++rt)
-                    for (int gidx = 0; gidx < groups; ++gidx)
-                        tiles.push_back({tfs::BatchTile{0, eidx[i], q, rt, gidx, shape[i]}, cost});
-            }
+            const size_t per = (size_t)j.n_row_tiles * ((j.at->n_bins + j.BG - 1) / j.BG);
+            for (int q = 0; q < j.n_valu; ++q)
+                groups_e.push_back({i, q, (double)(j.lblk[j.order[q]] + 1) * j.R * (3 + 4 * j.BG)});
+            n_tiles_total += per * j.n_valu;
         } else {
             const int nby = ((int)j.win.t0.size() + 3) / 4;
             const int ny = (nby + tfs::kRectRowBlocks - 1) / tfs::kRectRowBlocks;
-            const double cost = 60.0 * tfs::kRectRowBlocks;
-            for (int y = 0; y < ny; ++y)
-                for (int x = 0; x < j.n_tiles_n; ++x)
-                    for (int bin = 0; bin < j.at->n_bins; ++bin)
-                        tiles.push_back({tfs::BatchTile{1, ridx[i], x, y, bin, 0}, cost});
+            n_tiles_total += (size_t)ny * j.n_tiles_n * j.at->n_bins;
         }
     }
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const TileCost &a, const TileCost &c) { return a.cost > c.cost; });
-    if (tiles.size() > (size_t)INT32_MAX / 2) raise(TFSTAT_E_INVAL, "batch has too many tiles");
+    if (n_tiles_total > (size_t)INT32_MAX / 2) raise(TFSTAT_E_INVAL, "batch has too many tiles");
+    std::stable_sort(groups_e.begin(), groups_e.end(),
+                     [](const Group &a, const Group &c) { return a.cost > c.cost; });
+    std::vector<tfs::BatchTile> tiles;
+    tiles.reserve(n_tiles_total);
+    for (const Group &g : groups_e) {
+        const Job &j = *b->jobs[g.map];
+        const int bgs = (j.at->n_bins + j.BG - 1) / j.BG;
+        for (int rt = 0; rt < j.n_row_tiles; ++rt)
+            for (int gidx = 0; gidx < bgs; ++gidx)
+                tiles.push_back(tfs::BatchTile{0, eidx[g.map], g.q, rt, gidx, shape[g.map]});
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if (ridx[i] < 0) continue;
+        const Job &j = *b->jobs[i];
+        const int nby = ((int)j.win.t0.size() + 3) / 4;
+        const int ny = (nby + tfs::kRectRowBlocks - 1) / tfs::kRectRowBlocks;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < j.n_tiles_n; ++x)
+                for (int bin = 0; bin < j.at->n_bins; ++bin)
+                    tiles.push_back(tfs::BatchTile{1, ridx[i], x, y, bin, 0});
+    }
     b->n_tiles = (int)tiles.size();
 
     // workspace layout
@@ -1090,7 +1104,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             ++me;
         }
     }
-    for (size_t t = 0; t < tiles.size(); ++t) tl[t] = tiles[t].t;
+    std::memcpy(tl, tiles.data(), sizeof(tfs::BatchTile) * tiles.size());
 
     b->fp.exp_jobs = reinterpret_cast<const tfs::ExpValuParams *>(dptr(off_ep));
     b->fp.rect_jobs = reinterpret_cast<const tfs::RectParams *>(dptr(off_rp));
