@@ -205,6 +205,12 @@ class Context:
         """Requests admitted together into one fused batch, at most."""
         _abi.check(self._lib.tfstat_serve_config(self._ctx, int(max_batch)))
 
+    def tiling_config(self, runs_min_spread: int = -1):
+        """Exponential maps whose 64-row t0 tiles span at least this many
+        slots (median) use the runs form; 0 = every map, -1 = automatic (when
+        the span exceeds the band stage, except one-bin FP32 maps)."""
+        _abi.check(self._lib.tfstat_tiling_config(self._ctx, int(runs_min_spread)))
+
     # -- uneven batch ----------------------------------------------------------------
     def batch(self, items, precision="fp32", tune: bool = False) -> "Batch":
         """Plans a batch of maps: items is a sequence of (atoms_id, window)."""

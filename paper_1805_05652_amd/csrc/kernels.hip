@@ -26,15 +26,15 @@ constexpr int kLanes = 64;
 constexpr int kWaves = 4;
 constexpr int kThreads = kLanes * kWaves;
 constexpr int kDC = 256;          // band slots staged per round (at most)
-constexpr int kMinDC = 64;        // fewest band slots per round worth staging
+constexpr int kMinDC = kExpMinStageRound;   // fewest band slots per round worth staging
 
-// Slots one LDS stage holds: a 64-row tile whose rows span `spread` slots
-// stages spread + dn slots per round, dn = min(kDC, stage - spread) >= kMinDC.
-// The FP32 one-bin shape keeps 4 workgroups per CU (40 KB of LDS each) with
-// a 1008-slot stage.
+// Slots one LDS stage holds (exp_stage_len): a 64-row tile whose rows span
+// `spread` slots stages spread + dn slots per round, dn = min(kDC, stage -
+// spread) >= kMinDC.  The FP32 one-bin shape keeps 4 workgroups per CU
+// (40 KB of LDS each) with a 1008-slot stage.
 template <typename XT, int BG>
 constexpr int stage_len() {
-    return (sizeof(XT) == 4 && BG == 1) ? 1008 : 512;
+    return exp_stage_len(sizeof(XT) == 8 ? 0 : 1, BG);
 }
 
 // ---------------------------------------------------------------------------
@@ -464,6 +464,273 @@ __global__ __launch_bounds__(kThreads, (exp_waves<XT, R, BG, ABC_ONLY>())) void 
 }
 
 // ---------------------------------------------------------------------------
+// Exponential-window sums for t0 rows far apart in slot space ("runs" form).
+//
+// When the 64 rows of a tile start many slots apart, the union of their
+// bands is far wider than one LDS stage, and each staged slot feeds only a
+// few rows.  Here each row gets its own run of kG consecutive slots per
+// round, loaded with coalesced reads into LDS, and the four waves of the
+// workgroup sum four different tau blocks (R taus each, blk_list positions
+// q0 .. q0 + 3) over the same runs, so that every staged slot feeds 4R taus
+// of its row.  The loads of the next round are in flight while the current
+// round is summed.  Each wave sums the whole band of its block (the other
+// form splits it over the four waves) and finalizes the block alone.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename XT, int BG>
+struct RunCfg {
+    static constexpr int kCpb = (int)sizeof(XT) / 4;        // 16-byte chunks per bin and slot
+    static constexpr int kNC = 2 + BG * kCpb;               // chunk arrays: (a2, b2), (ab, 0), data
+    static constexpr int kG = kNC == 3 ? 8 : 4;             // slots per run and round (LDS: 24 or 16-24 KB)
+    static constexpr int kSh = kG == 8 ? 1 : 2;             // LDS swizzle: rows per rotation step
+    static constexpr int kPer = kLanes * kG * kNC / kThreads;   // chunks each thread loads per round
+    static_assert(kLanes * kG * kNC % kThreads == 0, "whole chunks per thread");
+    static_assert(kThreads % kG == 0, "a thread keeps its slot within the run");
+};
+
+// One round: the runs (16-byte chunks) and each wave's weights g[d][r],
+// g^2[d][r] for the round's kG slots, so that every operand of the sums is
+// read from LDS (in-order completion lets the loads of one step overlap the
+// products of the previous one).
+template <typename XT, int R, int BG>
+struct RunSmem {
+    u32x4 c[RunCfg<XT, BG>::kNC][kLanes * RunCfg<XT, BG>::kG];
+    XT g[kWaves][RunCfg<XT, BG>::kG][R] __attribute__((aligned(16)));
+    double q[kWaves][RunCfg<XT, BG>::kG][R] __attribute__((aligned(16)));
+};
+
+// Element of row r, slot j of a run: rows of kG elements, rotated by r >> kSh
+// so that the 16 lanes of a quarter wave reading one slot hit 16 distinct
+// 16-byte bank groups.
+template <typename XT, int BG>
+__device__ inline int run_index(int r, int j) {
+    using C = RunCfg<XT, BG>;
+    return r * C::kG + ((j + (r >> C::kSh)) & (C::kG - 1));
+}
+
+template <typename XT, int R, int BG, typename PP>
+__device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSmem<XT, R, BG> &sm, int q0,
+                                                                    int row_tile, int bin_group) {
+    using C = RunCfg<XT, BG>;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kLanes - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int bin0 = bin_group * BG;
+    const int n_bins = p.at.n_bins;
+    const int K = p.at.K;
+    const int m_first = row_tile * kLanes;
+    const int k_lo = p.rows[m_first].k0;
+
+    // this wave's block; the workgroup's band is the longest of its blocks
+    const int q = q0 + wave;
+    const bool has_blk = q < p.n_list;
+    const int nb = has_blk ? p.blk_list[q] : p.blk_list[q0];
+    const int kmax = K - k_lo;
+    const int dw = has_blk ? max(min(p.lblk[nb], kmax), 0) : 0;
+    int dall = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w)
+        if (q0 + w < p.n_list) dall = max(dall, min(p.lblk[p.blk_list[q0 + w]], kmax));
+    const int64_t off = p.blk_off[nb];
+    const XT *__restrict__ gw_base = wplane<XT>(p) + off;
+    const double *__restrict__ gq_base = p.gsq + off;
+    const XT *__restrict__ xg = xplane<XT>(p);
+    const double *__restrict__ abc = p.at.abc;
+
+    // This thread always loads slot js of its runs, for row rr and, with
+    // kG = 8, row rr + 32: chunk i of a round is array i / kRep, row
+    // rr + (i % kRep) * (kThreads / kG).
+    constexpr int kRep = kLanes * C::kG / kThreads;
+    const int js = tid % C::kG;
+    const int rr = tid / C::kG;
+    int kr[kRep];
+    int sidx[kRep];
+#pragma unroll
+    for (int h = 0; h < kRep; ++h) {
+        const int r = rr + h * (kThreads / C::kG);
+        kr[h] = p.rows[min(m_first + r, p.n_t0 - 1)].k0 + js;
+        sidx[h] = run_index<XT, BG>(r, js);
+    }
+    u32x4 buf[C::kPer];
+    // chunk sources of one round: slot k of array a (k outside the data
+    // reads row K, which is zero)
+#define TFS_RUNS_LOAD(D0)                                                                       \
+    _Pragma("unroll") for (int i = 0; i < C::kPer; ++i) {                                       \
+        const int a = i / kRep;                                                                 \
+        int k = kr[i % kRep] + (D0);                                                            \
+        if ((unsigned)k >= (unsigned)K) k = K;                                                  \
+        if (a < 2) {                                                                            \
+            buf[i] = *reinterpret_cast<const u32x4 *>(abc + (size_t)k * 4 + 2 * a);            \
+        } else {                                                                                \
+            const int b = (a - 2) / C::kCpb;                                                    \
+            const bool bin_ok = bin0 + b < n_bins;                                              \
+            const size_t e = ((size_t)(bin_ok ? k : K) * n_bins + (bin_ok ? bin0 + b : 0)) * 4; \
+            buf[i] = reinterpret_cast<const u32x4 *>(xg + e)[(a - 2) % C::kCpb];                \
+        }                                                                                       \
+    }
+
+    // The wave's weights of one round: lane l < kWc copies one 16-byte chunk
+    // of rows d0 .. d0 + kG - 1 of its block's tables (rows past the band
+    // repeat the last one; a wave without rows copies the zero atom row).
+    constexpr int kCg = R * (int)sizeof(XT) / 16;    // chunks per g row
+    constexpr int kCq = R * 8 / 16;                  // chunks per g^2 row
+    constexpr int kWc = C::kG * (kCg + kCq);
+    static_assert(kWc <= kLanes && R * sizeof(XT) % 16 == 0, "one weight chunk per lane");
+    const int lb = has_blk ? p.lblk[nb] : 0;
+    const bool wl = lane < kWc;
+    const int wj = lane < C::kG * kCg ? lane / kCg : (lane - C::kG * kCg) / kCq;
+    const int wc = lane < C::kG * kCg ? lane % kCg : (lane - C::kG * kCg) % kCq;
+    u32x4 *const wdst = lane < C::kG * kCg ? reinterpret_cast<u32x4 *>(&sm.g[wave][wj][0]) + wc
+                                           : reinterpret_cast<u32x4 *>(&sm.q[wave][wj][0]) + wc;
+    u32x4 wbuf;
+#define TFS_RUNS_WLOAD(D0)                                                                      \
+    {                                                                                           \
+        const int d = min((D0) + wj, lb - 1);                                                   \
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(abc + (size_t)K * 4);               \
+        if (wl && d >= 0)                                                                       \
+            src = lane < C::kG * kCg ? reinterpret_cast<const u32x4 *>(gw_base + (size_t)d * R) + wc \
+                                     : reinterpret_cast<const u32x4 *>(gq_base + (size_t)d * R) + wc; \
+        wbuf = *src;                                                                            \
+    }
+
+    ExpAcc<XT, R, BG> acc;
+    acc.zero();
+    TFS_RUNS_LOAD(0)
+    TFS_RUNS_WLOAD(0)
+#pragma unroll 1
+    for (int d0 = 0; d0 < dall; d0 += C::kG) {
+        __syncthreads();   // every wave is done with the previous round
+        auto &cur = sm.c;
+#pragma unroll
+        for (int i = 0; i < C::kPer; ++i) cur[i / kRep][sidx[i % kRep]] = buf[i];
+        if (wl) *wdst = wbuf;
+        __syncthreads();
+        // next round (past the band this reads zero rows or unused slots;
+        // an unconditional load keeps buf in registers)
+        TFS_RUNS_LOAD(d0 + C::kG)
+        TFS_RUNS_WLOAD(d0 + C::kG)
+        const int jn = min(C::kG, dw - d0);
+#pragma unroll 2
+        for (int j = 0; j < jn; ++j) {
+            const int e = run_index<XT, BG>(lane, j);
+            const double2 v = *reinterpret_cast<const double2 *>(&cur[0][e]);
+            const double ab = *reinterpret_cast<const double *>(&cur[1][e]);
+            Q4<XT> x[BG];
+#pragma unroll
+            for (int b = 0; b < BG; ++b) {
+                if constexpr (sizeof(XT) == 4) {
+                    const u32x4 u = cur[2 + b][e];
+                    x[b] = Q4<XT>{__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z),
+                                  __uint_as_float(u.w)};
+                } else {
+                    const double2 lo = *reinterpret_cast<const double2 *>(&cur[2 + 2 * b][e]);
+                    const double2 hi = *reinterpret_cast<const double2 *>(&cur[3 + 2 * b][e]);
+                    x[b] = Q4<XT>{lo.x, lo.y, hi.x, hi.y};
+                }
+            }
+            acc.step(&sm.g[wave][j][0], &sm.q[wave][j][0], v.x, v.y, ab, x);
+        }
+    }
+#undef TFS_RUNS_LOAD
+#undef TFS_RUNS_WLOAD
+    if (!has_blk) return;
+
+    // Finalize the wave's block: exact band end, row scale, D, 2F, map,
+    // reductions (as in exp_tile).
+    const bool row_ok = m_first + lane < p.n_t0;
+    const int m = min(m_first + lane, p.n_t0 - 1);
+    const RowPlan rp = p.rows[m];
+    const int64_t T = p.at.t_sft;
+    Red red[BG];
+#pragma unroll
+    for (int b = 0; b < BG; ++b) red[b] = red_empty();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int n = nb * R + r;
+        const bool ok = row_ok && n < p.n_tau;
+        const int nn = min(n, p.n_tau - 1);
+        const int64_t tau = p.tau[nn];
+        const int64_t span = 3 * tau;
+        const int64_t lmn = span > rp.delta ? (span - rp.delta + T - 1) / T : 0;
+        const int lc = p.lcol[nn];
+        double A = acc.A[r], B = acc.B[r], Cc = acc.C[r];
+        double f[BG][4];
+#pragma unroll
+        for (int b = 0; b < BG; ++b)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) f[b][c] = (double)acc.f[r][b][c];
+        const int64_t dend = p.scale_rows ? min(lmn, (int64_t)K - rp.k0) : 0;
+        for (int64_t d = lc; d < dend; ++d) {
+            const int64_t k = (int64_t)rp.k0 + d;
+            if (k < 0) continue;
+            const double gd = exp(-(double)(d * T) / (double)tau);
+            const double qd = gd * gd;
+            A += qd * abc[k * 4 + 0];
+            B += qd * abc[k * 4 + 1];
+            Cc += qd * abc[k * 4 + 2];
+#pragma unroll
+            for (int b = 0; b < BG; ++b) {
+                if (bin0 + b >= n_bins) continue;
+                const Q4<XT> x = load_q4(xg + ((size_t)k * n_bins + bin0 + b) * 4);
+                f[b][0] += gd * (double)x.x;
+                f[b][1] += gd * (double)x.y;
+                f[b][2] += gd * (double)x.z;
+                f[b][3] += gd * (double)x.w;
+            }
+        }
+        if (p.scale_rows && rp.delta != 0) {
+            const double s = exp(-(double)rp.delta / (double)tau);
+            const double s2 = s * s;
+            A *= s2; B *= s2; Cc *= s2;
+#pragma unroll
+            for (int b = 0; b < BG; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[b][c] *= s;
+        }
+#pragma unroll
+        for (int b = 0; b < BG; ++b) {
+            const int bin = bin0 + b;
+            if (!ok || bin >= n_bins) continue;
+            const double v = twoF_cell(A, B, Cc, f[b][0], f[b][1], f[b][2], f[b][3]);
+            if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
+            const Red cell{0.5 * v, 1.0, (long long)m * p.n_tau + n};
+            red[b] = red_combine(red[b], cell);
+        }
+    }
+    const int tile = nb * p.n_row_tiles + row_tile;
+#pragma unroll
+    for (int b = 0; b < BG; ++b) {
+        const Red w = red_wave(red[b]);
+        if (lane == 0 && bin0 + b < n_bins) {
+            Partial &o = p.part[(size_t)(bin0 + b) * p.n_tiles + tile];
+            o.fmax = w.f;
+            o.s = w.s;
+            o.idx = w.i;
+        }
+    }
+}
+
+// Waves per SIMD the runs form is built for (the four-bin shape needs more
+// registers per lane).
+template <typename XT, int R, int BG>
+constexpr int runs_waves() {
+    return BG == 4 ? 2 : 3;
+}
+
+template <typename XT, int R, int BG>
+__global__ __launch_bounds__(kThreads, (runs_waves<XT, R, BG>())) void exp_runs_kernel(ExpValuParams p) {
+    __shared__ RunSmem<XT, R, BG> sm;
+    // groups of four tau blocks, dealt round-robin to the XCDs
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7;
+    const int slot = bid >> 3;
+    const int g = (slot / p.n_row_tiles) * 8 + xcd;
+    if (g * kWaves >= p.n_list) return;
+    exp_runs_tile<XT, R, BG>(p, sm, g * kWaves, slot % p.n_row_tiles, blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------
 // Exponential weight tables g_n[d] = exp(-d T / tau_n) for d < lcol[n],
 // blocked [block][d][R] and zero-padded to the block's longest band.
 // ---------------------------------------------------------------------------
@@ -731,6 +998,11 @@ struct FusedSmem {
                                 : sizeof(ExpSmem<double, 4, 1>));
     static constexpr size_t bytes = exp_bytes > sizeof(Red) * kWaves ? exp_bytes : sizeof(Red) * kWaves;
 };
+static_assert(sizeof(RunSmem<double, 4, 1>) <= sizeof(ExpSmem<double, 4, 1>) &&
+                  sizeof(RunSmem<float, 8, 1>) <= sizeof(ExpSmem<float, 8, 1>) &&
+                  sizeof(RunSmem<float, 4, 2>) <= sizeof(ExpSmem<float, 4, 2>) &&
+                  sizeof(RunSmem<float, 4, 4>) <= sizeof(ExpSmem<float, 4, 4>),
+              "runs staging fits the fused kernel's shared memory");
 
 // Loads a descriptor that the kernel never writes, whose address is the same
 // in every lane, and keeps it in scalar registers.
@@ -743,6 +1015,19 @@ __device__ __attribute__((always_inline)) inline T load_uniform(const T *src) {
 #pragma unroll
     for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
     return out;
+}
+
+template <int SHAPE, typename PP>
+__device__ __attribute__((always_inline)) inline void fused_runs(PP &p, char *smem,
+                                                                 const BatchTile &t) {
+    if constexpr (SHAPE == kShapeD41)
+        exp_runs_tile<double, 4, 1>(p, *reinterpret_cast<RunSmem<double, 4, 1> *>(smem), t.x, t.y, t.z);
+    else if constexpr (SHAPE == kShapeF81)
+        exp_runs_tile<float, 8, 1>(p, *reinterpret_cast<RunSmem<float, 8, 1> *>(smem), t.x, t.y, t.z);
+    else if constexpr (SHAPE == kShapeF42)
+        exp_runs_tile<float, 4, 2>(p, *reinterpret_cast<RunSmem<float, 4, 2> *>(smem), t.x, t.y, t.z);
+    else
+        exp_runs_tile<float, 4, 4>(p, *reinterpret_cast<RunSmem<float, 4, 4> *>(smem), t.x, t.y, t.z);
 }
 
 template <int SHAPE, typename PP>
@@ -792,6 +1077,19 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
             continue;
         }
         auto &ep = const_params(p.exp_jobs + t.job);
+        if (t.kind == 2) {
+            if constexpr (V == kShapeMixed) {
+                switch (t.shape) {
+                case kShapeD41: fused_runs<kShapeD41>(ep, smem, t); break;
+                case kShapeF81: fused_runs<kShapeF81>(ep, smem, t); break;
+                case kShapeF42: fused_runs<kShapeF42>(ep, smem, t); break;
+                default: fused_runs<kShapeF44>(ep, smem, t); break;
+                }
+            } else {
+                fused_runs<V>(ep, smem, t);
+            }
+            continue;
+        }
         if constexpr (V == kShapeMixed) {
             switch (t.shape) {
             case kShapeD41: fused_exp<kShapeD41>(ep, smem, t); break;
@@ -881,6 +1179,24 @@ hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, hipS
         hipLaunchKernelGGL((exp_valu_kernel<float, 4, 2>), grid, dim3(kThreads), 0, s, p);
     else if (prec == 1 && R == 4 && BG == 4)
         hipLaunchKernelGGL((exp_valu_kernel<float, 4, 4>), grid, dim3(kThreads), 0, s, p);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, hipStream_t s) {
+    if (p.n_list <= 0) return hipSuccess;
+    const int n_groups = (p.n_list + kWaves - 1) / kWaves;
+    const dim3 grid((unsigned)(8 * ((n_groups + 7) / 8) * p.n_row_tiles),
+                    (unsigned)((p.at.n_bins + BG - 1) / BG));
+    if (prec == 0 && R == 4 && BG == 1)
+        hipLaunchKernelGGL((exp_runs_kernel<double, 4, 1>), grid, dim3(kThreads), 0, s, p);
+    else if (prec == 1 && R == 8 && BG == 1)
+        hipLaunchKernelGGL((exp_runs_kernel<float, 8, 1>), grid, dim3(kThreads), 0, s, p);
+    else if (prec == 1 && R == 4 && BG == 2)
+        hipLaunchKernelGGL((exp_runs_kernel<float, 4, 2>), grid, dim3(kThreads), 0, s, p);
+    else if (prec == 1 && R == 4 && BG == 4)
+        hipLaunchKernelGGL((exp_runs_kernel<float, 4, 4>), grid, dim3(kThreads), 0, s, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

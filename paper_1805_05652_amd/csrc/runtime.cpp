@@ -245,6 +245,10 @@ enum { NK = TFSTAT_K_COUNT };
 constexpr int kMfmaTaus = 8;       // taus per matrix-core work item
 inline int32_t abc_pitch(int32_t n_tau) { return (n_tau + kMfmaTaus - 1) / kMfmaTaus * kMfmaTaus; }
 constexpr int kMfmaMinBand = 64;   // shorter bands stay on the VALU path
+// Tiling threshold of the exponential VALU sums (tfstat_tiling_config):
+// kRunsAuto sends a map to the runs form when its median 64-row tile spans
+// more slots than one LDS stage can stage in rounds of kExpMinStageRound.
+constexpr int32_t kRunsAuto = -1;
 
 // ---------------------------------------------------------------------------
 // One map computation: plan (host, integer), workspace, launches, results.
@@ -261,6 +265,8 @@ struct Job {
     std::vector<int64_t> blk_off;
     int R = 0, BG = 0, NB = 0, n_row_tiles = 0, n_tiles = 0, n_tiles_n = 0;
     int force_R = 0, force_BG = 0;   // exponential VALU tile shape chosen by the caller
+    int32_t runs_min_spread = kRunsAuto;   // see tfstat_tiling_config
+    bool runs = false;         // VALU blocks by the runs form (t0 rows far apart)
     int64_t wtot = 0, max_blk = 0;
     bool use_recur = false;    // RECUR64: exponential sums by the t0 recurrence
     int32_t recur_stride = 0, recur_k0 = 0, recur_bg = 1;
@@ -387,6 +393,21 @@ void plan_job(Job &j) {
         j.n_tiles = j.NB * j.n_row_tiles;
         j.n_valu = j.NB;
         j.n_mfma = 0;
+        {
+            std::vector<int64_t> spread(j.n_row_tiles);
+            for (int t = 0; t < j.n_row_tiles; ++t)
+                spread[t] = (int64_t)j.rows[std::min(t * 64 + 63, n_t0 - 1)].k0 - j.rows[t * 64].k0;
+            std::nth_element(spread.begin(), spread.begin() + j.n_row_tiles / 2, spread.end());
+            const int64_t med = spread[j.n_row_tiles / 2];
+            // automatic: the runs form where the band stage would fall back
+            // to per-lane reads through the caches, except for the 8-tau
+            // one-bin shape, whose 32-tau runs tiles leave too few
+            // workgroups for one map (its per-lane reads are faster there)
+            if (j.runs_min_spread >= 0)
+                j.runs = med >= j.runs_min_spread;
+            else
+                j.runs = j.R != 8 && med > tfs::exp_stage_len(prec, j.BG) - tfs::kExpMinStageRound;
+        }
         if (j.use_mfma) {
             // a block with any short band stays on the FP32 VALU path: short
             // windows carry little work and the worst conditioning, which
@@ -525,6 +546,7 @@ struct tfstat_ctx {
     std::unique_ptr<tfstat_batch> slot_batch[kSlots];   // their fused batch, if batched
     hipEvent_t slot_done[kSlots] = {nullptr};
     int serve_max_batch = 16;                           // requests fused into one launch at most
+    std::atomic<int32_t> runs_min_spread{kRunsAuto};   // see tfstat_tiling_config
     std::thread worker;
     std::condition_variable cv;
     bool stop = false;
@@ -729,8 +751,10 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         tfs::ExpValuParams p = exp_params(j);
         if (j.n_valu > 0) {
             record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
-            hip_check(tfs::launch_exp_valu(p, wants64(j) ? 0 : 1, j.R, j.BG, s),
-                      "exp kernel");
+            if (j.runs)
+                hip_check(tfs::launch_exp_runs(p, wants64(j) ? 0 : 1, j.R, j.BG, s), "exp runs kernel");
+            else
+                hip_check(tfs::launch_exp_valu(p, wants64(j) ? 0 : 1, j.R, j.BG, s), "exp kernel");
             record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
         }
         if (j.n_mfma > 0) {
@@ -989,9 +1013,12 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
         Job &j = *b->jobs[i];
         if (eidx[i] >= 0) {
             const size_t per = (size_t)j.n_row_tiles * ((j.at->n_bins + j.BG - 1) / j.BG);
-            for (int q = 0; q < j.n_valu; ++q)
-                groups_e.push_back({i, q, (double)(j.lblk[j.order[q]] + 1) * j.R * (3 + 4 * j.BG)});
-            n_tiles_total += per * j.n_valu;
+            // a runs tile takes four blocks, each over its whole band on one
+            // wave: about four times the time of one block's tile
+            const int step = j.runs ? 4 : 1;
+            for (int q = 0; q < j.n_valu; q += step)
+                groups_e.push_back({i, q, (double)(j.lblk[j.order[q]] + 1) * j.R * (3 + 4 * j.BG) * step});
+            n_tiles_total += per * ((j.n_valu + step - 1) / step);
         } else {
             const int nby = ((int)j.win.t0.size() + 3) / 4;
             const int ny = (nby + tfs::kRectRowBlocks - 1) / tfs::kRectRowBlocks;
@@ -1008,7 +1035,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
         const int bgs = (j.at->n_bins + j.BG - 1) / j.BG;
         for (int rt = 0; rt < j.n_row_tiles; ++rt)
             for (int gidx = 0; gidx < bgs; ++gidx)
-                tiles.push_back(tfs::BatchTile{0, eidx[g.map], g.q, rt, gidx, shape[g.map]});
+                tiles.push_back(tfs::BatchTile{j.runs ? 2 : 0, eidx[g.map], g.q, rt, gidx, shape[g.map]});
     }
     for (int32_t i = 0; i < n; ++i) {
         if (ridx[i] < 0) continue;
@@ -1168,6 +1195,7 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
             j.force_R = R;
             j.force_BG = BG;
         }
+        j.runs_min_spread = ctx->runs_min_spread.load();
         plan_job(j);
     }
     if (!batch_layout(ctx, b, ctx->batch_stream, true, false))
@@ -1638,6 +1666,7 @@ int tfstat_fmap(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win, i
         j.win = copy_window(win);
         j.prec = precision;
         j.twoF = twoF_dev;
+        j.runs_min_spread = ctx->runs_min_spread.load();
         plan_job(j);
         {
             std::lock_guard<std::mutex> g(ctx->mu);
@@ -1725,6 +1754,7 @@ int tfstat_submit(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win,
         std::lock_guard<std::mutex> g(ctx->mu);
         job->at = find_atoms(ctx, id);
         if (precision == TFSTAT_PREC_BF16X3) ensure_planes(ctx, job->at);
+        job->runs_min_spread = ctx->runs_min_spread.load();
         plan_job(*job);
         // A request whose workspace cannot fit beside the resident atoms
         // would wait forever: refuse it now.
@@ -1930,6 +1960,14 @@ int tfstat_serve_config(tfstat_ctx *ctx, int32_t max_batch) {
         if (max_batch < 1 || max_batch > 1024) raise(TFSTAT_E_INVAL, "max_batch must be in 1..1024");
         std::lock_guard<std::mutex> g(ctx->mu);
         ctx->serve_max_batch = max_batch;
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_tiling_config(tfstat_ctx *ctx, int32_t runs_min_spread) {
+    return guarded([&] {
+        if (!ctx) raise(TFSTAT_E_INVAL, "ctx is null");
+        ctx->runs_min_spread.store(runs_min_spread < 0 ? kRunsAuto : runs_min_spread);
         return (int)TFSTAT_OK;
     });
 }

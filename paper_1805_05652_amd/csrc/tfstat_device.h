@@ -71,6 +71,13 @@ struct ExpValuParams {
                               // tails); 0: shape window (one delta, tables hold it)
 };
 
+// LDS stage of the band-staged exponential form: slots per stage for a
+// precision (0 = FP64 sums, 1 = FP32) and bins per lane, and the fewest band
+// slots per round worth staging.  Tiles whose rows span more than
+// stage - kExpMinStageRound slots read through the caches instead.
+constexpr int kExpMinStageRound = 64;
+constexpr int exp_stage_len(int prec, int BG) { return (prec == 1 && BG == 1) ? 1008 : 512; }
+
 // Exponential-window F_a, F_b on bf16 matrix cores for grids whose t0 rows
 // are consecutive slots with one common delta.
 struct ExpMfmaParams {
@@ -197,9 +204,9 @@ inline void shape_dims(int shape, int *prec, int *R, int *BG) {
 constexpr int kRectRowBlocks = 4;   // 4-row rect blocks per batch tile (16 rows)
 
 struct BatchTile {
-    int32_t kind;    // 0: exponential, 1: rectangular
+    int32_t kind;    // 0: exponential, 1: rectangular, 2: exponential, rows far apart
     int32_t job;     // index into FusedParams::exp_jobs or ::rect_jobs
-    int32_t x;       // exp: position in blk_list; rect: tau tile (64 taus)
+    int32_t x;       // exp: position in blk_list (kind 2: first of four); rect: tau tile (64 taus)
     int32_t y;       // exp: 64-row tile; rect: first 4-row block / kRectRowBlocks
     int32_t z;       // exp: bin group; rect: bin
     int32_t shape;   // exp: ExpShape of the job
@@ -258,6 +265,11 @@ hipError_t launch_weights(const WeightParams &p, int64_t total_max_per_block,
 // prec: 0 = FP64 sums, 1 = FP32 sums.  bins_per_group chosen by the caller
 // from the supported set reported by exp_valu_config().
 hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG,
+                           hipStream_t s);
+// The same sums for grids whose t0 rows lie far apart: each row stages its
+// own run of slots and the four waves of a workgroup take four consecutive
+// blocks of blk_list (p.n_list blocks in groups of four).
+hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG,
                            hipStream_t s);
 // A/B/C only (FP64), R = 8 blocks, into p.abc_out.
 hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s);

@@ -101,6 +101,28 @@ def test_sparse_row_batch(ctx, prec):
             ctx.free(aid)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_runs_form(ctx, prec):
+    """Every exponential map of the batch on the runs form (tiling threshold
+    0): against the oracle, and bit-identical to tfstat_fmap of the same map
+    planned the same way."""
+    _case("batch runs form " + prec)
+    cands = small_candidates(8, seed_base=7700)
+    ids = upload_all(ctx, cands)
+    try:
+        ctx.tiling_config(0)
+        with ctx.batch(list(zip(ids, [w for _, w in cands])), prec) as b:
+            got = b.run()
+        for (atoms, win), aid, res in zip(cands, ids, got):
+            check_against_oracle(res, atoms, win, TOL[prec])
+            single, _ = ctx.fmap(aid, win, prec)
+            same_results(res, single)
+    finally:
+        ctx.tiling_config(-1)
+        for aid in ids:
+            ctx.free(aid)
+
+
 def test_graph_replays_with_eager_work_between(ctx):
     """Every replay of the captured graph gives the first run's results, with
     the library's own eager launches and synchronisations in between."""

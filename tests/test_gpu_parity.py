@@ -35,6 +35,23 @@ def _case(msg):
     print("case:", msg, flush=True)
 
 
+DENSE_ONLY = 1 << 30   # tiling: every map on the band-staged form
+RUNS_ALWAYS = 0        # tiling: every map on the runs form
+
+
+class tiling:
+    """Sets the exponential tiling threshold for the maps planned inside."""
+
+    def __init__(self, ctx, runs_min_spread):
+        self.ctx, self.v = ctx, runs_min_spread
+
+    def __enter__(self):
+        self.ctx.tiling_config(self.v)
+
+    def __exit__(self, *exc):
+        self.ctx.tiling_config(-1)
+
+
 def check_map(got, ref, tol):
     got = np.asarray(got, dtype=np.float64)
     assert got.shape == ref.shape
@@ -111,24 +128,30 @@ def test_exp_bins_groups(ctx, n_bins):
     run_and_check(ctx, atoms, win, "fp32")
 
 
-def test_exp_sparse_rows_read_through_cache(ctx):
-    """Rows 10 slots apart: a 64-row tile spans more slots than one LDS stage."""
-    _case("exp sparse rows")
+@pytest.mark.parametrize("form", ["dense", "default"])
+def test_exp_sparse_rows_read_through_cache(ctx, form):
+    """Rows 10 slots apart: a 64-row tile spans more slots than one LDS stage
+    (band-staged form: each lane reads its slots through the caches; by
+    default: the runs form)."""
+    _case("exp sparse rows " + form)
     atoms = tfsynth.make_atoms(301, 900, 0.1, n_bins=2)
     win = tfsynth.regular_window("exp", 0, 10 * T, 85, 2 * T, 7 * T + 13, 30)
-    run_and_check(ctx, atoms, win, "fp32")
-    run_and_check(ctx, atoms, win, "fp64")
+    with tiling(ctx, DENSE_ONLY if form == "dense" else -1):
+        run_and_check(ctx, atoms, win, "fp32")
+        run_and_check(ctx, atoms, win, "fp64")
 
 
 @pytest.mark.parametrize("step,n_bins", [(13, 1), (16, 1), (5, 2), (7, 5)])
-def test_exp_row_spread_staging_limits(ctx, step, n_bins):
+@pytest.mark.parametrize("form", ["dense", "runs"])
+def test_exp_row_spread_staging_limits(ctx, step, n_bins, form):
     """64-row tiles spanning 819 and 1008 slots (one bin: staged in shorter
     rounds, then read through the caches) and 315 and 441 slots (two and five
-    bins: staged in shorter rounds); ragged band ends."""
-    _case("exp row spread step %d bins %d" % (step, n_bins))
+    bins: staged in shorter rounds); ragged band ends.  Both tile forms."""
+    _case("exp row spread step %d bins %d %s" % (step, n_bins, form))
     atoms = tfsynth.make_atoms(311 + step, 1500, 0.1, n_bins=n_bins)
     win = tfsynth.regular_window("exp", 3 * T + 40, step * T, 100, 2 * T, 9 * T + 17, 40)
-    run_and_check(ctx, atoms, win, "fp32")
+    with tiling(ctx, DENSE_ONLY if form == "dense" else RUNS_ALWAYS):
+        run_and_check(ctx, atoms, win, "fp32")
 
 
 @pytest.mark.parametrize("prec,n_bins,kind", [("fp32", 1, "exp"), ("fp32", 3, "exp"), ("fp32", 6, "exp"),
@@ -152,6 +175,78 @@ def test_exp_long_bands_many_chunks(ctx):
                                injections=[tfsynth.Injection(0, "exp", 100 * T, 200 * T, 0.6)])
     win = tfsynth.regular_window("exp", 0, T, 200, 2 * T, 61 * T, 24)
     run_and_check(ctx, atoms, win, "fp32")
+
+
+def _runs_case(case):
+    """Maps for the runs form, from consecutive rows (every slot shared by 64
+    rows) to rows 31 slots apart; ragged tiles, edges, bin groups, shapes."""
+    if case.startswith("ragged"):
+        atoms = tfsynth.make_atoms(111, 300, 0.2, n_bins=3,
+                                   injections=[tfsynth.Injection(2, "exp", 40 * T, 30 * T, 1.2)])
+        rng = np.random.default_rng(15)
+        t0 = np.unique(np.concatenate([[-5 * T - 77, -T, -1, 0, 1, T - 1],
+                                       rng.integers(0, 300 * T, size=120),
+                                       [299 * T, 299 * T + 1, 300 * T + 5, 400 * T]]))
+        tau = np.unique(np.concatenate([[1, T - 1, T, T + 1, 2 * T], rng.integers(2 * T, 200 * T, size=37),
+                                        [300 * T, 1000 * T]]))
+        return atoms, tfsynth.list_window("exp", t0, tau)
+    if case.startswith("bins"):
+        n_bins = int(case[4:])
+        atoms = tfsynth.make_atoms(220 + n_bins, 700, 0.1, n_bins=n_bins)
+        return atoms, tfsynth.regular_window("exp", 5 * T + 9, 7 * T, 93, 2 * T, 5 * T + 1, 41)
+    if case == "consecutive":
+        atoms = tfsynth.make_atoms(231, 500, 0.1, n_bins=2)
+        return atoms, tfsynth.regular_window("exp", 0, T, 130, 2 * T, T, 77)
+    if case == "far31":
+        atoms = tfsynth.make_atoms(232, 3100, 0.15, n_bins=1,
+                                   injections=[tfsynth.Injection(0, "exp", 900 * T, 60 * T, 1.0)])
+        return atoms, tfsynth.regular_window("exp", 2 * T + 500, 31 * T, 97, 2 * T, 13 * T, 36)
+    if case.startswith("shape"):
+        atoms = tfsynth.make_atoms(233, 900, 0.1, n_bins=5)
+        base = tfsynth.regular_window("exp", 100, 9 * T, 90, 2 * T, 3 * T + 7, 45)
+        return atoms, _bump_window(base)
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case,prec", [("ragged", "fp32"), ("ragged", "fp64"), ("bins1", "fp32"),
+                                       ("bins2", "fp32"), ("bins5", "fp32"), ("bins8", "fp32"),
+                                       ("bins1", "fp64"), ("consecutive", "fp32"), ("far31", "fp32"),
+                                       ("far31", "fp64"), ("shape", "fp32"), ("shape", "fp64")])
+def test_exp_runs_form(ctx, case, prec):
+    """The runs form on every map (tiling threshold 0): t0 off the slot grid,
+    before and after the data, taus shorter than one SFT and longer than the
+    data, partial bin groups, groups of four tau blocks with a ragged last
+    group, shape windows."""
+    _case("exp runs form %s %s" % (case, prec))
+    atoms, win = _runs_case(case)
+    with tiling(ctx, RUNS_ALWAYS):
+        run_and_check(ctx, atoms, win, prec)
+
+
+def test_exp_forms_agree(ctx):
+    """The two forms of the same map agree within the FP32 tolerance, and
+    each is bitwise repeatable."""
+    _case("exp forms agree")
+    atoms, win = _runs_case("bins5")
+    aid = ctx.upload_atoms(atoms)
+    try:
+        out = {}
+        for name, v in (("dense", DENSE_ONLY), ("runs", RUNS_ALWAYS)):
+            with tiling(ctx, v):
+                a, ma = ctx.fmap(aid, win, "fp32", want_map=True)
+                b, mb = ctx.fmap(aid, win, "fp32", want_map=True)
+            assert torch_equal(ma, mb)
+            out[name] = (a, ma.cpu().numpy().astype(np.float64))
+        d, r = out["dense"][1], out["runs"][1]
+        assert np.all((d == 0) == (r == 0))
+        assert np.max(np.abs(d - r) / np.maximum(np.abs(d), 1.0)) <= 2e-4
+    finally:
+        ctx.free(aid)
+
+
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a, b))
 
 
 def test_single_cell_and_single_sft(ctx):
