@@ -59,16 +59,41 @@ __device__ inline Red red_combine(const Red &a, const Red &b) {
     return r;
 }
 
+// Adds one cell (F = 2F / 2 and its linear index) to a lane's running
+// state: one exponential per cell, FP32 arguments (exp(F - fmax) <= 1).
+__device__ inline void red_add(Red &r, double F, long long idx) {
+    if (F > r.f) {
+        r.s = (r.f == -INFINITY) ? 1.0 : r.s * (double)__expf((float)(r.f - F)) + 1.0;
+        r.f = F;
+        r.i = idx;
+    } else {
+        r.s += (double)__expf((float)(F - r.f));
+        if (F == r.f && idx < r.i) r.i = idx;
+    }
+}
+
+// Wave reduction: the maximum and its first index by butterfly, then every
+// lane's sum rescaled to that maximum (one exponential per lane; FP32
+// argument unless EXACT) and added by butterfly; lane 0's result is used.
+template <bool EXACT = false>
 __device__ inline Red red_wave(Red v) {
+    double fm = v.f;
+    long long im = v.i;
 #pragma unroll
     for (int o = 1; o < kLanes; o <<= 1) {
-        Red w;
-        w.f = __shfl_xor(v.f, o, kLanes);
-        w.s = __shfl_xor(v.s, o, kLanes);
-        w.i = __shfl_xor(v.i, o, kLanes);
-        v = red_combine(v, w);
+        const double fo = __shfl_xor(fm, o, kLanes);
+        const long long io = __shfl_xor(im, o, kLanes);
+        if (fo > fm || (fo == fm && io < im)) {
+            fm = fo;
+            im = io;
+        }
     }
-    return v;
+    if (fm == -INFINITY) return red_empty();
+    const double e = EXACT ? exp(v.f - fm) : (double)__expf((float)(v.f - fm));
+    double sv = (v.f == -INFINITY) ? 0.0 : v.s * e;
+#pragma unroll
+    for (int o = 1; o < kLanes; o <<= 1) sv += __shfl_xor(sv, o, kLanes);
+    return Red{fm, sv, im};
 }
 
 // 2F of one cell from windowed sums (eq. F_FaFb), FP64, with the
@@ -226,7 +251,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nb = p.blk_list[q];
     const int tile = nb * p.n_row_tiles + row_tile;
-    const int bin0 = bin_group * BG;
+    const int bin0 = p.bin_base + bin_group * BG;
     const int n_bins = p.at.n_bins;
     const int K = p.at.K;
 
@@ -421,8 +446,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
             if (!ok || bin >= n_bins) continue;
             const double v = twoF_cell(A, B, C, f[b][0], f[b][1], f[b][2], f[b][3]);
             if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
-            const Red cell{0.5 * v, 1.0, (long long)m * p.n_tau + n};
-            red[b] = red_combine(red[b], cell);
+            red_add(red[b], 0.5 * v, (long long)m * p.n_tau + n);
         }
     }
     if constexpr (ABC_ONLY) return;
@@ -516,7 +540,7 @@ __device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSm
     const int tid = threadIdx.x;
     const int lane = tid & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int bin0 = bin_group * BG;
+    const int bin0 = p.bin_base + bin_group * BG;
     const int n_bins = p.at.n_bins;
     const int K = p.at.K;
     const int m_first = row_tile * kLanes;
@@ -694,8 +718,7 @@ __device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSm
             if (!ok || bin >= n_bins) continue;
             const double v = twoF_cell(A, B, Cc, f[b][0], f[b][1], f[b][2], f[b][3]);
             if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
-            const Red cell{0.5 * v, 1.0, (long long)m * p.n_tau + n};
-            red[b] = red_combine(red[b], cell);
+            red_add(red[b], 0.5 * v, (long long)m * p.n_tau + n);
         }
     }
     const int tile = nb * p.n_row_tiles + row_tile;
@@ -1085,6 +1108,9 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
                 case kShapeF42: fused_runs<kShapeF42>(ep, smem, t); break;
                 default: fused_runs<kShapeF44>(ep, smem, t); break;
                 }
+            } else if constexpr (V == kShapeF44) {
+                if (t.shape == kShapeF42) fused_runs<kShapeF42>(ep, smem, t);   // tail bin pair
+                else fused_runs<V>(ep, smem, t);
             } else {
                 fused_runs<V>(ep, smem, t);
             }
@@ -1097,6 +1123,9 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
             case kShapeF42: fused_exp<kShapeF42>(ep, smem, t); break;
             default: fused_exp<kShapeF44>(ep, smem, t); break;
             }
+        } else if constexpr (V == kShapeF44) {
+            if (t.shape == kShapeF42) fused_exp<kShapeF42>(ep, smem, t);   // tail bin pair
+            else fused_exp<V>(ep, smem, t);
         } else {
             fused_exp<V>(ep, smem, t);
         }
@@ -1124,7 +1153,7 @@ __global__ __launch_bounds__(256) void map_reduce_kernel(MapReduceParams p) {
             r.s += exp(F - r.f);
         }
     }
-    r = red_wave(r);
+    r = red_wave<true>(r);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) wred[wave] = r;
     __syncthreads();
@@ -1167,10 +1196,11 @@ hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, hipStream_t s) {
-    if (p.n_list <= 0) return hipSuccess;
+hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, int n_groups, hipStream_t s) {
+    if (p.n_list <= 0 || n_groups <= 0) return hipSuccess;
+    if (p.bin_base + (n_groups - 1) * BG >= p.at.n_bins) return hipErrorInvalidValue;
     const int groups = (p.n_list + 7) / 8;
-    const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), (unsigned)((p.at.n_bins + BG - 1) / BG));
+    const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), (unsigned)n_groups);
     if (prec == 0 && R == 4 && BG == 1)
         hipLaunchKernelGGL((exp_valu_kernel<double, 4, 1>), grid, dim3(kThreads), 0, s, p);
     else if (prec == 1 && R == 8 && BG == 1)
@@ -1184,11 +1214,11 @@ hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, hipStream_t s) {
-    if (p.n_list <= 0) return hipSuccess;
-    const int n_groups = (p.n_list + kWaves - 1) / kWaves;
-    const dim3 grid((unsigned)(8 * ((n_groups + 7) / 8) * p.n_row_tiles),
-                    (unsigned)((p.at.n_bins + BG - 1) / BG));
+hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, int n_groups, hipStream_t s) {
+    if (p.n_list <= 0 || n_groups <= 0) return hipSuccess;
+    if (p.bin_base + (n_groups - 1) * BG >= p.at.n_bins) return hipErrorInvalidValue;
+    const int n_q = (p.n_list + kWaves - 1) / kWaves;
+    const dim3 grid((unsigned)(8 * ((n_q + 7) / 8) * p.n_row_tiles), (unsigned)n_groups);
     if (prec == 0 && R == 4 && BG == 1)
         hipLaunchKernelGGL((exp_runs_kernel<double, 4, 1>), grid, dim3(kThreads), 0, s, p);
     else if (prec == 1 && R == 8 && BG == 1)

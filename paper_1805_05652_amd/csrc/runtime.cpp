@@ -267,6 +267,10 @@ struct Job {
     int force_R = 0, force_BG = 0;   // exponential VALU tile shape chosen by the caller
     int32_t runs_min_spread = kRunsAuto;   // see tfstat_tiling_config
     bool runs = false;         // VALU blocks by the runs form (t0 rows far apart)
+    // bin groups of BG bins; with four-bin groups and one or two bins left
+    // over, those take one two-bin group after the n_groups full ones
+    int n_groups = 0;
+    bool tail2 = false;
     int64_t wtot = 0, max_blk = 0;
     bool use_recur = false;    // RECUR64: exponential sums by the t0 recurrence
     int32_t recur_stride = 0, recur_k0 = 0, recur_bg = 1;
@@ -373,6 +377,8 @@ void plan_job(Job &j) {
             j.BG = 1;
         }
         j.NB = (n_tau + j.R - 1) / j.R;
+        j.tail2 = j.BG == 4 && (at.n_bins % 4 == 1 || at.n_bins % 4 == 2);
+        j.n_groups = j.tail2 ? at.n_bins / 4 : (at.n_bins + j.BG - 1) / j.BG;
         j.lblk.assign(j.NB, 0);
         j.blk_off.assign(j.NB, 0);
         int64_t acc = 0;
@@ -751,10 +757,14 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         tfs::ExpValuParams p = exp_params(j);
         if (j.n_valu > 0) {
             record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
-            if (j.runs)
-                hip_check(tfs::launch_exp_runs(p, wants64(j) ? 0 : 1, j.R, j.BG, s), "exp runs kernel");
-            else
-                hip_check(tfs::launch_exp_valu(p, wants64(j) ? 0 : 1, j.R, j.BG, s), "exp kernel");
+            auto launch = j.runs ? tfs::launch_exp_runs : tfs::launch_exp_valu;
+            const int pr = wants64(j) ? 0 : 1;
+            hip_check(launch(p, pr, j.R, j.BG, j.n_groups, s), "exp kernel");
+            if (j.tail2) {
+                tfs::ExpValuParams pt = p;
+                pt.bin_base = 4 * j.n_groups;
+                hip_check(launch(pt, pr, j.R, 2, 1, s), "exp kernel (bin pair)");
+            }
             record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
         }
         if (j.n_mfma > 0) {
@@ -1012,7 +1022,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
         if (eidx[i] >= 0) {
-            const size_t per = (size_t)j.n_row_tiles * ((j.at->n_bins + j.BG - 1) / j.BG);
+            const size_t per = (size_t)j.n_row_tiles * (j.n_groups + (j.tail2 ? 1 : 0));
             // a runs tile takes four blocks, each over its whole band on one
             // wave: about four times the time of one block's tile
             const int step = j.runs ? 4 : 1;
@@ -1032,10 +1042,14 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     tiles.reserve(n_tiles_total);
     for (const Group &g : groups_e) {
         const Job &j = *b->jobs[g.map];
-        const int bgs = (j.at->n_bins + j.BG - 1) / j.BG;
-        for (int rt = 0; rt < j.n_row_tiles; ++rt)
-            for (int gidx = 0; gidx < bgs; ++gidx)
-                tiles.push_back(tfs::BatchTile{j.runs ? 2 : 0, eidx[g.map], g.q, rt, gidx, shape[g.map]});
+        const int kind = j.runs ? 2 : 0;
+        for (int rt = 0; rt < j.n_row_tiles; ++rt) {
+            for (int gidx = 0; gidx < j.n_groups; ++gidx)
+                tiles.push_back(tfs::BatchTile{kind, eidx[g.map], g.q, rt, gidx, shape[g.map]});
+            // the bin pair after the four-bin groups: group index in pairs
+            if (j.tail2)
+                tiles.push_back(tfs::BatchTile{kind, eidx[g.map], g.q, rt, 2 * j.n_groups, tfs::kShapeF42});
+        }
     }
     for (int32_t i = 0; i < n; ++i) {
         if (ridx[i] < 0) continue;

@@ -53,7 +53,7 @@ struct ExpValuParams {
     int32_t n_row_tiles;      // ceil(n_t0 / 64)
     int32_t n_list;           // number of tau blocks this launch processes
     int32_t n_tiles;          // partial slots per bin (all blocks x row tiles)
-    int32_t pad0;
+    int32_t bin_base;         // first bin of bin group 0 of a stand-alone launch
     const RowPlan *rows;      // [n_t0]
     const int64_t *tau;       // [n_tau]
     const int32_t *lcol;      // [n_tau] table length per tau: shortest band over rows
@@ -264,12 +264,13 @@ hipError_t launch_weights(const WeightParams &p, int64_t total_max_per_block,
                           hipStream_t s);
 // prec: 0 = FP64 sums, 1 = FP32 sums.  bins_per_group chosen by the caller
 // from the supported set reported by exp_valu_config().
-hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG,
+// n_groups bin groups of BG bins from p.bin_base.
+hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, int n_groups,
                            hipStream_t s);
 // The same sums for grids whose t0 rows lie far apart: each row stages its
 // own run of slots and the four waves of a workgroup take four consecutive
 // blocks of blk_list (p.n_list blocks in groups of four).
-hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG,
+hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, int n_groups,
                            hipStream_t s);
 // A/B/C only (FP64), R = 8 blocks, into p.abc_out.
 hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s);
