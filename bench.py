@@ -119,11 +119,12 @@ def cpu_baseline(atoms, win, budget_s: float = 20.0):
                       % (sample.n_t0, win.n_t0, win.n_tau, atoms.n_bins, dt)}
 
 
-def traffic_from_profile(workload: str, kernel_file: str):
+def traffic_from_profile(workload: str, kernel_file: str, variant=None):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by a
-    plain copy's reading), or None when the counters are missing or the
-    kernel source changed since they were taken."""
+    plain copy's reading), or None when the counters are missing, the
+    kernel source changed since they were taken, or they were taken on
+    another build variant of the kernel."""
     import hashlib
     meta = os.path.join(ROOT, "profiles", kernel_file + "_" + workload + ".json")
     if not os.path.exists(meta):
@@ -131,6 +132,8 @@ def traffic_from_profile(workload: str, kernel_file: str):
     m = json.load(open(meta))
     src = os.path.join(ROOT, "paper_1805_05652_amd", "csrc", m.get("source", "kernels.hip"))
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != m["kernels_source_sha256"]:
+        return None
+    if variant is not None and m.get("variant") != variant:
         return None
     return m["traffic_bytes_per_launch"]
 
@@ -143,9 +146,13 @@ def serving(ctx, seed: int = 4000, rate_hz: float = 200.0, duration_s: float = 4
     Each request (slots log-uniform up to max_slots, grids up to max_grid,
     1..max_bins bins, window type random) is uploaded before the stream
     starts; requests are then submitted at their arrival times and polled.
-    Latency is arrival to observed completion.  The baseline runs the same
-    requests one after another through tfstat_fmap in plain FP32 and derives
-    FIFO latencies from the measured service times and the same arrivals."""
+    Latency is arrival to observed completion.  Streams: the offered rate
+    with continuous batching (up to 16 requests per launch) and with one
+    request per slot, half the offered rate, and every request at t = 0
+    (the served rate is then the loop's capacity).  The baseline runs the
+    same requests one after another through tfstat_fmap in plain FP32 and
+    derives FIFO latencies from the measured service times and the same
+    arrivals."""
     reqs = tfsynth.request_stream(seed, rate_hz, duration_s, max_slots, max_grid, max_bins)
     jobs = []
     for r in reqs:
@@ -178,6 +185,8 @@ def serving(ctx, seed: int = 4000, rate_hz: float = 200.0, duration_s: float = 4
     wall1, lat1 = run_stream(1)
     wall, lat = run_stream(16)
     wall_h, lat_h = run_stream(16, stretch=2.0)
+    # every request at t = 0: the served rate is the loop's capacity
+    wall_c, _ = run_stream(16, stretch=0.0)
     # sequential plain FP32 baseline on the same requests
     svc = []
     for arr, aid, win, nb in jobs:
@@ -201,6 +210,8 @@ def serving(ctx, seed: int = 4000, rate_hz: float = 200.0, duration_s: float = 4
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "half_rate": {"offered_rate_hz": rate_hz / 2, "maps_per_s": len(jobs) / wall_h,
                       "p50_ms": float(np.percentile(lat_h, 50)), "p99_ms": float(np.percentile(lat_h, 99))},
+        "all_at_once": {"maps_per_s": len(jobs) / wall_c,
+                        "bin_maps_per_s": sum(j[3] for j in jobs) / wall_c},
         "one_request_per_slot": {"maps_per_s": len(jobs) / wall1,
                                  "p50_ms": float(np.percentile(lat1, 50)),
                                  "p99_ms": float(np.percentile(lat1, 99))},
@@ -264,7 +275,8 @@ def bench_batch(args, tf, torch):
     # FMA (A, B, C) per exp cell*SFT, about 30 FP64 flops per rect cell*bin
     flops = 8.0 * exp_present + 6.0 * exp_cells_sfts + 30.0 * rect_cells
     roof = {"bound": "alu", "achieved": flops / (fused_ms * 1e-3) / 1e12, "peak": PEAK_ALU_TFLOPS,
-            "unit": "TFLOP/s", "kernel": "fused", "kernel_avg_ms": fused_ms, "traffic": None}
+            "unit": "TFLOP/s", "kernel": "fused", "kernel_avg_ms": fused_ms,
+            "traffic": traffic_from_profile("batch", "fused", st["variant"])}
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {
         "metric": "F-map cells*SFTs/s (exp window) and served maps/s with p50/p99 latency",

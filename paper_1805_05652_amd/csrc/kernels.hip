@@ -1023,8 +1023,7 @@ struct FusedSmem {
 };
 static_assert(sizeof(RunSmem<double, 4, 1>) <= sizeof(ExpSmem<double, 4, 1>) &&
                   sizeof(RunSmem<float, 8, 1>) <= sizeof(ExpSmem<float, 8, 1>) &&
-                  sizeof(RunSmem<float, 4, 2>) <= sizeof(ExpSmem<float, 4, 2>) &&
-                  sizeof(RunSmem<float, 4, 4>) <= sizeof(ExpSmem<float, 4, 4>),
+                  sizeof(RunSmem<float, 4, 2>) <= sizeof(ExpSmem<float, 4, 2>),
               "runs staging fits the fused kernel's shared memory");
 
 // Loads a descriptor that the kernel never writes, whose address is the same
@@ -1040,6 +1039,8 @@ __device__ __attribute__((always_inline)) inline T load_uniform(const T *src) {
     return out;
 }
 
+// Runs tiles come in three shapes: maps with four-bin groups run their
+// runs tiles as bin pairs (same sums, fewer registers per lane).
 template <int SHAPE, typename PP>
 __device__ __attribute__((always_inline)) inline void fused_runs(PP &p, char *smem,
                                                                  const BatchTile &t) {
@@ -1047,10 +1048,8 @@ __device__ __attribute__((always_inline)) inline void fused_runs(PP &p, char *sm
         exp_runs_tile<double, 4, 1>(p, *reinterpret_cast<RunSmem<double, 4, 1> *>(smem), t.x, t.y, t.z);
     else if constexpr (SHAPE == kShapeF81)
         exp_runs_tile<float, 8, 1>(p, *reinterpret_cast<RunSmem<float, 8, 1> *>(smem), t.x, t.y, t.z);
-    else if constexpr (SHAPE == kShapeF42)
-        exp_runs_tile<float, 4, 2>(p, *reinterpret_cast<RunSmem<float, 4, 2> *>(smem), t.x, t.y, t.z);
     else
-        exp_runs_tile<float, 4, 4>(p, *reinterpret_cast<RunSmem<float, 4, 4> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<float, 4, 2>(p, *reinterpret_cast<RunSmem<float, 4, 2> *>(smem), t.x, t.y, t.z);
 }
 
 template <int SHAPE, typename PP>
@@ -1105,12 +1104,8 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
                 switch (t.shape) {
                 case kShapeD41: fused_runs<kShapeD41>(ep, smem, t); break;
                 case kShapeF81: fused_runs<kShapeF81>(ep, smem, t); break;
-                case kShapeF42: fused_runs<kShapeF42>(ep, smem, t); break;
-                default: fused_runs<kShapeF44>(ep, smem, t); break;
+                default: fused_runs<kShapeF42>(ep, smem, t); break;
                 }
-            } else if constexpr (V == kShapeF44) {
-                if (t.shape == kShapeF42) fused_runs<kShapeF42>(ep, smem, t);   // tail bin pair
-                else fused_runs<V>(ep, smem, t);
             } else {
                 fused_runs<V>(ep, smem, t);
             }
@@ -1225,8 +1220,6 @@ hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, int 
         hipLaunchKernelGGL((exp_runs_kernel<float, 8, 1>), grid, dim3(kThreads), 0, s, p);
     else if (prec == 1 && R == 4 && BG == 2)
         hipLaunchKernelGGL((exp_runs_kernel<float, 4, 2>), grid, dim3(kThreads), 0, s, p);
-    else if (prec == 1 && R == 4 && BG == 4)
-        hipLaunchKernelGGL((exp_runs_kernel<float, 4, 4>), grid, dim3(kThreads), 0, s, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -413,6 +413,13 @@ void plan_job(Job &j) {
                 j.runs = med >= j.runs_min_spread;
             else
                 j.runs = j.R != 8 && med > tfs::exp_stage_len(prec, j.BG) - tfs::kExpMinStageRound;
+            // the runs form takes four-bin maps as bin pairs (the sums of
+            // every cell are the same, with fewer registers per lane)
+            if (j.runs && j.BG == 4) {
+                j.BG = 2;
+                j.tail2 = false;
+                j.n_groups = (at.n_bins + 1) / 2;
+            }
         }
         if (j.use_mfma) {
             // a block with any short band stays on the FP32 VALU path: short

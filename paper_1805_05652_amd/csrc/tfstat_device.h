@@ -269,7 +269,9 @@ hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, int 
                            hipStream_t s);
 // The same sums for grids whose t0 rows lie far apart: each row stages its
 // own run of slots and the four waves of a workgroup take four consecutive
-// blocks of blk_list (p.n_list blocks in groups of four).
+// blocks of blk_list (p.n_list blocks in groups of four).  Shapes: FP64
+// R = 4 BG = 1, FP32 R = 8 BG = 1 and FP32 R = 4 BG = 2 (four-bin maps run
+// their runs tiles as bin pairs).
 hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, int n_groups,
                            hipStream_t s);
 // A/B/C only (FP64), R = 8 blocks, into p.abc_out.
