@@ -25,7 +25,10 @@ namespace {
 constexpr int kLanes = 64;
 constexpr int kWaves = 4;
 constexpr int kThreads = kLanes * kWaves;
-constexpr int kDC = 256;          // band slots staged per round (at most)
+#ifndef TFS_KDC
+#define TFS_KDC 256
+#endif
+constexpr int kDC = TFS_KDC;      // band slots staged per round (at most)
 constexpr int kMinDC = kExpMinStageRound;   // fewest band slots per round worth staging
 
 // Slots one LDS stage holds (exp_stage_len): a 64-row tile whose rows span
@@ -240,6 +243,54 @@ struct ExpAcc {
     }
 };
 
+// s_waitcnt operand (gfx9 encoding) that waits for LDS / scalar memory only:
+// vmcnt 63, expcnt 7, lgkmcnt 0
+constexpr int kWaitLgkm0 = 0xC07F;
+
+// Operands of one band step of the staged form: the R weights and squared
+// weights of slot offset d (uniform: scalar registers) and the lane's atoms.
+template <typename XT, int R, int BG>
+struct StepOps {
+    XT w[R];
+    double q[R];
+    double a2, b2, ab;
+    Q4<XT> x[BG];
+};
+
+template <bool ABC_ONLY, typename SM, typename XT, int R, int BG>
+__device__ __attribute__((always_inline)) inline void fetch_step(const SM &sm, const XT *__restrict__ gw_base,
+                                                                 const double *__restrict__ gq_base, int my,
+                                                                 int d0, int dd, StepOps<XT, R, BG> &o) {
+    const int li = my + dd;
+    const size_t d = (size_t)(d0 + dd);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        o.w[r] = gw_base[d * R + r];
+        o.q[r] = gq_base[d * R + r];
+    }
+    o.a2 = sm.u.stage.a2[li];
+    o.b2 = sm.u.stage.b2[li];
+    o.ab = sm.u.stage.ab[li];
+    if constexpr (!ABC_ONLY) {
+#pragma unroll
+        for (int b = 0; b < BG; ++b) o.x[b] = sm.u.stage.x[b][li];
+    }
+}
+
+// Shapes whose staged band loop is software-pipelined: bit 1 FP64, 2 FP32
+// R = 8, 4 FP32 R = 4 BG = 2, 8 FP32 R = 4 BG = 4, 16 A/B/C only.  Only the
+// four-bin shape has the registers for a second operand set at its
+// occupancy (measured: faster in the fused batch kernel, about even in
+// the stand-alone kernel).
+#ifndef TFS_PIPE_MASK
+#define TFS_PIPE_MASK 8
+#endif
+template <typename XT, int R, int BG, bool ABC_ONLY>
+constexpr bool exp_pipe() {
+    const int bit = ABC_ONLY ? 16 : sizeof(XT) == 8 ? 1 : R == 8 ? 2 : BG == 2 ? 4 : 8;
+    return (TFS_PIPE_MASK & bit) != 0;
+}
+
 // One (64-row tile, R-tau block, BG-bin group) task of the exponential map:
 // q indexes p.blk_list.  Every thread of the workgroup calls it.
 template <typename XT, int R, int BG, bool ABC_ONLY = false, typename PP>
@@ -309,16 +360,43 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
             const int per = (dn + kWaves - 1) / kWaves;
             const int ds = wave * per;
             const int de = min(dn, ds + per);
-            for (int dd = ds; dd < de; ++dd) {
-                const int li = my + dd;
-                Q4<XT> x[BG];
-                if constexpr (!ABC_ONLY) {
-#pragma unroll
-                    for (int b = 0; b < BG; ++b) x[b] = sm.u.stage.x[b][li];
+            if constexpr (exp_pipe<XT, R, BG, ABC_ONLY>()) {
+                // Software pipeline: the operands of step dd + 1 (weights by
+                // scalar loads, atoms from LDS) are fetched while the sums of
+                // step dd run.  Scalar loads complete out of order, so the
+                // wait for one step's operands is taken explicitly at the top
+                // of each half-iteration, before the next step's fetch.
+                if (ds < de) {
+                    StepOps<XT, R, BG> a, b;
+                    fetch_step<ABC_ONLY>(sm, gw_base, gq_base, my, d0, ds, a);
+                    int dd = ds;
+#pragma unroll 1
+                    for (; dd + 2 <= de; dd += 2) {
+                        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        fetch_step<ABC_ONLY>(sm, gw_base, gq_base, my, d0, dd + 1, b);
+                        __builtin_amdgcn_sched_barrier(0);
+                        acc.step(a.w, a.q, a.a2, a.b2, a.ab, a.x);
+                        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        fetch_step<ABC_ONLY>(sm, gw_base, gq_base, my, d0, min(dd + 2, de - 1), a);
+                        __builtin_amdgcn_sched_barrier(0);
+                        acc.step(b.w, b.q, b.a2, b.b2, b.ab, b.x);
+                    }
+                    if (dd < de) acc.step(a.w, a.q, a.a2, a.b2, a.ab, a.x);
                 }
-                const int d = d0 + dd;
-                acc.step(gw_base + (size_t)d * R, gq_base + (size_t)d * R,
-                         sm.u.stage.a2[li], sm.u.stage.b2[li], sm.u.stage.ab[li], x);
+            } else {
+                for (int dd = ds; dd < de; ++dd) {
+                    const int li = my + dd;
+                    Q4<XT> x[BG];
+                    if constexpr (!ABC_ONLY) {
+#pragma unroll
+                        for (int b = 0; b < BG; ++b) x[b] = sm.u.stage.x[b][li];
+                    }
+                    const int d = d0 + dd;
+                    acc.step(gw_base + (size_t)d * R, gq_base + (size_t)d * R,
+                             sm.u.stage.a2[li], sm.u.stage.b2[li], sm.u.stage.ab[li], x);
+                }
             }
         }
     } else {
