@@ -176,7 +176,13 @@ struct ExpSmem {
     Red wred[kWaves][BG];
 };
 
-template <typename XT, int R, int BG, bool ABC_ONLY = false>
+// What an exponential tile sums: everything, A/B/C only (FP64, for the
+// matrix-core form), or F_a/F_b only (A/B/C read from abc_out).
+constexpr int kModeAll = 0;
+constexpr int kModeAbc = 1;
+constexpr int kModeF = 2;
+
+template <typename XT, int R, int BG, int MODE = kModeAll>
 struct ExpAcc {
     double A[R], B[R], C[R];
     XT f[R][BG][4];
@@ -196,11 +202,13 @@ struct ExpAcc {
                                 double a2, double b2, double ab, const Q4<XT> *x) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double q = gq[r];
-            A[r] = fma(q, a2, A[r]);
-            B[r] = fma(q, b2, B[r]);
-            C[r] = fma(q, ab, C[r]);
-            if constexpr (ABC_ONLY) continue;
+            if constexpr (MODE != kModeF) {
+                const double q = gq[r];
+                A[r] = fma(q, a2, A[r]);
+                B[r] = fma(q, b2, B[r]);
+                C[r] = fma(q, ab, C[r]);
+            }
+            if constexpr (MODE == kModeAbc) continue;
             const XT g = gw[r];
 #pragma unroll
             for (int b = 0; b < BG; ++b) {
@@ -216,10 +224,12 @@ struct ExpAcc {
     __device__ inline void store(SM &sm, int j, int lane) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            sm.u.comb.abc[j][r][0][lane] = A[r];
-            sm.u.comb.abc[j][r][1][lane] = B[r];
-            sm.u.comb.abc[j][r][2][lane] = C[r];
-            if constexpr (ABC_ONLY) continue;
+            if constexpr (MODE != kModeF) {
+                sm.u.comb.abc[j][r][0][lane] = A[r];
+                sm.u.comb.abc[j][r][1][lane] = B[r];
+                sm.u.comb.abc[j][r][2][lane] = C[r];
+            }
+            if constexpr (MODE == kModeAbc) continue;
 #pragma unroll
             for (int b = 0; b < BG; ++b)
 #pragma unroll
@@ -231,10 +241,12 @@ struct ExpAcc {
     __device__ inline void add(const SM &sm, int j, int lane) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            A[r] += sm.u.comb.abc[j][r][0][lane];
-            B[r] += sm.u.comb.abc[j][r][1][lane];
-            C[r] += sm.u.comb.abc[j][r][2][lane];
-            if constexpr (ABC_ONLY) continue;
+            if constexpr (MODE != kModeF) {
+                A[r] += sm.u.comb.abc[j][r][0][lane];
+                B[r] += sm.u.comb.abc[j][r][1][lane];
+                C[r] += sm.u.comb.abc[j][r][2][lane];
+            }
+            if constexpr (MODE == kModeAbc) continue;
 #pragma unroll
             for (int b = 0; b < BG; ++b)
 #pragma unroll
@@ -257,7 +269,7 @@ struct StepOps {
     Q4<XT> x[BG];
 };
 
-template <bool ABC_ONLY, typename SM, typename XT, int R, int BG>
+template <int MODE, typename SM, typename XT, int R, int BG>
 __device__ __attribute__((always_inline)) inline void fetch_step(const SM &sm, const XT *__restrict__ gw_base,
                                                                  const double *__restrict__ gq_base, int my,
                                                                  int d0, int dd, StepOps<XT, R, BG> &o) {
@@ -268,32 +280,34 @@ __device__ __attribute__((always_inline)) inline void fetch_step(const SM &sm, c
         o.w[r] = gw_base[d * R + r];
         o.q[r] = gq_base[d * R + r];
     }
-    o.a2 = sm.u.stage.a2[li];
-    o.b2 = sm.u.stage.b2[li];
-    o.ab = sm.u.stage.ab[li];
-    if constexpr (!ABC_ONLY) {
+    if constexpr (MODE != kModeF) {
+        o.a2 = sm.u.stage.a2[li];
+        o.b2 = sm.u.stage.b2[li];
+        o.ab = sm.u.stage.ab[li];
+    }
+    if constexpr (MODE != kModeAbc) {
 #pragma unroll
         for (int b = 0; b < BG; ++b) o.x[b] = sm.u.stage.x[b][li];
     }
 }
 
 // Shapes whose staged band loop is software-pipelined: bit 1 FP64, 2 FP32
-// R = 8, 4 FP32 R = 4 BG = 2, 8 FP32 R = 4 BG = 4, 16 A/B/C only.  Only the
+// R = 8, 4 FP32 R = 4 BG = 2, 8 FP32 R = 4 BG = 4, 16 A/B/C only, 32 F only.  Only the
 // four-bin shape has the registers for a second operand set at its
 // occupancy (measured: faster in the fused batch kernel, about even in
 // the stand-alone kernel).
 #ifndef TFS_PIPE_MASK
 #define TFS_PIPE_MASK 8
 #endif
-template <typename XT, int R, int BG, bool ABC_ONLY>
+template <typename XT, int R, int BG, int MODE>
 constexpr bool exp_pipe() {
-    const int bit = ABC_ONLY ? 16 : sizeof(XT) == 8 ? 1 : R == 8 ? 2 : BG == 2 ? 4 : 8;
+    const int bit = MODE == kModeAbc ? 16 : MODE == kModeF ? 32 : sizeof(XT) == 8 ? 1 : R == 8 ? 2 : BG == 2 ? 4 : 8;
     return (TFS_PIPE_MASK & bit) != 0;
 }
 
 // One (64-row tile, R-tau block, BG-bin group) task of the exponential map:
 // q indexes p.blk_list.  Every thread of the workgroup calls it.
-template <typename XT, int R, int BG, bool ABC_ONLY = false, typename PP>
+template <typename XT, int R, int BG, int MODE = kModeAll, typename PP>
 __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
                                                                ExpSmem<XT, R, BG> &sm, int q,
                                                                int row_tile, int bin_group) {
@@ -322,7 +336,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
     const XT *__restrict__ xg = xplane<XT>(p);
     const double *__restrict__ abc = p.at.abc;
 
-    ExpAcc<XT, R, BG, ABC_ONLY> acc;
+    ExpAcc<XT, R, BG, MODE> acc;
     acc.zero();
 
     constexpr int kStageLen = stage_len<XT, BG>();
@@ -336,17 +350,19 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
             for (int i = tid; i < width; i += kThreads) {
                 const int k = k_lo + d0 + i;
                 const bool in = (unsigned)k < (unsigned)K;
-                double a2 = 0.0, b2 = 0.0, ab = 0.0;
-                if (in) {
-                    const double2 v = *reinterpret_cast<const double2 *>(abc + (size_t)k * 4);
-                    a2 = v.x;
-                    b2 = v.y;
-                    ab = abc[(size_t)k * 4 + 2];
+                if constexpr (MODE != kModeF) {
+                    double a2 = 0.0, b2 = 0.0, ab = 0.0;
+                    if (in) {
+                        const double2 v = *reinterpret_cast<const double2 *>(abc + (size_t)k * 4);
+                        a2 = v.x;
+                        b2 = v.y;
+                        ab = abc[(size_t)k * 4 + 2];
+                    }
+                    sm.u.stage.a2[i] = a2;
+                    sm.u.stage.b2[i] = b2;
+                    sm.u.stage.ab[i] = ab;
                 }
-                sm.u.stage.a2[i] = a2;
-                sm.u.stage.b2[i] = b2;
-                sm.u.stage.ab[i] = ab;
-                if constexpr (!ABC_ONLY) {
+                if constexpr (MODE != kModeAbc) {
 #pragma unroll
                     for (int b = 0; b < BG; ++b) {
                         Q4<XT> x{XT(0), XT(0), XT(0), XT(0)};
@@ -360,7 +376,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
             const int per = (dn + kWaves - 1) / kWaves;
             const int ds = wave * per;
             const int de = min(dn, ds + per);
-            if constexpr (exp_pipe<XT, R, BG, ABC_ONLY>()) {
+            if constexpr (exp_pipe<XT, R, BG, MODE>()) {
                 // Software pipeline: the operands of step dd + 1 (weights by
                 // scalar loads, atoms from LDS) are fetched while the sums of
                 // step dd run.  Scalar loads complete out of order, so the
@@ -368,18 +384,18 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
                 // of each half-iteration, before the next step's fetch.
                 if (ds < de) {
                     StepOps<XT, R, BG> a, b;
-                    fetch_step<ABC_ONLY>(sm, gw_base, gq_base, my, d0, ds, a);
+                    fetch_step<MODE>(sm, gw_base, gq_base, my, d0, ds, a);
                     int dd = ds;
 #pragma unroll 1
                     for (; dd + 2 <= de; dd += 2) {
                         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
                         __builtin_amdgcn_sched_barrier(0);
-                        fetch_step<ABC_ONLY>(sm, gw_base, gq_base, my, d0, dd + 1, b);
+                        fetch_step<MODE>(sm, gw_base, gq_base, my, d0, dd + 1, b);
                         __builtin_amdgcn_sched_barrier(0);
                         acc.step(a.w, a.q, a.a2, a.b2, a.ab, a.x);
                         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
                         __builtin_amdgcn_sched_barrier(0);
-                        fetch_step<ABC_ONLY>(sm, gw_base, gq_base, my, d0, min(dd + 2, de - 1), a);
+                        fetch_step<MODE>(sm, gw_base, gq_base, my, d0, min(dd + 2, de - 1), a);
                         __builtin_amdgcn_sched_barrier(0);
                         acc.step(b.w, b.q, b.a2, b.b2, b.ab, b.x);
                     }
@@ -389,7 +405,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
                 for (int dd = ds; dd < de; ++dd) {
                     const int li = my + dd;
                     Q4<XT> x[BG];
-                    if constexpr (!ABC_ONLY) {
+                    if constexpr (MODE != kModeAbc) {
 #pragma unroll
                         for (int b = 0; b < BG; ++b) x[b] = sm.u.stage.x[b][li];
                     }
@@ -413,7 +429,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
             a2 = v.x;
             b2 = v.y;
             ab = abc[(size_t)kk * 4 + 2];
-            if constexpr (!ABC_ONLY) {
+            if constexpr (MODE != kModeAbc) {
 #pragma unroll
                 for (int b = 0; b < BG; ++b)
                     x[b] = (bin0 + b < n_bins) ? load_q4(xg + ((size_t)kk * n_bins + bin0 + b) * 4)
@@ -468,15 +484,18 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
         const int64_t span = 3 * tau;
         const int64_t lmn = span > rp.delta ? (span - rp.delta + T - 1) / T : 0;
         const int lc = p.lcol[nn];
-        double A = sm.u.comb.abc[0][r][0][lane];
-        double B = sm.u.comb.abc[0][r][1][lane];
-        double C = sm.u.comb.abc[0][r][2][lane];
+        double A = 0.0, B = 0.0, C = 0.0;
+        if constexpr (MODE != kModeF) {
+            A = sm.u.comb.abc[0][r][0][lane];
+            B = sm.u.comb.abc[0][r][1][lane];
+            C = sm.u.comb.abc[0][r][2][lane];
+        }
         double f[BG][4];
 #pragma unroll
         for (int b = 0; b < BG; ++b)
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                f[b][c] = ABC_ONLY ? 0.0 : (double)sm.u.comb.f[0][r][b][c][lane];
+                f[b][c] = MODE == kModeAbc ? 0.0 : (double)sm.u.comb.f[0][r][b][c][lane];
         // The table holds the shortest band over all rows of the grid; a row
         // whose band reaches further (smaller delta) adds its last terms
         // here, in FP64, with weights exp(-d T / tau).  (Shape windows have
@@ -486,13 +505,15 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
             const int64_t k = (int64_t)rp.k0 + d;
             if (k < 0) continue;
             const double gd = exp(-(double)(d * T) / (double)tau);
-            const double qd = gd * gd;
-            A += qd * abc[k * 4 + 0];
-            B += qd * abc[k * 4 + 1];
-            C += qd * abc[k * 4 + 2];
+            if constexpr (MODE != kModeF) {
+                const double qd = gd * gd;
+                A += qd * abc[k * 4 + 0];
+                B += qd * abc[k * 4 + 1];
+                C += qd * abc[k * 4 + 2];
+            }
 #pragma unroll
             for (int b = 0; b < BG; ++b) {
-                if (ABC_ONLY || bin0 + b >= n_bins) continue;
+                if (MODE == kModeAbc || bin0 + b >= n_bins) continue;
                 const Q4<XT> x = load_q4(xg + ((size_t)k * n_bins + bin0 + b) * 4);
                 f[b][0] += gd * (double)x.x;
                 f[b][1] += gd * (double)x.y;
@@ -509,7 +530,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
 #pragma unroll
                 for (int c = 0; c < 4; ++c) f[b][c] *= s;
         }
-        if constexpr (ABC_ONLY) {
+        if constexpr (MODE == kModeAbc) {
             if (ok) {
                 double *o = p.abc_out + ((size_t)m * p.abc_pitch + n) * 3;
                 o[0] = A;
@@ -517,6 +538,13 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
                 o[2] = C;
             }
             continue;
+        }
+        if constexpr (MODE == kModeF) {
+            // A, B, C of the cell (scaled, exact band) from the A/B/C-only pass
+            const double *o = p.abc_out + ((size_t)m * p.abc_pitch + nn) * 3;
+            A = o[0];
+            B = o[1];
+            C = o[2];
         }
 #pragma unroll
         for (int b = 0; b < BG; ++b) {
@@ -527,7 +555,7 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
             red_add(red[b], 0.5 * v, (long long)m * p.n_tau + n);
         }
     }
-    if constexpr (ABC_ONLY) return;
+    if constexpr (MODE == kModeAbc) return;
 #pragma unroll
     for (int b = 0; b < BG; ++b) {
         const Red w = red_wave(red[b]);
@@ -545,13 +573,15 @@ __device__ __attribute__((always_inline)) inline void exp_tile(PP &p,
 }
 
 // Waves per SIMD each exponential tile shape is built for.
-template <typename XT, int R, int BG, bool ABC_ONLY>
+template <typename XT, int R, int BG, int MODE>
 constexpr int exp_waves() {
-    return ABC_ONLY ? 5 : (sizeof(XT) == 8 ? 5 : (R == 8 ? 4 : (BG == 4 ? 3 : 5)));
+    return MODE == kModeAbc ? 5
+           : MODE == kModeF ? 3
+           : (sizeof(XT) == 8 ? 5 : (R == 8 ? 4 : (BG == 4 ? 3 : 5)));
 }
 
-template <typename XT, int R, int BG, bool ABC_ONLY = false>
-__global__ __launch_bounds__(kThreads, (exp_waves<XT, R, BG, ABC_ONLY>())) void exp_valu_kernel(ExpValuParams p) {
+template <typename XT, int R, int BG, int MODE = kModeAll>
+__global__ __launch_bounds__(kThreads, (exp_waves<XT, R, BG, MODE>())) void exp_valu_kernel(ExpValuParams p) {
     __shared__ ExpSmem<XT, R, BG> sm;
     // XCD-aware task order: workgroup b runs on XCD b % 8.  Blocks of tau
     // (sorted largest band first) are dealt round-robin to the XCDs and all
@@ -562,7 +592,7 @@ __global__ __launch_bounds__(kThreads, (exp_waves<XT, R, BG, ABC_ONLY>())) void 
     const int slot = bid >> 3;
     const int q = (slot / p.n_row_tiles) * 8 + xcd;
     if (q >= p.n_list) return;
-    exp_tile<XT, R, BG, ABC_ONLY>(p, sm, q, slot % p.n_row_tiles, blockIdx.y);
+    exp_tile<XT, R, BG, MODE>(p, sm, q, slot % p.n_row_tiles, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1265,7 +1295,16 @@ hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s) {
     if (p.n_list <= 0) return hipSuccess;
     const int groups = (p.n_list + 7) / 8;
     const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), 1u);
-    hipLaunchKernelGGL((exp_valu_kernel<float, 8, 1, true>), grid, dim3(kThreads), 0, s, p);
+    hipLaunchKernelGGL((exp_valu_kernel<float, 8, 1, kModeAbc>), grid, dim3(kThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp_fonly(const ExpValuParams &p, int n_groups, hipStream_t s) {
+    if (p.n_list <= 0 || n_groups <= 0) return hipSuccess;
+    if (p.bin_base + (n_groups - 1) * 4 >= p.at.n_bins || !p.abc_out) return hipErrorInvalidValue;
+    const int groups = (p.n_list + 7) / 8;
+    const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), (unsigned)n_groups);
+    hipLaunchKernelGGL((exp_valu_kernel<float, 8, 4, kModeF>), grid, dim3(kThreads), 0, s, p);
     return hipGetLastError();
 }
 

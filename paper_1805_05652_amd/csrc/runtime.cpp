@@ -762,7 +762,10 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, false);
 
         tfs::ExpValuParams p = exp_params(j);
-        if (j.n_valu > 0) {
+        // with matrix-core blocks, the VALU blocks take A/B/C from the A/B/C
+        // pass (which then covers every block) and sum only F_a, F_b
+        const bool split_abc = j.use_mfma && j.n_mfma > 0;
+        if (j.n_valu > 0 && !split_abc) {
             record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
             auto launch = j.runs ? tfs::launch_exp_runs : tfs::launch_exp_valu;
             const int pr = wants64(j) ? 0 : 1;
@@ -776,14 +779,23 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         }
         if (j.n_mfma > 0) {
             tfs::ExpValuParams pa = p;
-            pa.n_list = j.n_mfma;
-            pa.blk_list = p.blk_list + j.n_valu;
+            pa.n_list = j.n_valu + j.n_mfma;
             pa.twoF = nullptr;
             pa.abc_out = ws_ptr<double>(j, j.off_abc);
             pa.abc_pitch = abc_pitch(n_tau);
             record_kernel(ctx, j, TFSTAT_K_ABC, s, true);
             hip_check(tfs::launch_exp_abc(pa, s), "exp abc kernel");
             record_kernel(ctx, j, TFSTAT_K_ABC, s, false);
+            pa.blk_list = p.blk_list + j.n_valu;   // the matrix-core blocks
+            pa.n_list = j.n_mfma;
+            if (j.n_valu > 0) {
+                tfs::ExpValuParams pf = p;
+                pf.abc_out = ws_ptr<double>(j, j.off_abc);
+                pf.abc_pitch = abc_pitch(n_tau);
+                record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
+                hip_check(tfs::launch_exp_fonly(pf, (at.n_bins + 3) / 4, s), "exp F kernel");
+                record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
+            }
             tfs::ExpMfmaParams q{};
             q.n_bins = at.n_bins;
             q.bins16 = at.bins16;

@@ -275,6 +275,10 @@ hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, int 
 hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, int n_groups,
                            hipStream_t s);
 // A/B/C only (FP64), R = 8 blocks, into p.abc_out.
+// F_a, F_b only, R = 8 blocks, four bins per lane, n_groups bin groups from
+// p.bin_base; A, B, C of every cell read from p.abc_out (short-band blocks
+// of the matrix-core form).
+hipError_t launch_exp_fonly(const ExpValuParams &p, int n_groups, hipStream_t s);
 hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s);
 hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s);
 hipError_t launch_exp_recur(const RecurParams &p, int BG, hipStream_t s);
