@@ -216,6 +216,9 @@ def serving(ctx, seed: int = 4000, rate_hz: float = 200.0, duration_s: float = 4
                                  "p50_ms": float(np.percentile(lat1, 50)),
                                  "p99_ms": float(np.percentile(lat1, 99))},
         "sequential_fp32": {"maps_per_s": len(jobs) / sum(svc),
+                            "service_s_by_window": {
+                                k: float(sum(sv for (_, _, w, _), sv in zip(jobs, svc) if w.kind == k))
+                                for k in ("rect", "exp")},
                             "p50_ms": float(np.percentile(seq_lat, 50)),
                             "p99_ms": float(np.percentile(seq_lat, 99))},
         "workload": "Poisson %.0f/s for %.1f s; slots log-uniform [200, %d], grids U{100..%d}, "

@@ -292,12 +292,13 @@ __device__ __attribute__((always_inline)) inline void fetch_step(const SM &sm, c
 }
 
 // Shapes whose staged band loop is software-pipelined: bit 1 FP64, 2 FP32
-// R = 8, 4 FP32 R = 4 BG = 2, 8 FP32 R = 4 BG = 4, 16 A/B/C only, 32 F only.  Only the
-// four-bin shape has the registers for a second operand set at its
-// occupancy (measured: faster in the fused batch kernel, about even in
-// the stand-alone kernel).
+// R = 8, 4 FP32 R = 4 BG = 2, 8 FP32 R = 4 BG = 4, 16 A/B/C only, 32 F
+// only.  The four-bin shape and the A/B/C pass have the registers for a
+// second operand set at their occupancy (measured: the four-bin shape
+// faster in the fused batch kernel and about even alone, the A/B/C pass a
+// third faster); the others would spill or lose a wave per SIMD.
 #ifndef TFS_PIPE_MASK
-#define TFS_PIPE_MASK 8
+#define TFS_PIPE_MASK 24
 #endif
 template <typename XT, int R, int BG, int MODE>
 constexpr bool exp_pipe() {
