@@ -615,7 +615,8 @@ template <typename XT, int BG>
 struct RunCfg {
     static constexpr int kCpb = (int)sizeof(XT) / 4;        // 16-byte chunks per bin and slot
     static constexpr int kNC = 2 + BG * kCpb;               // chunk arrays: (a2, b2), (ab, 0), data
-    static constexpr int kG = kNC == 3 ? 8 : 4;             // slots per run and round (LDS: 24 or 16-24 KB)
+    static constexpr int kG = kNC == 3 ? 8 : 4;             // slots per run and round (runs: 24 KB for
+                                                            // one FP32 bin, 16 KB for the others)
     static constexpr int kSh = kG == 8 ? 1 : 2;             // LDS swizzle: rows per rotation step
     static constexpr int kPer = kLanes * kG * kNC / kThreads;   // chunks each thread loads per round
     static_assert(kLanes * kG * kNC % kThreads == 0, "whole chunks per thread");
