@@ -246,23 +246,31 @@ int tfstat_serve_config(tfstat_ctx *ctx, int32_t max_batch);
 
 /*
  * Tiling of exponential-window maps (section 3: every cell sums its own
- * window).  The VALU sums take 64 t0 rows at a time.  When the rows of a
- * tile start far apart in slot space (a t0 step of many SFTs), the union of
- * their windows does not fit one shared-memory stage; such maps stage each
- * row's own run of slots instead, four tau blocks per workgroup ("runs"
- * form).  A map takes the runs form when the median over its 64-row tiles
- * of the slot span between first and last row is at least runs_min_spread
- * (0 sends every map there).  A negative value restores the default: the
- * runs form when that span exceeds 448 slots, what the band stage holds,
- * for maps with two or more bins per lane or FP64 sums (FP32 maps with one
- * bin stay on the band-staged form, which reads such rows through the
- * caches).  Both forms sum the same terms with the same weights (the
- * other form splits each band over four waves, this one does not), so they
- * agree within rounding; the choice is made when a map is planned
- * (tfstat_fmap, tfstat_submit, tfstat_batch_create), so a map gives the
- * same results alone, batched and served.  Errors: E_INVAL for a null ctx.
+ * window).  The VALU sums take 64 t0 rows at a time.
+ *
+ * Runs form.  When the rows of a tile start far apart in slot space (a t0
+ * step of many SFTs), the union of their windows does not fit one
+ * shared-memory stage; such maps stage each row's own run of slots instead,
+ * four tau blocks per workgroup.  A map takes the runs form when the median
+ * over its 64-row tiles of the slot span between first and last row is at
+ * least runs_min_spread (0 sends every map there).  A negative value
+ * restores the default: the runs form when that span exceeds 448 slots,
+ * what the band stage holds, for maps with two or more bins per lane or
+ * FP64 sums (FP32 maps with one bin stay on the band-staged form, which
+ * reads such rows through the caches).
+ *
+ * Split form.  An FP32 map with at least split_min_bins bins (default 8;
+ * 0: never; a negative value restores the default) whose tiles fit the band
+ * stage computes A, B, C of every cell once, in FP64, and then sums only
+ * F_a, F_b, four bins per lane; otherwise every group of bins sums A, B, C
+ * again.  An explicit runs_min_spread that the map reaches takes precedence.
+ *
+ * Every form sums the same terms with the same weights, so they agree
+ * within rounding.  The choice is made when a map is planned (tfstat_fmap,
+ * tfstat_submit, tfstat_batch_create), so a map gives the same results
+ * alone, batched and served.  Errors: E_INVAL for a null ctx.
  */
-int tfstat_tiling_config(tfstat_ctx *ctx, int32_t runs_min_spread);
+int tfstat_tiling_config(tfstat_ctx *ctx, int32_t runs_min_spread, int32_t split_min_bins);
 
 /*
  * Uneven batch: many maps -- different resident atoms, grids, numbers of

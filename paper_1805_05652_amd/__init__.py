@@ -205,11 +205,13 @@ class Context:
         """Requests admitted together into one fused batch, at most."""
         _abi.check(self._lib.tfstat_serve_config(self._ctx, int(max_batch)))
 
-    def tiling_config(self, runs_min_spread: int = -1):
-        """Exponential maps whose 64-row t0 tiles span at least this many
-        slots (median) use the runs form; 0 = every map, -1 = automatic (when
-        the span exceeds the band stage, except one-bin FP32 maps)."""
-        _abi.check(self._lib.tfstat_tiling_config(self._ctx, int(runs_min_spread)))
+    def tiling_config(self, runs_min_spread: int = -1, split_min_bins: int = -1):
+        """Exponential maps whose 64-row t0 tiles span at least
+        runs_min_spread slots (median) use the runs form (0 = every map, -1 =
+        automatic: when the span exceeds the band stage, except one-bin FP32
+        maps); FP32 maps with at least split_min_bins bins use the split form
+        (0 = never, -1 = default 8)."""
+        _abi.check(self._lib.tfstat_tiling_config(self._ctx, int(runs_min_spread), int(split_min_bins)))
 
     # -- uneven batch ----------------------------------------------------------------
     def batch(self, items, precision="fp32", tune: bool = False) -> "Batch":

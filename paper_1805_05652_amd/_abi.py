@@ -104,7 +104,7 @@ SIGNATURES = {
     "tfstat_poll": (ctypes.c_int, [_P, _U64, ctypes.POINTER(BinResult), ctypes.POINTER(ctypes.c_int)]),
     "tfstat_cancel": (ctypes.c_int, [_P, _U64]),
     "tfstat_serve_config": (ctypes.c_int, [_P, _I32]),
-    "tfstat_tiling_config": (ctypes.c_int, [_P, _I32]),
+    "tfstat_tiling_config": (ctypes.c_int, [_P, _I32, _I32]),
     "tfstat_batch_create": (ctypes.c_int, [_P, _I32, ctypes.POINTER(_U64), ctypes.POINTER(Window), _I32,
                                            _I32, ctypes.POINTER(_P)]),
     "tfstat_batch_run": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(BinResult)]),

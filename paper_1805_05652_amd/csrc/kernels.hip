@@ -1108,6 +1108,13 @@ __global__ __launch_bounds__(256) void merge_batch_kernel(MergeBatchParams p) {
     merge_map(const_params(p.jobs + p.job[e]), p.map[e], sred);
 }
 
+// A/B/C pre-pass of a batch: one (64-row tile, tau block) per workgroup.
+__global__ __launch_bounds__(kThreads, (exp_waves<float, 8, 1, kModeAbc>())) void abc_batch_kernel(AbcBatchParams p) {
+    __shared__ ExpSmem<float, 8, 1> sm;
+    const int e = blockIdx.x;
+    exp_tile<float, 8, 1, kModeAbc>(const_params(p.jobs + p.job[e]), sm, p.x[e], p.y[e], 0);
+}
+
 __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *dst, int32_t n, int32_t value) {
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) dst[i] = value;
 }
@@ -1121,15 +1128,18 @@ __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *dst, int32_t n, 
 // ---------------------------------------------------------------------------
 template <int V>
 struct FusedSmem {
-    static constexpr size_t exp_bytes =
-        V == kShapeD41   ? sizeof(ExpSmem<double, 4, 1>)
-        : V == kShapeF81 ? sizeof(ExpSmem<float, 8, 1>)
-        : V == kShapeF42 ? sizeof(ExpSmem<float, 4, 2>)
-        : V == kShapeF44 ? sizeof(ExpSmem<float, 4, 4>)
-                         : (sizeof(ExpSmem<float, 4, 4>) > sizeof(ExpSmem<double, 4, 1>)
-                                ? sizeof(ExpSmem<float, 4, 4>)
-                                : sizeof(ExpSmem<double, 4, 1>));
-    static constexpr size_t bytes = exp_bytes > sizeof(Red) * kWaves ? exp_bytes : sizeof(Red) * kWaves;
+    static constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+    // FP32 variants also run F_a/F_b-only tiles (8 taus, bin pairs: the
+    // same sums as the stand-alone kernel's four bins per lane, in fewer
+    // registers)
+    static constexpr size_t fonly = V == kShapeD41 ? 0 : sizeof(ExpSmem<float, 8, 2>);
+    static constexpr size_t exp_bytes = cmax(
+        fonly, V == kShapeD41   ? sizeof(ExpSmem<double, 4, 1>)
+               : V == kShapeF81 ? sizeof(ExpSmem<float, 8, 1>)
+               : V == kShapeF42 ? sizeof(ExpSmem<float, 4, 2>)
+               : V == kShapeF44 ? sizeof(ExpSmem<float, 4, 4>)
+                                : cmax(sizeof(ExpSmem<float, 4, 4>), sizeof(ExpSmem<double, 4, 1>)));
+    static constexpr size_t bytes = cmax(exp_bytes, sizeof(Red) * kWaves);
 };
 static_assert(sizeof(RunSmem<double, 4, 1>) <= sizeof(ExpSmem<double, 4, 1>) &&
                   sizeof(RunSmem<float, 8, 1>) <= sizeof(ExpSmem<float, 8, 1>) &&
@@ -1209,6 +1219,12 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
             continue;
         }
         auto &ep = const_params(p.exp_jobs + t.job);
+        if constexpr (V != kShapeD41) {
+            if (t.kind == 3) {
+                exp_tile<float, 8, 2, kModeF>(ep, *reinterpret_cast<ExpSmem<float, 8, 2> *>(smem), t.x, t.y, t.z);
+                continue;
+            }
+        }
         if (t.kind == 2) {
             if constexpr (V == kShapeMixed) {
                 switch (t.shape) {
@@ -1384,6 +1400,12 @@ hipError_t launch_weights_batch(const WeightBatchParams &p, hipStream_t s) {
     if (p.chunks < 1 || p.chunks > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(weights_batch_kernel, dim3((unsigned)p.n_entries, (unsigned)p.chunks), dim3(256), 0,
                        s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_abc_batch(const AbcBatchParams &p, hipStream_t s) {
+    if (p.n_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(abc_batch_kernel, dim3((unsigned)p.n_entries), dim3(kThreads), 0, s, p);
     return hipGetLastError();
 }
 

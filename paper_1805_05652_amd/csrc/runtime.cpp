@@ -249,6 +249,9 @@ constexpr int kMfmaMinBand = 64;   // shorter bands stay on the VALU path
 // kRunsAuto sends a map to the runs form when its median 64-row tile spans
 // more slots than one LDS stage can stage in rounds of kExpMinStageRound.
 constexpr int32_t kRunsAuto = -1;
+// FP32 maps with at least this many bins (and rows close enough for the band
+// stage) take the split form: A/B/C pass, then F_a/F_b-only tiles.
+constexpr int32_t kSplitMinBins = 8;
 
 // ---------------------------------------------------------------------------
 // One map computation: plan (host, integer), workspace, launches, results.
@@ -267,6 +270,10 @@ struct Job {
     int force_R = 0, force_BG = 0;   // exponential VALU tile shape chosen by the caller
     int32_t runs_min_spread = kRunsAuto;   // see tfstat_tiling_config
     bool runs = false;         // VALU blocks by the runs form (t0 rows far apart)
+    int32_t split_min_bins = kSplitMinBins;     // see tfstat_tiling_config
+    // A/B/C once per cell in an FP64 pass, then F_a, F_b only with four bins
+    // per lane (FP32 maps with many bins and rows close together)
+    bool split = false;
     // bin groups of BG bins; with four-bin groups and one or two bins left
     // over, those take one two-bin group after the n_groups full ones
     int n_groups = 0;
@@ -367,6 +374,15 @@ void plan_job(Job &j) {
         j.n_tiles = n_tau;
     } else if (is_exp) {
         const int prec = (j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_RECUR64) ? 0 : 1;
+        // median slot span of the 64-row tiles (tile form choice below)
+        int64_t med;
+        {
+            std::vector<int64_t> spread(j.n_row_tiles);
+            for (int t = 0; t < j.n_row_tiles; ++t)
+                spread[t] = (int64_t)j.rows[std::min(t * 64 + 63, n_t0 - 1)].k0 - j.rows[t * 64].k0;
+            std::nth_element(spread.begin(), spread.begin() + j.n_row_tiles / 2, spread.end());
+            med = spread[j.n_row_tiles / 2];
+        }
         tfs::exp_valu_config(prec, at.n_bins, &j.R, &j.BG);
         if (j.force_R) {
             j.R = j.force_R;
@@ -376,8 +392,17 @@ void plan_job(Job &j) {
             j.R = kMfmaTaus;
             j.BG = 1;
         }
+        // the split form (its own tile shape in every batch variant); an
+        // explicit runs threshold that the map reaches takes precedence
+        const bool runs_forced = j.runs_min_spread >= 0 && med >= j.runs_min_spread;
+        j.split = prec == 1 && !j.use_mfma && !runs_forced && j.split_min_bins > 0 &&
+                  at.n_bins >= j.split_min_bins && med <= tfs::exp_stage_len(1, 4) - tfs::kExpMinStageRound;
+        if (j.split) {
+            j.R = kMfmaTaus;
+            j.BG = 4;
+        }
         j.NB = (n_tau + j.R - 1) / j.R;
-        j.tail2 = j.BG == 4 && (at.n_bins % 4 == 1 || at.n_bins % 4 == 2);
+        j.tail2 = j.BG == 4 && !j.split && (at.n_bins % 4 == 1 || at.n_bins % 4 == 2);
         j.n_groups = j.tail2 ? at.n_bins / 4 : (at.n_bins + j.BG - 1) / j.BG;
         j.lblk.assign(j.NB, 0);
         j.blk_off.assign(j.NB, 0);
@@ -399,12 +424,7 @@ void plan_job(Job &j) {
         j.n_tiles = j.NB * j.n_row_tiles;
         j.n_valu = j.NB;
         j.n_mfma = 0;
-        {
-            std::vector<int64_t> spread(j.n_row_tiles);
-            for (int t = 0; t < j.n_row_tiles; ++t)
-                spread[t] = (int64_t)j.rows[std::min(t * 64 + 63, n_t0 - 1)].k0 - j.rows[t * 64].k0;
-            std::nth_element(spread.begin(), spread.begin() + j.n_row_tiles / 2, spread.end());
-            const int64_t med = spread[j.n_row_tiles / 2];
+        if (!j.split) {
             // automatic: the runs form where the band stage would fall back
             // to per-lane reads through the caches, except for the 8-tau
             // one-bin shape, whose 32-tau runs tiles leave too few
@@ -486,6 +506,7 @@ void plan_job(Job &j) {
             j.off_abc = take(sizeof(double) * 3 * (size_t)n_t0 * abc_pitch(n_tau));
             j.off_gsh = take(sizeof(unsigned short) * (size_t)j.gsh_total);
         }
+        if (j.split) j.off_abc = take(sizeof(double) * 3 * (size_t)n_t0 * abc_pitch(n_tau));
     } else {
         j.off_pabc = take(sizeof(double) * 8 * ((size_t)at.K + 1));
         j.off_px = take(sizeof(double) * 8 * (size_t)at.n_bins * ((size_t)at.K + 1));
@@ -560,6 +581,7 @@ struct tfstat_ctx {
     hipEvent_t slot_done[kSlots] = {nullptr};
     int serve_max_batch = 16;                           // requests fused into one launch at most
     std::atomic<int32_t> runs_min_spread{kRunsAuto};   // see tfstat_tiling_config
+    std::atomic<int32_t> split_min_bins{kSplitMinBins};
     std::thread worker;
     std::condition_variable cv;
     bool stop = false;
@@ -686,6 +708,10 @@ tfs::ExpValuParams exp_params(Job &j) {
     p.twoF = j.twoF;
     p.part = ws_ptr<tfs::Partial>(j, j.off_part);
     p.abc_out = nullptr;
+    if (j.split) {
+        p.abc_out = ws_ptr<double>(j, j.off_abc);
+        p.abc_pitch = abc_pitch((int32_t)j.win.tau.size());
+    }
     p.scale_rows = j.win.type == TFSTAT_WIN_EXP ? 1 : 0;
     return p;
 }
@@ -764,7 +790,18 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
         tfs::ExpValuParams p = exp_params(j);
         // with matrix-core blocks, the VALU blocks take A/B/C from the A/B/C
         // pass (which then covers every block) and sum only F_a, F_b
-        const bool split_abc = j.use_mfma && j.n_mfma > 0;
+        const bool split_abc = (j.use_mfma && j.n_mfma > 0) || j.split;
+        if (j.split) {
+            // A, B, C of every cell, then F_a, F_b only, four bins per lane
+            tfs::ExpValuParams pa = p;
+            pa.twoF = nullptr;
+            record_kernel(ctx, j, TFSTAT_K_ABC, s, true);
+            hip_check(tfs::launch_exp_abc(pa, s), "exp abc kernel");
+            record_kernel(ctx, j, TFSTAT_K_ABC, s, false);
+            record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
+            hip_check(tfs::launch_exp_fonly(p, j.n_groups, s), "exp F kernel");
+            record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
+        }
         if (j.n_valu > 0 && !split_abc) {
             record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
             auto launch = j.runs ? tfs::launch_exp_runs : tfs::launch_exp_valu;
@@ -952,6 +989,7 @@ struct tfstat_batch {
     const tfs::ScanJob *scan_jobs = nullptr;
     int n_scan = 0;
     tfs::MergeBatchParams mbp{};
+    tfs::AbcBatchParams abp{};       // A/B/C pre-pass of the split-form maps
     tfs::BinResultDev *res_dev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1010,7 +1048,7 @@ int job_shape(const Job &j) {
 bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bool have_lock) {
     const int32_t n = (int32_t)b->jobs.size();
     std::vector<int> shape(n, -1), eidx(n, -1), ridx(n, -1);
-    int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0;
+    int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0, n_abc = 0;
     int32_t max_chunks = 1;
     b->res_off.assign(n, 0);
     b->n_results = 0;
@@ -1020,6 +1058,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             shape[i] = job_shape(j);
             eidx[i] = n_exp++;
             n_went += j.NB;
+            if (j.split) n_abc += j.n_valu * j.n_row_tiles;
             max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
         } else {
             ridx[i] = n_rect++;
@@ -1041,12 +1080,15 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
         if (eidx[i] >= 0) {
-            const size_t per = (size_t)j.n_row_tiles * (j.n_groups + (j.tail2 ? 1 : 0));
+            // split maps: F_a/F_b-only tiles of bin pairs
+            const int bgs = j.split ? (j.at->n_bins + 1) / 2 : j.n_groups + (j.tail2 ? 1 : 0);
+            const size_t per = (size_t)j.n_row_tiles * bgs;
             // a runs tile takes four blocks, each over its whole band on one
             // wave: about four times the time of one block's tile
             const int step = j.runs ? 4 : 1;
+            const int per_step = j.split ? 4 * 2 : 3 + 4 * j.BG;   // FMAs per lane, slot and tau
             for (int q = 0; q < j.n_valu; q += step)
-                groups_e.push_back({i, q, (double)(j.lblk[j.order[q]] + 1) * j.R * (3 + 4 * j.BG) * step});
+                groups_e.push_back({i, q, (double)(j.lblk[j.order[q]] + 1) * j.R * per_step * step});
             n_tiles_total += per * ((j.n_valu + step - 1) / step);
         } else {
             const int nby = ((int)j.win.t0.size() + 3) / 4;
@@ -1061,9 +1103,10 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     tiles.reserve(n_tiles_total);
     for (const Group &g : groups_e) {
         const Job &j = *b->jobs[g.map];
-        const int kind = j.runs ? 2 : 0;
+        const int kind = j.runs ? 2 : (j.split ? 3 : 0);
+        const int ng = j.split ? (j.at->n_bins + 1) / 2 : j.n_groups;
         for (int rt = 0; rt < j.n_row_tiles; ++rt) {
-            for (int gidx = 0; gidx < j.n_groups; ++gidx)
+            for (int gidx = 0; gidx < ng; ++gidx)
                 tiles.push_back(tfs::BatchTile{kind, eidx[g.map], g.q, rt, gidx, shape[g.map]});
             // the bin pair after the four-bin groups: group index in pairs
             if (j.tail2)
@@ -1102,6 +1145,9 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     const size_t off_mjob = take(sizeof(int32_t) * b->n_results);
     const size_t off_mmap = take(sizeof(int32_t) * b->n_results);
     const size_t off_tiles = take(sizeof(tfs::BatchTile) * tiles.size());
+    const size_t off_ajob = take(sizeof(int32_t) * n_abc);
+    const size_t off_ax = take(sizeof(int32_t) * n_abc);
+    const size_t off_ay = take(sizeof(int32_t) * n_abc);
     const size_t desc_end = o;
     const size_t off_counter = take(sizeof(int32_t));
     const size_t off_res = take(sizeof(tfs::BinResultDev) * b->n_results);
@@ -1136,7 +1182,10 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     auto *mjob = reinterpret_cast<int32_t *>(hptr(off_mjob));
     auto *mmap = reinterpret_cast<int32_t *>(hptr(off_mmap));
     auto *tl = reinterpret_cast<tfs::BatchTile *>(hptr(off_tiles));
-    int we = 0, se = 0, me = 0;
+    auto *ajob = reinterpret_cast<int32_t *>(hptr(off_ajob));
+    auto *ax = reinterpret_cast<int32_t *>(hptr(off_ax));
+    auto *ay = reinterpret_cast<int32_t *>(hptr(off_ay));
+    int we = 0, se = 0, me = 0, ae = 0;
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
         if (eidx[i] >= 0) {
@@ -1146,6 +1195,16 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
                 wjob[we] = eidx[i];
                 wblk[we] = nb;
                 ++we;
+            }
+            if (j.split) {
+                // longest bands first, as in the tile list
+                for (int q = 0; q < j.n_valu; ++q)
+                    for (int rt = 0; rt < j.n_row_tiles; ++rt) {
+                        ajob[ae] = eidx[i];
+                        ax[ae] = q;
+                        ay[ae] = rt;
+                        ++ae;
+                    }
             }
         } else {
             rp[ridx[i]] = rect_params(j);
@@ -1178,6 +1237,11 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     b->wbp.chunks = max_chunks;
     b->scan_jobs = reinterpret_cast<const tfs::ScanJob *>(dptr(off_scan));
     b->n_scan = n_scan;
+    b->abp.jobs = b->fp.exp_jobs;
+    b->abp.job = reinterpret_cast<const int32_t *>(dptr(off_ajob));
+    b->abp.x = reinterpret_cast<const int32_t *>(dptr(off_ax));
+    b->abp.y = reinterpret_cast<const int32_t *>(dptr(off_ay));
+    b->abp.n_entries = n_abc;
     b->mbp.jobs = reinterpret_cast<const tfs::MergeParams *>(dptr(off_mp));
     b->mbp.job = reinterpret_cast<const int32_t *>(dptr(off_mjob));
     b->mbp.map = reinterpret_cast<const int32_t *>(dptr(off_mmap));
@@ -1229,6 +1293,7 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
             j.force_BG = BG;
         }
         j.runs_min_spread = ctx->runs_min_spread.load();
+        j.split_min_bins = ctx->split_min_bins.load();
         plan_job(j);
     }
     if (!batch_layout(ctx, b, ctx->batch_stream, true, false))
@@ -1242,6 +1307,7 @@ hipError_t batch_enqueue(tfstat_batch *b, hipStream_t s, bool timed) {
     hipError_t e = tfs::launch_fill_i32(b->fp.counter, 1, 0, s);
     if (e == hipSuccess) e = tfs::launch_weights_batch(b->wbp, s);
     if (e == hipSuccess) e = tfs::launch_scan_batch(b->scan_jobs, b->n_scan, s);
+    if (e == hipSuccess) e = tfs::launch_abc_batch(b->abp, s);
     if (e == hipSuccess && timed) e = hipEventRecord(b->evf0, s);
     if (e == hipSuccess) e = tfs::launch_fused(b->fp, b->variant, b->groups, s);
     if (e == hipSuccess && timed) e = hipEventRecord(b->evf1, s);
@@ -1700,6 +1766,7 @@ int tfstat_fmap(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win, i
         j.prec = precision;
         j.twoF = twoF_dev;
         j.runs_min_spread = ctx->runs_min_spread.load();
+        j.split_min_bins = ctx->split_min_bins.load();
         plan_job(j);
         {
             std::lock_guard<std::mutex> g(ctx->mu);
@@ -1788,6 +1855,7 @@ int tfstat_submit(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win,
         job->at = find_atoms(ctx, id);
         if (precision == TFSTAT_PREC_BF16X3) ensure_planes(ctx, job->at);
         job->runs_min_spread = ctx->runs_min_spread.load();
+        job->split_min_bins = ctx->split_min_bins.load();
         plan_job(*job);
         // A request whose workspace cannot fit beside the resident atoms
         // would wait forever: refuse it now.
@@ -1997,10 +2065,11 @@ int tfstat_serve_config(tfstat_ctx *ctx, int32_t max_batch) {
     });
 }
 
-int tfstat_tiling_config(tfstat_ctx *ctx, int32_t runs_min_spread) {
+int tfstat_tiling_config(tfstat_ctx *ctx, int32_t runs_min_spread, int32_t split_min_bins) {
     return guarded([&] {
         if (!ctx) raise(TFSTAT_E_INVAL, "ctx is null");
         ctx->runs_min_spread.store(runs_min_spread < 0 ? kRunsAuto : runs_min_spread);
+        ctx->split_min_bins.store(split_min_bins < 0 ? kSplitMinBins : split_min_bins);
         return (int)TFSTAT_OK;
     });
 }

@@ -204,7 +204,9 @@ inline void shape_dims(int shape, int *prec, int *R, int *BG) {
 constexpr int kRectRowBlocks = 4;   // 4-row rect blocks per batch tile (16 rows)
 
 struct BatchTile {
-    int32_t kind;    // 0: exponential, 1: rectangular, 2: exponential, rows far apart
+    int32_t kind;    // 0: exponential, 1: rectangular, 2: exponential, rows far apart,
+                     // 3: exponential F_a/F_b only (A, B, C from the A/B/C pre-pass;
+                     //    z counts bin pairs)
     int32_t job;     // index into FusedParams::exp_jobs or ::rect_jobs
     int32_t x;       // exp: position in blk_list (kind 2: first of four); rect: tau tile (64 taus)
     int32_t y;       // exp: 64-row tile; rect: first 4-row block / kRectRowBlocks
@@ -219,6 +221,17 @@ struct FusedParams {
     int32_t n_tiles;
     int32_t pad;
     int32_t *counter;         // next tile; zeroed before every launch
+};
+
+// A/B/C pre-pass of the maps whose tiles sum F_a, F_b only: entry i is
+// (64-row tile y[i], position x[i] in blk_list) of job job[i].
+struct AbcBatchParams {
+    const ExpValuParams *jobs;
+    const int32_t *job;
+    const int32_t *x;
+    const int32_t *y;
+    int32_t n_entries;
+    int32_t pad;
 };
 
 // Weight tables of many maps: entry i is block blk[i] of job job[i].
@@ -314,6 +327,7 @@ hipError_t launch_rect(const RectParams &p, hipStream_t s);
 hipError_t launch_merge(const MergeParams &p, hipStream_t s);
 hipError_t launch_map_reduce(const MapReduceParams &p, hipStream_t s);
 hipError_t launch_weights_batch(const WeightBatchParams &p, hipStream_t s);
+hipError_t launch_abc_batch(const AbcBatchParams &p, hipStream_t s);
 hipError_t launch_scan_batch(const ScanJob *jobs, int32_t n_jobs, hipStream_t s);
 hipError_t launch_merge_batch(const MergeBatchParams &p, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t n, int32_t value, hipStream_t s);

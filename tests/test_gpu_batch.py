@@ -17,6 +17,7 @@ import tfsynth
 
 pytestmark = pytest.mark.gpu
 
+T = tfsynth.T_SFT
 TOL = {"fp32": 1e-4, "fp64": 1e-9}
 
 
@@ -119,6 +120,35 @@ def test_batch_runs_form(ctx, prec):
             same_results(res, single)
     finally:
         ctx.tiling_config(-1)
+        for aid in ids:
+            ctx.free(aid)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_split_form(ctx, prec):
+    """Maps of 8 to 13 bins (FP32: the split form, an A/B/C pre-pass and
+    F_a/F_b-only tiles in the persistent launch; FP64: plain tiles) mixed
+    with rect maps: against the oracle and bit-identical to tfstat_fmap."""
+    _case("batch split form " + prec)
+    cands = []
+    for i in range(6):
+        atoms = tfsynth.make_atoms(7800 + i, 300 + 90 * i, 0.1 * (i % 3), n_bins=8 + i,
+                                   injections=[tfsynth.Injection(i % 4, "exp", 50 * T, 20 * T, 1.0)])
+        kind = "rect" if i % 3 == 2 else "exp"
+        win = tfsynth.regular_window(kind, 3 * T + 7 * i, T, 70 + 20 * i, 2 * T,
+                                     2 * T + 13 * i, 31 + 7 * i)
+        cands.append((atoms, win))
+    ids = upload_all(ctx, cands)
+    try:
+        with ctx.batch(list(zip(ids, [w for _, w in cands])), prec) as b:
+            got = b.run()
+            again = b.run()
+        for (atoms, win), aid, res, res2 in zip(cands, ids, got, again):
+            check_against_oracle(res, atoms, win, TOL[prec])
+            single, _ = ctx.fmap(aid, win, prec)
+            same_results(res, single)
+            same_results(res, res2)
+    finally:
         for aid in ids:
             ctx.free(aid)
 

@@ -40,16 +40,16 @@ RUNS_ALWAYS = 0        # tiling: every map on the runs form
 
 
 class tiling:
-    """Sets the exponential tiling threshold for the maps planned inside."""
+    """Sets the exponential tiling thresholds for the maps planned inside."""
 
-    def __init__(self, ctx, runs_min_spread):
-        self.ctx, self.v = ctx, runs_min_spread
+    def __init__(self, ctx, runs_min_spread, split_min_bins=-1):
+        self.ctx, self.v, self.s = ctx, runs_min_spread, split_min_bins
 
     def __enter__(self):
-        self.ctx.tiling_config(self.v)
+        self.ctx.tiling_config(self.v, self.s)
 
     def __exit__(self, *exc):
-        self.ctx.tiling_config(-1)
+        self.ctx.tiling_config(-1, -1)
 
 
 def check_map(got, ref, tol):
@@ -240,6 +240,46 @@ def test_exp_forms_agree(ctx):
         d, r = out["dense"][1], out["runs"][1]
         assert np.all((d == 0) == (r == 0))
         assert np.max(np.abs(d - r) / np.maximum(np.abs(d), 1.0)) <= 2e-4
+    finally:
+        ctx.free(aid)
+
+
+@pytest.mark.parametrize("case", ["bins8", "bins9", "bins12", "ragged12", "shape10", "tail"])
+def test_exp_split_form(ctx, case):
+    """The split form (A, B, C once per cell, then F_a, F_b four bins per
+    lane) against the oracle: 8, 9 and 12 bins (a partial last group), t0
+    off the slot grid and before/after the data, shape windows, and bands
+    reaching past the data end; also against the form without the split."""
+    _case("exp split form " + case)
+    if case.startswith("bins"):
+        n_bins = int(case[4:])
+        atoms = tfsynth.make_atoms(240 + n_bins, 420, 0.12, n_bins=n_bins,
+                                   injections=[tfsynth.Injection(3, "exp", 90 * T, 25 * T, 1.0)])
+        win = tfsynth.regular_window("exp", 7 + 2 * T, T, 150, 2 * T, 3 * T + 11, 43)
+    elif case == "ragged12":
+        atoms = tfsynth.make_atoms(251, 300, 0.2, n_bins=12)
+        rng = np.random.default_rng(25)
+        t0 = np.unique(np.concatenate([[-5 * T - 77, -T, -1, 0, 1, T - 1],
+                                       rng.integers(0, 300 * T, size=120), [299 * T + 1, 300 * T + 5]]))
+        tau = np.unique(np.concatenate([[1, T - 1, T, 2 * T], rng.integers(2 * T, 200 * T, size=29),
+                                        [300 * T, 1000 * T]]))
+        win = tfsynth.list_window("exp", t0, tau)
+    elif case == "shape10":
+        atoms = tfsynth.make_atoms(252, 500, 0.1, n_bins=10)
+        win = _bump_window(tfsynth.regular_window("exp", 100, 2 * T, 140, 2 * T, 5 * T + 7, 33))
+    else:
+        atoms = tfsynth.make_atoms(253, 260, 0.1, n_bins=8)
+        win = tfsynth.regular_window("exp", 0, T, 200, 20 * T, 11 * T, 30)
+    res, ref, err = run_and_check(ctx, atoms, win, "fp32")
+    aid = ctx.upload_atoms(atoms)
+    try:
+        with tiling(ctx, -1, 0):
+            other, m_other = ctx.fmap(aid, win, "fp32", want_map=True)
+        _, m_split = ctx.fmap(aid, win, "fp32", want_map=True)
+        a = m_split.cpu().numpy().astype(np.float64)
+        b = m_other.cpu().numpy().astype(np.float64)
+        assert np.all((a == 0) == (b == 0))
+        assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0)) <= 2e-4
     finally:
         ctx.free(aid)
 
