@@ -238,7 +238,9 @@ int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t);
  * the requests at the head of the queue are admitted together: up to
  * max_batch of them (default 16), as many as the arena holds, run as one
  * batch with one persistent fused launch over all their tiles (FP32 and FP64
- * requests; matrix-core and recurrence requests run alone).  max_batch = 1
+ * requests of up to 2e9 window terms -- cells x slots x bins, or cells x
+ * bins for rectangular windows; larger requests, and matrix-core and
+ * recurrence requests, run alone with their own kernels).  max_batch = 1
  * admits one request per slot.  Results never depend on the batching.
  * Errors: E_INVAL (max_batch outside 1..1024).
  */

@@ -1387,12 +1387,28 @@ void ensure_batch_stream(tfstat_ctx *ctx) {
 // serve_max_batch of them, as many as the arena can hold -- and run as one
 // fused batch (one persistent launch over all their tiles) on that slot;
 // requests that the fused kernel does not cover (matrix-core and recurrence
-// precisions) run alone.  Up to kSlots admissions are in flight at once, so
+// precisions) and large requests run alone.  Up to kSlots admissions are in
+// flight at once, so
 // requests arriving while others run overlap with them on the device.  A
 // request's results do not depend on what it was batched with.
 // ---------------------------------------------------------------------------
+// Requests whose own kernels run longer than about a millisecond gain
+// nothing from sharing a launch, and would hold the results of the small
+// requests fused with them until they finish: they run alone.  Work is
+// counted in window terms (cell x slot x bin, or cell x bin for rect).
+constexpr double kServeFuseMaxWork = 2e9;
+
+double est_work(const Job &j) {
+    const double cells_bins = (double)j.win.t0.size() * (double)j.at->n_bins;
+    if (!banded(j.win.type)) return cells_bins * (double)j.win.tau.size();
+    double band = 0.0;   // sum over taus of the band length, from the block tables
+    for (int b = 0; b < j.NB; ++b) band += (double)j.lblk[b] * j.R;
+    return cells_bins * band;
+}
+
 bool fusable(const Job &j) {
-    return (j.prec == TFSTAT_PREC_FP32 || j.prec == TFSTAT_PREC_FP64) && !j.use_mfma && !j.use_recur;
+    return (j.prec == TFSTAT_PREC_FP32 || j.prec == TFSTAT_PREC_FP64) && !j.use_mfma && !j.use_recur &&
+           est_work(j) <= kServeFuseMaxWork;
 }
 
 void worker_loop(tfstat_ctx *ctx) {
