@@ -611,13 +611,16 @@ __global__ __launch_bounds__(kThreads, (exp_waves<XT, R, BG, MODE>())) void exp_
 // ---------------------------------------------------------------------------
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <typename XT, int BG>
+// G: slots per run and round.  The stand-alone kernel stages 8 (fewer
+// barriers per sum); the persistent kernel 4 (fewer prefetch registers
+// beside its other tile shapes).  The order of the sums does not depend on
+// it.
+template <typename XT, int BG, int G>
 struct RunCfg {
     static constexpr int kCpb = (int)sizeof(XT) / 4;        // 16-byte chunks per bin and slot
     static constexpr int kNC = 2 + BG * kCpb;               // chunk arrays: (a2, b2), (ab, 0), data
-    static constexpr int kG = kNC == 3 ? 8 : 4;             // slots per run and round (runs: 24 KB for
-                                                            // one FP32 bin, 16 KB for the others)
-    static constexpr int kSh = kG == 8 ? 1 : 2;             // LDS swizzle: rows per rotation step
+    static constexpr int kG = G;                            // slots per run and round
+    static constexpr int kSh = G == 8 ? 1 : 2;              // LDS swizzle: rows per rotation step
     static constexpr int kPer = kLanes * kG * kNC / kThreads;   // chunks each thread loads per round
     static_assert(kLanes * kG * kNC % kThreads == 0, "whole chunks per thread");
     static_assert(kThreads % kG == 0, "a thread keeps its slot within the run");
@@ -627,26 +630,26 @@ struct RunCfg {
 // g^2[d][r] for the round's kG slots, so that every operand of the sums is
 // read from LDS (in-order completion lets the loads of one step overlap the
 // products of the previous one).
-template <typename XT, int R, int BG>
+template <typename XT, int R, int BG, int G>
 struct RunSmem {
-    u32x4 c[RunCfg<XT, BG>::kNC][kLanes * RunCfg<XT, BG>::kG];
-    XT g[kWaves][RunCfg<XT, BG>::kG][R] __attribute__((aligned(16)));
-    double q[kWaves][RunCfg<XT, BG>::kG][R] __attribute__((aligned(16)));
+    u32x4 c[RunCfg<XT, BG, G>::kNC][kLanes * G];
+    XT g[kWaves][G][R] __attribute__((aligned(16)));
+    double q[kWaves][G][R] __attribute__((aligned(16)));
 };
 
 // Element of row r, slot j of a run: rows of kG elements, rotated by r >> kSh
 // so that the 16 lanes of a quarter wave reading one slot hit 16 distinct
 // 16-byte bank groups.
-template <typename XT, int BG>
+template <typename XT, int BG, int G>
 __device__ inline int run_index(int r, int j) {
-    using C = RunCfg<XT, BG>;
+    using C = RunCfg<XT, BG, G>;
     return r * C::kG + ((j + (r >> C::kSh)) & (C::kG - 1));
 }
 
-template <typename XT, int R, int BG, typename PP>
-__device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSmem<XT, R, BG> &sm, int q0,
+template <typename XT, int R, int BG, int G, typename PP>
+__device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSmem<XT, R, BG, G> &sm, int q0,
                                                                     int row_tile, int bin_group) {
-    using C = RunCfg<XT, BG>;
+    using C = RunCfg<XT, BG, G>;
     const int tid = threadIdx.x;
     const int lane = tid & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -684,7 +687,7 @@ __device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSm
     for (int h = 0; h < kRep; ++h) {
         const int r = rr + h * (kThreads / C::kG);
         kr[h] = p.rows[min(m_first + r, p.n_t0 - 1)].k0 + js;
-        sidx[h] = run_index<XT, BG>(r, js);
+        sidx[h] = run_index<XT, BG, G>(r, js);
     }
     u32x4 buf[C::kPer];
     // chunk sources of one round: slot k of array a (k outside the data
@@ -747,7 +750,7 @@ __device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSm
         const int jn = min(C::kG, dw - d0);
 #pragma unroll 2
         for (int j = 0; j < jn; ++j) {
-            const int e = run_index<XT, BG>(lane, j);
+            const int e = run_index<XT, BG, G>(lane, j);
             const double2 v = *reinterpret_cast<const double2 *>(&cur[0][e]);
             const double ab = *reinterpret_cast<const double *>(&cur[1][e]);
             Q4<XT> x[BG];
@@ -853,14 +856,14 @@ constexpr int runs_waves() {
 
 template <typename XT, int R, int BG>
 __global__ __launch_bounds__(kThreads, (runs_waves<XT, R, BG>())) void exp_runs_kernel(ExpValuParams p) {
-    __shared__ RunSmem<XT, R, BG> sm;
+    __shared__ RunSmem<XT, R, BG, 8> sm;
     // groups of four tau blocks, dealt round-robin to the XCDs
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
     const int slot = bid >> 3;
     const int g = (slot / p.n_row_tiles) * 8 + xcd;
     if (g * kWaves >= p.n_list) return;
-    exp_runs_tile<XT, R, BG>(p, sm, g * kWaves, slot % p.n_row_tiles, blockIdx.y);
+    exp_runs_tile<XT, R, BG, 8>(p, sm, g * kWaves, slot % p.n_row_tiles, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1139,12 +1142,12 @@ struct FusedSmem {
                : V == kShapeF42 ? sizeof(ExpSmem<float, 4, 2>)
                : V == kShapeF44 ? sizeof(ExpSmem<float, 4, 4>)
                                 : cmax(sizeof(ExpSmem<float, 4, 4>), sizeof(ExpSmem<double, 4, 1>)));
-    static constexpr size_t bytes = cmax(exp_bytes, sizeof(Red) * kWaves);
+    // runs tiles: FP64 (R = 4) or FP32 one bin (R = 8) and bin pairs (R = 4)
+    static constexpr size_t runs_bytes = V == kShapeD41 ? sizeof(RunSmem<double, 4, 1, 4>)
+                                         : cmax(sizeof(RunSmem<float, 8, 1, 4>), sizeof(RunSmem<float, 4, 2, 4>));
+    static constexpr size_t bytes = cmax(cmax(exp_bytes, runs_bytes), sizeof(Red) * kWaves);
 };
-static_assert(sizeof(RunSmem<double, 4, 1>) <= sizeof(ExpSmem<double, 4, 1>) &&
-                  sizeof(RunSmem<float, 8, 1>) <= sizeof(ExpSmem<float, 8, 1>) &&
-                  sizeof(RunSmem<float, 4, 2>) <= sizeof(ExpSmem<float, 4, 2>),
-              "runs staging fits the fused kernel's shared memory");
+
 
 // Loads a descriptor that the kernel never writes, whose address is the same
 // in every lane, and keeps it in scalar registers.
@@ -1165,11 +1168,11 @@ template <int SHAPE, typename PP>
 __device__ __attribute__((always_inline)) inline void fused_runs(PP &p, char *smem,
                                                                  const BatchTile &t) {
     if constexpr (SHAPE == kShapeD41)
-        exp_runs_tile<double, 4, 1>(p, *reinterpret_cast<RunSmem<double, 4, 1> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<double, 4, 1, 4>(p, *reinterpret_cast<RunSmem<double, 4, 1, 4> *>(smem), t.x, t.y, t.z);
     else if constexpr (SHAPE == kShapeF81)
-        exp_runs_tile<float, 8, 1>(p, *reinterpret_cast<RunSmem<float, 8, 1> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<float, 8, 1, 4>(p, *reinterpret_cast<RunSmem<float, 8, 1, 4> *>(smem), t.x, t.y, t.z);
     else
-        exp_runs_tile<float, 4, 2>(p, *reinterpret_cast<RunSmem<float, 4, 2> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<float, 4, 2, 4>(p, *reinterpret_cast<RunSmem<float, 4, 2, 4> *>(smem), t.x, t.y, t.z);
 }
 
 template <int SHAPE, typename PP>
