@@ -55,12 +55,14 @@ struct Red {
 
 __device__ inline Red red_empty() { return Red{-INFINITY, 0.0, 0x7fffffffffffffffLL}; }
 
+// Max-shifted merge of two partial sums of exp(F); the scale factors
+// exp(f - max) <= 1 are taken in FP32 (relative error ~1e-7 on the sum).
 __device__ inline Red red_combine(const Red &a, const Red &b) {
     Red r;
     r.f = fmax(a.f, b.f);
     if (r.f == -INFINITY) return red_empty();
-    const double sa = (a.f == -INFINITY) ? 0.0 : a.s * exp(a.f - r.f);
-    const double sb = (b.f == -INFINITY) ? 0.0 : b.s * exp(b.f - r.f);
+    const double sa = (a.f == -INFINITY) ? 0.0 : a.s * (double)__expf((float)(a.f - r.f));
+    const double sb = (b.f == -INFINITY) ? 0.0 : b.s * (double)__expf((float)(b.f - r.f));
     r.s = sa + sb;
     r.i = (a.f > b.f) ? a.i : (b.f > a.f) ? b.i : (a.i < b.i ? a.i : b.i);
     return r;
@@ -74,13 +76,23 @@ __device__ inline Red red_shfl_xor(const Red &v, int o) {
     return w;
 }
 
-__device__ inline double twoF_cell(double A, double B, double C, double far_, double fai,
-                                   double fbr, double fbi) {
+// 2F = (2 / D) (B |F_a|^2 + A |F_b|^2 - 2 C Re(F_a F_b*)), D = A B - C^2
+// (section 2), with F = s acc: the factor k = 2 s^2 / D is folded into the
+// cell's A, B, C once per (row, tau) and shared by all bins of the tile.
+// Degenerate cells (D <= rtol A B) get zero coefficients, hence 2F = 0.
+__device__ inline void fold_abc(double *abc, double s) {
+    const double A = abc[0], B = abc[1], C = abc[2];
     const double D = A * B - C * C;
-    if (D <= kDegenerateRtol * A * B) return 0.0;
-    const double num = B * (far_ * far_ + fai * fai) + A * (fbr * fbr + fbi * fbi)
-                       - 2.0 * C * (far_ * fbr + fai * fbi);
-    return 2.0 * (num / D);
+    double k = 0.0;
+    if (D > kDegenerateRtol * A * B) k = 2.0 * s * s / D;
+    abc[0] = k * A;
+    abc[1] = k * B;
+    abc[2] = 2.0 * k * C;
+}
+
+__device__ inline double twoF_folded(const double *abc, double far_, double fai, double fbr, double fbi) {
+    return abc[1] * (far_ * far_ + fai * fai) + abc[0] * (fbr * fbr + fbi * fbi)
+           - abc[2] * (far_ * fbr + fai * fbi);
 }
 
 // Round-to-nearest-even FP32 -> bf16 bits (inputs are finite).
@@ -366,8 +378,15 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
             if (w + 1 < n_win) run_window(w + 1, tab1, tab0);
         }
 
-        if (half == 0) {   // A/B/C copies have landed (also with no K steps)
+        if (half == 0) {   // A/B/C copies have landed (also with no K steps):
+                           // fold the window scale and 1 / D into them
             __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            for (int e = tid; e < 64 * kBlk; e += 256) {
+                const int n = nb * kBlk + (e % kBlk);
+                const double tau = (double)p.tau[n < p.n_tau ? n : p.n_tau - 1];
+                fold_abc(abcs[e / kBlk][e % kBlk], p.delta ? exp(-(double)p.delta / tau) : 1.0);
+            }
             __syncthreads();
         }
         // Finalize this pass: lane holds rows 16w + 4 kg + r (r < 4) of bin
@@ -379,17 +398,14 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
         for (int t = 0; t < kNT; ++t) {
             const int n = nb * kBlk + t0 + t;
             const bool n_ok = n < p.n_tau;
-            const double tau = (double)p.tau[n_ok ? n : p.n_tau - 1];
-            const double s = p.delta ? exp(-(double)p.delta / tau) : 1.0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m_first + 16 * wave + 4 * kg + r;
                 v2[t][r] = -INFINITY;
                 if (!n_ok || m >= p.n_t0 || !bin_ok) continue;
-                const double *abc = abcs[m - m_first][t0 + t];
-                const double v = twoF_cell(abc[0], abc[1], abc[2], s * (double)acc[t][0][r],
-                                           s * (double)acc[t][1][r], s * (double)acc[t][2][r],
-                                           s * (double)acc[t][3][r]);
+                const double v = twoF_folded(abcs[m - m_first][t0 + t], (double)acc[t][0][r],
+                                             (double)acc[t][1][r], (double)acc[t][2][r],
+                                             (double)acc[t][3][r]);
                 if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
                 v2[t][r] = v;
                 const long long idx = (long long)m * p.n_tau + n;
