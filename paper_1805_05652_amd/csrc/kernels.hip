@@ -301,7 +301,7 @@ __device__ __attribute__((always_inline)) inline void fetch_step(const SM &sm, c
 
 // Shapes whose staged band loop is software-pipelined: bit 1 FP64, 2 FP32
 // R = 8, 4 FP32 R = 4 BG = 2, 8 FP32 R = 4 BG = 4, 16 A/B/C only, 32 F
-// only.  The four-bin shape and the A/B/C pass have the registers for a
+// only, 64 FP32 R = 4 BG = 1.  The four-bin shape and the A/B/C pass have the registers for a
 // second operand set at their occupancy (measured: the four-bin shape
 // faster in the fused batch kernel and about even alone, the A/B/C pass a
 // third faster); this set is fetched with vector loads (weights included).
@@ -310,7 +310,7 @@ __device__ __attribute__((always_inline)) inline void fetch_step(const SM &sm, c
 #endif
 template <typename XT, int R, int BG, int MODE>
 constexpr int exp_shape_bit() {
-    return MODE == kModeAbc ? 16 : MODE == kModeF ? 32 : sizeof(XT) == 8 ? 1 : R == 8 ? 2 : BG == 2 ? 4 : 8;
+    return MODE == kModeAbc ? 16 : MODE == kModeF ? 32 : sizeof(XT) == 8 ? 1 : R == 8 ? 2 : BG == 1 ? 64 : BG == 2 ? 4 : 8;
 }
 template <typename XT, int R, int BG, int MODE>
 constexpr bool exp_pipe() {
@@ -322,7 +322,7 @@ constexpr bool exp_pipe() {
 // the one-bin FP32 map 7% faster, FP64 even, the batch 1% faster; the F-only
 // and four-bin shapes slower in the fused batch kernel.
 #ifndef TFS_SPIPE_MASK
-#define TFS_SPIPE_MASK 7
+#define TFS_SPIPE_MASK 71
 #endif
 template <typename XT, int R, int BG, int MODE>
 constexpr bool exp_spipe() {
@@ -1097,7 +1097,9 @@ __global__ __launch_bounds__(kScanWaves * 64) void scan_batch_kernel(const ScanJ
 
 // ---------------------------------------------------------------------------
 // Rectangular-window cells: window sums as prefix differences, finalize,
-// optional map, per-tile reduction.  Block = 4 rows x 64 taus of one bin.
+// optional map, per-tile reduction.  Tile = kRectRows rows x 64 taus of one
+// bin: lane = tau, the waves take every fourth row, and each lane keeps a
+// running (max, sum, first argmax) over its cells, so the tile reduces once.
 // ---------------------------------------------------------------------------
 template <typename PP>
 __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red *wred,
@@ -1105,34 +1107,37 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red *wre
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = bx * 64 + lane;
-    const int m = by * kWaves + wave;
-    const bool ok = n < p.n_tau && m < p.n_t0;
+    const bool n_ok = n < p.n_tau;
     const int nn = min(n, p.n_tau - 1);
-    const int mm = min(m, p.n_t0 - 1);
-    const RowPlan rp = p.rows[mm];
     const int64_t tau = p.tau[nn];
     const int64_t T = p.t_sft;
-    const int64_t L = tau > rp.delta ? (tau - rp.delta + T - 1) / T : 0;
     const int64_t K = p.K;
-    const int64_t lo = min(max((int64_t)rp.k0, (int64_t)0), K);
-    const int64_t hi = min(max((int64_t)rp.k0 + L, (int64_t)0), K);
-    // window sums from compensated prefixes: (hi_h - hi_l) + (lo_h - lo_l)
-    const double *a_hi = p.pabc + hi * 8;
-    const double *a_lo = p.pabc + lo * 8;
-    const double A = (a_hi[0] - a_lo[0]) + (a_hi[4] - a_lo[4]);
-    const double B = (a_hi[1] - a_lo[1]) + (a_hi[5] - a_lo[5]);
-    const double C = (a_hi[2] - a_lo[2]) + (a_hi[6] - a_lo[6]);
     const int64_t CW = (int64_t)p.n_bins * 4;
-    const double *x_hi = p.px + hi * 2 * CW + bin * 4;
-    const double *x_lo = p.px + lo * 2 * CW + bin * 4;
-    double f[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) f[c] = (x_hi[c] - x_lo[c]) + (x_hi[CW + c] - x_lo[CW + c]);
-    const double v = twoF_cell(A, B, C, f[0], f[1], f[2], f[3]);
     Red r = red_empty();
-    if (ok) {
-        if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
-        r = Red{0.5 * v, 1.0, (long long)m * p.n_tau + n};
+#pragma unroll 1
+    for (int i = 0; i < kRectRows / kWaves; ++i) {
+        const int m = by * kRectRows + i * kWaves + wave;
+        if (m >= p.n_t0) break;
+        const RowPlan rp = p.rows[m];
+        const int64_t L = tau > rp.delta ? (tau - rp.delta + T - 1) / T : 0;
+        const int64_t lo = min(max((int64_t)rp.k0, (int64_t)0), K);
+        const int64_t hi = min(max((int64_t)rp.k0 + L, (int64_t)0), K);
+        // window sums from compensated prefixes: (hi_h - hi_l) + (lo_h - lo_l)
+        const double *a_hi = p.pabc + hi * 8;
+        const double *a_lo = p.pabc + lo * 8;
+        const double A = (a_hi[0] - a_lo[0]) + (a_hi[4] - a_lo[4]);
+        const double B = (a_hi[1] - a_lo[1]) + (a_hi[5] - a_lo[5]);
+        const double C = (a_hi[2] - a_lo[2]) + (a_hi[6] - a_lo[6]);
+        const double *x_hi = p.px + hi * 2 * CW + bin * 4;
+        const double *x_lo = p.px + lo * 2 * CW + bin * 4;
+        double f[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) f[c] = (x_hi[c] - x_lo[c]) + (x_hi[CW + c] - x_lo[CW + c]);
+        const double v = twoF_cell(A, B, C, f[0], f[1], f[2], f[3]);
+        if (n_ok) {
+            if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
+            red_add(r, 0.5 * v, (long long)m * p.n_tau + n);
+        }
     }
     r = red_wave(r);
     if (lane == 0) wred[wave] = r;
@@ -1220,8 +1225,9 @@ struct FusedSmem {
         fonly, V == kShapeD41   ? sizeof(ExpSmem<double, 4, 1>)
                : V == kShapeF81 ? sizeof(ExpSmem<float, 8, 1>)
                : V == kShapeF42 ? sizeof(ExpSmem<float, 4, 2>)
-               : V == kShapeF44 ? sizeof(ExpSmem<float, 4, 4>)
-                                : cmax(sizeof(ExpSmem<float, 4, 4>), sizeof(ExpSmem<double, 4, 1>)));
+               : V == kShapeF44 ? cmax(sizeof(ExpSmem<float, 4, 4>), sizeof(ExpSmem<float, 4, 1>))
+                                : cmax(cmax(sizeof(ExpSmem<float, 4, 4>), sizeof(ExpSmem<float, 4, 1>)),
+                                       sizeof(ExpSmem<double, 4, 1>)));
     // runs tiles: FP64 (R = 4) or FP32 one bin (R = 8) and bin pairs (R = 4)
     static constexpr size_t runs_bytes = V == kShapeD41 ? sizeof(RunSmem<double, 4, 1, 4>)
                                          : cmax(sizeof(RunSmem<float, 8, 1, 4>), sizeof(RunSmem<float, 4, 2, 4>));
@@ -1264,6 +1270,8 @@ __device__ __attribute__((always_inline)) inline void fused_exp(PP &p, char *sme
         exp_tile<float, 8, 1>(p, *reinterpret_cast<ExpSmem<float, 8, 1> *>(smem), t.x, t.y, t.z);
     else if constexpr (SHAPE == kShapeF42)
         exp_tile<float, 4, 2>(p, *reinterpret_cast<ExpSmem<float, 4, 2> *>(smem), t.x, t.y, t.z);
+    else if constexpr (SHAPE == kShapeF41)
+        exp_tile<float, 4, 1>(p, *reinterpret_cast<ExpSmem<float, 4, 1> *>(smem), t.x, t.y, t.z);
     else
         exp_tile<float, 4, 4>(p, *reinterpret_cast<ExpSmem<float, 4, 4> *>(smem), t.x, t.y, t.z);
 }
@@ -1290,15 +1298,7 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
         const BatchTile t = load_uniform(p.tiles + ti);   // one tile, held in scalar registers
         if (t.kind == 1) {
             auto &rp = const_params(p.rect_jobs + t.job);
-            Red *wred = reinterpret_cast<Red *>(smem);
-            const int nby = (rp.n_t0 + kWaves - 1) / kWaves;
-#pragma unroll 1
-            for (int i = 0; i < kRectRowBlocks; ++i) {
-                const int by = t.y * kRectRowBlocks + i;
-                if (by >= nby) break;
-                if (i > 0) __syncthreads();   // wred of the previous block has been read
-                rect_block(rp, wred, t.x, by, t.z);
-            }
+            rect_block(rp, reinterpret_cast<Red *>(smem), t.x, t.y, t.z);
             continue;
         }
         auto &ep = const_params(p.exp_jobs + t.job);
@@ -1325,10 +1325,12 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
             case kShapeD41: fused_exp<kShapeD41>(ep, smem, t); break;
             case kShapeF81: fused_exp<kShapeF81>(ep, smem, t); break;
             case kShapeF42: fused_exp<kShapeF42>(ep, smem, t); break;
+            case kShapeF41: fused_exp<kShapeF41>(ep, smem, t); break;
             default: fused_exp<kShapeF44>(ep, smem, t); break;
             }
         } else if constexpr (V == kShapeF44) {
-            if (t.shape == kShapeF42) fused_exp<kShapeF42>(ep, smem, t);   // tail bin pair
+            if (t.shape == kShapeF42) fused_exp<kShapeF42>(ep, smem, t);        // tail bin pair
+            else if (t.shape == kShapeF41) fused_exp<kShapeF41>(ep, smem, t);   // tail bin
             else fused_exp<V>(ep, smem, t);
         } else {
             fused_exp<V>(ep, smem, t);
@@ -1420,6 +1422,8 @@ hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, int 
         hipLaunchKernelGGL((exp_valu_kernel<float, 8, 1>), grid, dim3(kThreads), 0, s, p);
     else if (prec == 1 && R == 4 && BG == 2)
         hipLaunchKernelGGL((exp_valu_kernel<float, 4, 2>), grid, dim3(kThreads), 0, s, p);
+    else if (prec == 1 && R == 4 && BG == 1)
+        hipLaunchKernelGGL((exp_valu_kernel<float, 4, 1>), grid, dim3(kThreads), 0, s, p);
     else if (prec == 1 && R == 4 && BG == 4)
         hipLaunchKernelGGL((exp_valu_kernel<float, 4, 4>), grid, dim3(kThreads), 0, s, p);
     else
@@ -1467,7 +1471,7 @@ hipError_t launch_scan(const double *in, int64_t stride, double *out, int32_t K,
 }
 
 hipError_t launch_rect(const RectParams &p, hipStream_t s) {
-    const dim3 grid((unsigned)p.n_tiles_n, (unsigned)((p.n_t0 + kWaves - 1) / kWaves),
+    const dim3 grid((unsigned)p.n_tiles_n, (unsigned)((p.n_t0 + kRectRows - 1) / kRectRows),
                     (unsigned)p.n_bins);
     hipLaunchKernelGGL(rect_kernel, grid, dim3(256), 0, s, p);
     return hipGetLastError();

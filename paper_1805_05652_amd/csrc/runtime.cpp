@@ -470,7 +470,7 @@ void plan_job(Job &j) {
         }
     } else {
         j.n_tiles_n = (n_tau + 63) / 64;
-        j.n_tiles = j.n_tiles_n * ((n_t0 + 3) / 4);
+        j.n_tiles = j.n_tiles_n * ((n_t0 + tfs::kRectRows - 1) / tfs::kRectRows);
     }
 
     // workspace layout
@@ -808,9 +808,10 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
             const int pr = wants64(j) ? 0 : 1;
             hip_check(launch(p, pr, j.R, j.BG, j.n_groups, s), "exp kernel");
             if (j.tail2) {
+                // the one or two bins after the four-bin groups
                 tfs::ExpValuParams pt = p;
                 pt.bin_base = 4 * j.n_groups;
-                hip_check(launch(pt, pr, j.R, 2, 1, s), "exp kernel (bin pair)");
+                hip_check(launch(pt, pr, j.R, j.at->n_bins % 4, 1, s), "exp kernel (tail bins)");
             }
             record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
         }
@@ -1091,8 +1092,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
                 groups_e.push_back({i, q, (double)(j.lblk[j.order[q]] + 1) * j.R * per_step * step});
             n_tiles_total += per * ((j.n_valu + step - 1) / step);
         } else {
-            const int nby = ((int)j.win.t0.size() + 3) / 4;
-            const int ny = (nby + tfs::kRectRowBlocks - 1) / tfs::kRectRowBlocks;
+            const int ny = ((int)j.win.t0.size() + tfs::kRectRows - 1) / tfs::kRectRows;
             n_tiles_total += (size_t)ny * j.n_tiles_n * j.at->n_bins;
         }
     }
@@ -1108,16 +1108,19 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
         for (int rt = 0; rt < j.n_row_tiles; ++rt) {
             for (int gidx = 0; gidx < ng; ++gidx)
                 tiles.push_back(tfs::BatchTile{kind, eidx[g.map], g.q, rt, gidx, shape[g.map]});
-            // the bin pair after the four-bin groups: group index in pairs
-            if (j.tail2)
-                tiles.push_back(tfs::BatchTile{kind, eidx[g.map], g.q, rt, 2 * j.n_groups, tfs::kShapeF42});
+            // the one or two bins after the four-bin groups: group index in
+            // units of the tail's bins per lane
+            if (j.tail2) {
+                const bool one = j.at->n_bins % 4 == 1;
+                tiles.push_back(tfs::BatchTile{kind, eidx[g.map], g.q, rt, (one ? 4 : 2) * j.n_groups,
+                                               one ? tfs::kShapeF41 : tfs::kShapeF42});
+            }
         }
     }
     for (int32_t i = 0; i < n; ++i) {
         if (ridx[i] < 0) continue;
         const Job &j = *b->jobs[i];
-        const int nby = ((int)j.win.t0.size() + 3) / 4;
-        const int ny = (nby + tfs::kRectRowBlocks - 1) / tfs::kRectRowBlocks;
+        const int ny = ((int)j.win.t0.size() + tfs::kRectRows - 1) / tfs::kRectRows;
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < j.n_tiles_n; ++x)
                 for (int bin = 0; bin < j.at->n_bins; ++bin)

@@ -192,7 +192,9 @@ enum ExpShape : int32_t {
     kShapeF42 = 2,   // FP32, R = 4, BG = 2
     kShapeF44 = 3,   // FP32, R = 4, BG = 4
     kShapeCount = 4,
-    kShapeMixed = 4  // fused-kernel variant: each map keeps its own shape
+    kShapeMixed = 4,  // fused-kernel variant: each map keeps its own shape
+    kShapeF41 = 5     // tile shape only: a four-bin map's one leftover bin
+                      // (FP32, R = 4, BG = 1)
 };
 inline void shape_dims(int shape, int *prec, int *R, int *BG) {
     static const int t[4][3] = {{0, 4, 1}, {1, 8, 1}, {1, 4, 2}, {1, 4, 4}};
@@ -201,7 +203,7 @@ inline void shape_dims(int shape, int *prec, int *R, int *BG) {
     *BG = t[shape][2];
 }
 
-constexpr int kRectRowBlocks = 4;   // 4-row rect blocks per batch tile (16 rows)
+constexpr int kRectRows = 64;   // rows per rect tile (x 64 taus of one bin)
 
 struct BatchTile {
     int32_t kind;    // 0: exponential, 1: rectangular, 2: exponential, rows far apart,
@@ -209,9 +211,9 @@ struct BatchTile {
                      //    z counts bin pairs)
     int32_t job;     // index into FusedParams::exp_jobs or ::rect_jobs
     int32_t x;       // exp: position in blk_list (kind 2: first of four); rect: tau tile (64 taus)
-    int32_t y;       // exp: 64-row tile; rect: first 4-row block / kRectRowBlocks
+    int32_t y;       // exp: 64-row tile; rect: kRectRows-row tile
     int32_t z;       // exp: bin group; rect: bin
-    int32_t shape;   // exp: ExpShape of the job
+    int32_t shape;   // exp: ExpShape of the job (a four-bin map's tail: kShapeF42, kShapeF41)
 };
 
 struct FusedParams {
