@@ -706,15 +706,11 @@ struct RunCfg {
     static_assert(kThreads % kG == 0, "a thread keeps its slot within the run");
 };
 
-// One round: the runs (16-byte chunks) and each wave's weights g[d][r],
-// g^2[d][r] for the round's kG slots, so that every operand of the sums is
-// read from LDS (in-order completion lets the loads of one step overlap the
-// products of the previous one).
+// One round: the runs (16-byte chunks) of the round's kG slots.  The
+// weights g[d][r], g^2[d][r] are wave-uniform and come from scalar loads.
 template <typename XT, int R, int BG, int G>
 struct RunSmem {
     u32x4 c[RunCfg<XT, BG, G>::kNC][kLanes * G];
-    XT g[kWaves][G][R] __attribute__((aligned(16)));
-    double q[kWaves][G][R] __attribute__((aligned(16)));
 };
 
 // Element of row r, slot j of a run: rows of kG elements, rotated by r >> kSh
@@ -787,70 +783,67 @@ __device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSm
         }                                                                                       \
     }
 
-    // The wave's weights of one round: lane l < kWc copies one 16-byte chunk
-    // of rows d0 .. d0 + kG - 1 of its block's tables (rows past the band
-    // repeat the last one; a wave without rows copies the zero atom row).
-    constexpr int kCg = R * (int)sizeof(XT) / 16;    // chunks per g row
-    constexpr int kCq = R * 8 / 16;                  // chunks per g^2 row
-    constexpr int kWc = C::kG * (kCg + kCq);
-    static_assert(kWc <= kLanes && R * sizeof(XT) % 16 == 0, "one weight chunk per lane");
-    const int lb = has_blk ? p.lblk[nb] : 0;
-    const bool wl = lane < kWc;
-    const int wj = lane < C::kG * kCg ? lane / kCg : (lane - C::kG * kCg) / kCq;
-    const int wc = lane < C::kG * kCg ? lane % kCg : (lane - C::kG * kCg) % kCq;
-    u32x4 *const wdst = lane < C::kG * kCg ? reinterpret_cast<u32x4 *>(&sm.g[wave][wj][0]) + wc
-                                           : reinterpret_cast<u32x4 *>(&sm.q[wave][wj][0]) + wc;
-    u32x4 wbuf;
-#define TFS_RUNS_WLOAD(D0)                                                                      \
-    {                                                                                           \
-        const int d = min((D0) + wj, lb - 1);                                                   \
-        const u32x4 *src = reinterpret_cast<const u32x4 *>(abc + (size_t)K * 4);               \
-        if (wl && d >= 0)                                                                       \
-            src = lane < C::kG * kCg ? reinterpret_cast<const u32x4 *>(gw_base + (size_t)d * R) + wc \
-                                     : reinterpret_cast<const u32x4 *>(gq_base + (size_t)d * R) + wc; \
-        wbuf = *src;                                                                            \
-    }
-
     ExpAcc<XT, R, BG> acc;
     acc.zero();
+    // The wave's weights of step d, one step ahead in scalar registers: the
+    // scalar loads of the next step are issued once this step's LDS operands
+    // have landed (both count on one counter; scalar loads complete out of
+    // order) and complete while this step's sums run.  Waves without a block
+    // run no steps and load no weights.
+    StepW<XT, R> wa, wb;
+    if (dw > 0) fetch_w<kModeAll>(gw_base, gq_base, 0, wa);
+    // step j of the round from d0 with the weights in CUR; those of step DN
+    // (clamped into the band) go to NXT
+#define TFS_RUNS_STEP(CUR, NXT, J, DN)                                                          \
+    {                                                                                           \
+        const int e = run_index<XT, BG, G>(lane, (J));                                          \
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);                                                 \
+        __builtin_amdgcn_sched_barrier(0);                                                      \
+        const double2 v = *reinterpret_cast<const double2 *>(&cur[0][e]);                       \
+        const double ab = *reinterpret_cast<const double *>(&cur[1][e]);                        \
+        Q4<XT> x[BG];                                                                           \
+        _Pragma("unroll") for (int b = 0; b < BG; ++b) {                                        \
+            if constexpr (sizeof(XT) == 4) {                                                    \
+                const u32x4 u = cur[2 + b][e];                                                  \
+                x[b] = Q4<XT>{__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), \
+                              __uint_as_float(u.w)};                                            \
+            } else {                                                                            \
+                const double2 lo = *reinterpret_cast<const double2 *>(&cur[2 + 2 * b][e]);      \
+                const double2 hi = *reinterpret_cast<const double2 *>(&cur[3 + 2 * b][e]);      \
+                x[b] = Q4<XT>{lo.x, lo.y, hi.x, hi.y};                                          \
+            }                                                                                   \
+        }                                                                                       \
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);                                                 \
+        __builtin_amdgcn_sched_barrier(0);                                                      \
+        fetch_w<kModeAll>(gw_base, gq_base, min((DN), dw - 1), NXT);                            \
+        __builtin_amdgcn_sched_barrier(0);                                                      \
+        acc.step(CUR.w, CUR.q, v.x, v.y, ab, x);                                                \
+    }
     TFS_RUNS_LOAD(0)
-    TFS_RUNS_WLOAD(0)
 #pragma unroll 1
     for (int d0 = 0; d0 < dall; d0 += C::kG) {
         __syncthreads();   // every wave is done with the previous round
         auto &cur = sm.c;
 #pragma unroll
         for (int i = 0; i < C::kPer; ++i) cur[i / kRep][sidx[i % kRep]] = buf[i];
-        if (wl) *wdst = wbuf;
         __syncthreads();
         // next round (past the band this reads zero rows or unused slots;
         // an unconditional load keeps buf in registers)
         TFS_RUNS_LOAD(d0 + C::kG)
-        TFS_RUNS_WLOAD(d0 + C::kG)
         const int jn = min(C::kG, dw - d0);
-#pragma unroll 2
-        for (int j = 0; j < jn; ++j) {
-            const int e = run_index<XT, BG, G>(lane, j);
-            const double2 v = *reinterpret_cast<const double2 *>(&cur[0][e]);
-            const double ab = *reinterpret_cast<const double *>(&cur[1][e]);
-            Q4<XT> x[BG];
-#pragma unroll
-            for (int b = 0; b < BG; ++b) {
-                if constexpr (sizeof(XT) == 4) {
-                    const u32x4 u = cur[2 + b][e];
-                    x[b] = Q4<XT>{__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z),
-                                  __uint_as_float(u.w)};
-                } else {
-                    const double2 lo = *reinterpret_cast<const double2 *>(&cur[2 + 2 * b][e]);
-                    const double2 hi = *reinterpret_cast<const double2 *>(&cur[3 + 2 * b][e]);
-                    x[b] = Q4<XT>{lo.x, lo.y, hi.x, hi.y};
-                }
-            }
-            acc.step(&sm.g[wave][j][0], &sm.q[wave][j][0], v.x, v.y, ab, x);
+        int j = 0;
+#pragma unroll 1
+        for (; j + 2 <= jn; j += 2) {
+            TFS_RUNS_STEP(wa, wb, j, d0 + j + 1)
+            TFS_RUNS_STEP(wb, wa, j + 1, d0 + j + 2)
+        }
+        if (j < jn) {
+            TFS_RUNS_STEP(wa, wb, j, d0 + j + 1)
+            wa = wb;
         }
     }
+#undef TFS_RUNS_STEP
 #undef TFS_RUNS_LOAD
-#undef TFS_RUNS_WLOAD
     if (!has_blk) return;
 
     // Finalize the wave's block: exact band end, row scale, D, 2F, map,
