@@ -706,11 +706,15 @@ struct RunCfg {
     static_assert(kThreads % kG == 0, "a thread keeps its slot within the run");
 };
 
-// One round: the runs (16-byte chunks) of the round's kG slots.  The
-// weights g[d][r], g^2[d][r] are wave-uniform and come from scalar loads.
-template <typename XT, int R, int BG, int G>
+// One round: the runs (16-byte chunks) of the round's kG slots and, unless
+// SW, each wave's weights g[d][r], g^2[d][r] for them.  The weights are
+// wave-uniform: with SW they come from scalar loads one step ahead instead
+// (no LDS reads for them; the scalar registers limit the one-bin shape).
+template <typename XT, int R, int BG, int G, bool SW>
 struct RunSmem {
     u32x4 c[RunCfg<XT, BG, G>::kNC][kLanes * G];
+    XT g[SW ? 1 : kWaves][G][R] __attribute__((aligned(16)));
+    double q[SW ? 1 : kWaves][G][R] __attribute__((aligned(16)));
 };
 
 // Element of row r, slot j of a run: rows of kG elements, rotated by r >> kSh
@@ -722,8 +726,8 @@ __device__ inline int run_index(int r, int j) {
     return r * C::kG + ((j + (r >> C::kSh)) & (C::kG - 1));
 }
 
-template <typename XT, int R, int BG, int G, typename PP>
-__device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSmem<XT, R, BG, G> &sm, int q0,
+template <typename XT, int R, int BG, int G, bool SW, typename PP>
+__device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSmem<XT, R, BG, G, SW> &sm, int q0,
                                                                     int row_tile, int bin_group) {
     using C = RunCfg<XT, BG, G>;
     const int tid = threadIdx.x;
@@ -783,15 +787,40 @@ __device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSm
         }                                                                                       \
     }
 
+    // Without SW, the wave's weights of one round: lane l < kWc copies one
+    // 16-byte chunk of rows d0 .. d0 + kG - 1 of its block's tables (rows
+    // past the band repeat the last one; a wave without rows copies the zero
+    // atom row).
+    constexpr int kCg = R * (int)sizeof(XT) / 16;    // chunks per g row
+    constexpr int kCq = R * 8 / 16;                  // chunks per g^2 row
+    constexpr int kWc = C::kG * (kCg + kCq);
+    static_assert(kWc <= kLanes && R * sizeof(XT) % 16 == 0, "one weight chunk per lane");
+    const int lb = has_blk ? p.lblk[nb] : 0;
+    const bool wl = !SW && lane < kWc;
+    const int wj = lane < C::kG * kCg ? lane / kCg : (lane - C::kG * kCg) / kCq;
+    const int wc = lane < C::kG * kCg ? lane % kCg : (lane - C::kG * kCg) % kCq;
+    u32x4 *const wdst = lane < C::kG * kCg ? reinterpret_cast<u32x4 *>(&sm.g[SW ? 0 : wave][wj][0]) + wc
+                                           : reinterpret_cast<u32x4 *>(&sm.q[SW ? 0 : wave][wj][0]) + wc;
+    u32x4 wbuf;
+#define TFS_RUNS_WLOAD(D0)                                                                      \
+    if constexpr (!SW) {                                                                        \
+        const int d = min((D0) + wj, lb - 1);                                                   \
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(abc + (size_t)K * 4);               \
+        if (wl && d >= 0)                                                                       \
+            src = lane < C::kG * kCg ? reinterpret_cast<const u32x4 *>(gw_base + (size_t)d * R) + wc \
+                                     : reinterpret_cast<const u32x4 *>(gq_base + (size_t)d * R) + wc; \
+        wbuf = *src;                                                                            \
+    }
+
     ExpAcc<XT, R, BG> acc;
     acc.zero();
-    // The wave's weights of step d, one step ahead in scalar registers: the
+    // With SW, the wave's weights of step d, one step ahead in scalar registers: the
     // scalar loads of the next step are issued once this step's LDS operands
     // have landed (both count on one counter; scalar loads complete out of
     // order) and complete while this step's sums run.  Waves without a block
     // run no steps and load no weights.
     StepW<XT, R> wa, wb;
-    if (dw > 0) fetch_w<kModeAll>(gw_base, gq_base, 0, wa);
+    if (SW && dw > 0) fetch_w<kModeAll>(gw_base, gq_base, 0, wa);
     // step j of the round from d0 with the weights in CUR; those of step DN
     // (clamped into the band) go to NXT
 #define TFS_RUNS_STEP(CUR, NXT, J, DN)                                                          \
@@ -820,17 +849,45 @@ __device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSm
         acc.step(CUR.w, CUR.q, v.x, v.y, ab, x);                                                \
     }
     TFS_RUNS_LOAD(0)
+    TFS_RUNS_WLOAD(0)
 #pragma unroll 1
     for (int d0 = 0; d0 < dall; d0 += C::kG) {
         __syncthreads();   // every wave is done with the previous round
         auto &cur = sm.c;
 #pragma unroll
         for (int i = 0; i < C::kPer; ++i) cur[i / kRep][sidx[i % kRep]] = buf[i];
+        if (wl) *wdst = wbuf;
         __syncthreads();
         // next round (past the band this reads zero rows or unused slots;
         // an unconditional load keeps buf in registers)
         TFS_RUNS_LOAD(d0 + C::kG)
+        TFS_RUNS_WLOAD(d0 + C::kG)
         const int jn = min(C::kG, dw - d0);
+        if constexpr (!SW) {
+            // every operand from LDS (in-order completion lets the loads of
+            // one step overlap the products of the previous one)
+#pragma unroll 2
+            for (int j = 0; j < jn; ++j) {
+                const int e = run_index<XT, BG, G>(lane, j);
+                const double2 v = *reinterpret_cast<const double2 *>(&cur[0][e]);
+                const double ab = *reinterpret_cast<const double *>(&cur[1][e]);
+                Q4<XT> x[BG];
+#pragma unroll
+                for (int b = 0; b < BG; ++b) {
+                    if constexpr (sizeof(XT) == 4) {
+                        const u32x4 u = cur[2 + b][e];
+                        x[b] = Q4<XT>{__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z),
+                                      __uint_as_float(u.w)};
+                    } else {
+                        const double2 lo = *reinterpret_cast<const double2 *>(&cur[2 + 2 * b][e]);
+                        const double2 hi = *reinterpret_cast<const double2 *>(&cur[3 + 2 * b][e]);
+                        x[b] = Q4<XT>{lo.x, lo.y, hi.x, hi.y};
+                    }
+                }
+                acc.step(&sm.g[SW ? 0 : wave][j][0], &sm.q[SW ? 0 : wave][j][0], v.x, v.y, ab, x);
+            }
+            continue;
+        }
         int j = 0;
 #pragma unroll 1
         for (; j + 2 <= jn; j += 2) {
@@ -844,6 +901,7 @@ __device__ __attribute__((always_inline)) inline void exp_runs_tile(PP &p, RunSm
     }
 #undef TFS_RUNS_STEP
 #undef TFS_RUNS_LOAD
+#undef TFS_RUNS_WLOAD
     if (!has_blk) return;
 
     // Finalize the wave's block: exact band end, row scale, D, 2F, map,
@@ -927,16 +985,25 @@ constexpr int runs_waves() {
     return BG == 4 ? 2 : 3;
 }
 
+// Weights of the stand-alone runs kernel (rounds of 8 slots): scalar loads
+// for FP64 sums, LDS for FP32 (measured: FP64 maps 5-9% faster with scalar
+// loads, FP32 bin pairs 2-9% and the one-bin shape 35% slower).  The
+// persistent kernel (rounds of 4) takes scalar loads for every shape.
+template <typename XT, int R, int BG>
+constexpr bool runs_sw() {
+    return sizeof(XT) == 8;
+}
+
 template <typename XT, int R, int BG>
 __global__ __launch_bounds__(kThreads, (runs_waves<XT, R, BG>())) void exp_runs_kernel(ExpValuParams p) {
-    __shared__ RunSmem<XT, R, BG, 8> sm;
+    __shared__ RunSmem<XT, R, BG, 8, runs_sw<XT, R, BG>()> sm;
     // groups of four tau blocks, dealt round-robin to the XCDs
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
     const int slot = bid >> 3;
     const int g = (slot / p.n_row_tiles) * 8 + xcd;
     if (g * kWaves >= p.n_list) return;
-    exp_runs_tile<XT, R, BG, 8>(p, sm, g * kWaves, slot % p.n_row_tiles, blockIdx.y);
+    exp_runs_tile<XT, R, BG, 8, runs_sw<XT, R, BG>()>(p, sm, g * kWaves, slot % p.n_row_tiles, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1222,8 +1289,9 @@ struct FusedSmem {
                                 : cmax(cmax(sizeof(ExpSmem<float, 4, 4>), sizeof(ExpSmem<float, 4, 1>)),
                                        sizeof(ExpSmem<double, 4, 1>)));
     // runs tiles: FP64 (R = 4) or FP32 one bin (R = 8) and bin pairs (R = 4)
-    static constexpr size_t runs_bytes = V == kShapeD41 ? sizeof(RunSmem<double, 4, 1, 4>)
-                                         : cmax(sizeof(RunSmem<float, 8, 1, 4>), sizeof(RunSmem<float, 4, 2, 4>));
+    static constexpr size_t runs_bytes = V == kShapeD41 ? sizeof(RunSmem<double, 4, 1, 4, true>)
+                                         : cmax(sizeof(RunSmem<float, 8, 1, 4, true>),
+                                                sizeof(RunSmem<float, 4, 2, 4, true>));
     static constexpr size_t bytes = cmax(cmax(exp_bytes, runs_bytes), sizeof(Red) * kWaves);
 };
 
@@ -1247,11 +1315,11 @@ template <int SHAPE, typename PP>
 __device__ __attribute__((always_inline)) inline void fused_runs(PP &p, char *smem,
                                                                  const BatchTile &t) {
     if constexpr (SHAPE == kShapeD41)
-        exp_runs_tile<double, 4, 1, 4>(p, *reinterpret_cast<RunSmem<double, 4, 1, 4> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<double, 4, 1, 4, true>(p, *reinterpret_cast<RunSmem<double, 4, 1, 4, true> *>(smem), t.x, t.y, t.z);
     else if constexpr (SHAPE == kShapeF81)
-        exp_runs_tile<float, 8, 1, 4>(p, *reinterpret_cast<RunSmem<float, 8, 1, 4> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<float, 8, 1, 4, true>(p, *reinterpret_cast<RunSmem<float, 8, 1, 4, true> *>(smem), t.x, t.y, t.z);
     else
-        exp_runs_tile<float, 4, 2, 4>(p, *reinterpret_cast<RunSmem<float, 4, 2, 4> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<float, 4, 2, 4, true>(p, *reinterpret_cast<RunSmem<float, 4, 2, 4, true> *>(smem), t.x, t.y, t.z);
 }
 
 template <int SHAPE, typename PP>
