@@ -1274,6 +1274,13 @@ __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t *dst, int32_t n, 
 // keep every CU busy in one launch.  Every workgroup leaves once the counter
 // has passed the end of the list.
 // ---------------------------------------------------------------------------
+// Slots per run and round in the persistent kernel's runs tiles (8 measured
+// even on the uneven batch once the weights moved to scalar registers).
+#ifndef TFS_FUSED_RUNS_G
+#define TFS_FUSED_RUNS_G 4
+#endif
+constexpr int kFusedRunsG = TFS_FUSED_RUNS_G;
+
 template <int V>
 struct FusedSmem {
     static constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
@@ -1289,9 +1296,9 @@ struct FusedSmem {
                                 : cmax(cmax(sizeof(ExpSmem<float, 4, 4>), sizeof(ExpSmem<float, 4, 1>)),
                                        sizeof(ExpSmem<double, 4, 1>)));
     // runs tiles: FP64 (R = 4) or FP32 one bin (R = 8) and bin pairs (R = 4)
-    static constexpr size_t runs_bytes = V == kShapeD41 ? sizeof(RunSmem<double, 4, 1, 4, true>)
-                                         : cmax(sizeof(RunSmem<float, 8, 1, 4, true>),
-                                                sizeof(RunSmem<float, 4, 2, 4, true>));
+    static constexpr size_t runs_bytes = V == kShapeD41 ? sizeof(RunSmem<double, 4, 1, kFusedRunsG, true>)
+                                         : cmax(sizeof(RunSmem<float, 8, 1, kFusedRunsG, true>),
+                                                sizeof(RunSmem<float, 4, 2, kFusedRunsG, true>));
     static constexpr size_t bytes = cmax(cmax(exp_bytes, runs_bytes), sizeof(Red) * kWaves);
 };
 
@@ -1315,11 +1322,11 @@ template <int SHAPE, typename PP>
 __device__ __attribute__((always_inline)) inline void fused_runs(PP &p, char *smem,
                                                                  const BatchTile &t) {
     if constexpr (SHAPE == kShapeD41)
-        exp_runs_tile<double, 4, 1, 4, true>(p, *reinterpret_cast<RunSmem<double, 4, 1, 4, true> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<double, 4, 1, kFusedRunsG, true>(p, *reinterpret_cast<RunSmem<double, 4, 1, kFusedRunsG, true> *>(smem), t.x, t.y, t.z);
     else if constexpr (SHAPE == kShapeF81)
-        exp_runs_tile<float, 8, 1, 4, true>(p, *reinterpret_cast<RunSmem<float, 8, 1, 4, true> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<float, 8, 1, kFusedRunsG, true>(p, *reinterpret_cast<RunSmem<float, 8, 1, kFusedRunsG, true> *>(smem), t.x, t.y, t.z);
     else
-        exp_runs_tile<float, 4, 2, 4, true>(p, *reinterpret_cast<RunSmem<float, 4, 2, 4, true> *>(smem), t.x, t.y, t.z);
+        exp_runs_tile<float, 4, 2, kFusedRunsG, true>(p, *reinterpret_cast<RunSmem<float, 4, 2, kFusedRunsG, true> *>(smem), t.x, t.y, t.z);
 }
 
 template <int SHAPE, typename PP>
