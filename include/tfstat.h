@@ -292,7 +292,11 @@ int tfstat_tiling_config(tfstat_ctx *ctx, int32_t runs_min_spread, int32_t split
  *              candidate (tile shape x persistent workgroups per CU) on this
  *              batch and keep the fastest; the choice is cached in the
  *              context under the batch's shape signature and reused by
- *              later batches of the same shape.
+ *              later batches of the same shape; -1 - v: the fused-kernel
+ *              variant v of tfstat_batch_stats (0 or 5 for FP64; 1..4 or
+ *              6..9 for FP32) at its widest launch, without the tuning
+ *              cache (every variant gives the results of its tile shapes,
+ *              which lets a caller compare them).
  * The plan keeps its workspace in the arena, and its atoms busy, until
  * tfstat_batch_destroy.
  * Errors: E_INVAL, E_GRID, E_NOTFOUND, E_NOMEM, E_DEVICE.

@@ -214,9 +214,11 @@ class Context:
         _abi.check(self._lib.tfstat_tiling_config(self._ctx, int(runs_min_spread), int(split_min_bins)))
 
     # -- uneven batch ----------------------------------------------------------------
-    def batch(self, items, precision="fp32", tune: bool = False) -> "Batch":
-        """Plans a batch of maps: items is a sequence of (atoms_id, window)."""
-        return Batch(self, items, precision, tune)
+    def batch(self, items, precision="fp32", tune: bool = False, variant: str = None) -> "Batch":
+        """Plans a batch of maps: items is a sequence of (atoms_id, window).
+        variant (a name of Batch.stats()["variant"]) forces that fused-kernel
+        build instead of the default or the autotuner's choice."""
+        return Batch(self, items, precision, tune, variant)
 
     # -- profiling -----------------------------------------------------------------
     def profile(self, on: bool = True):
@@ -239,7 +241,7 @@ class Batch:
     """Many maps planned together and run as one captured graph with one
     persistent fused launch (tfstat_batch_*)."""
 
-    def __init__(self, ctx: Context, items, precision="fp32", tune: bool = False):
+    def __init__(self, ctx: Context, items, precision="fp32", tune: bool = False, variant: str = None):
         self._ctx = ctx
         self._lib = ctx._lib
         items = list(items)
@@ -250,8 +252,11 @@ class Batch:
         wins = (_abi.Window * len(items))(*[w.struct for w in self._wins])
         self._bins = [ctx._n_bins(int(a)) for a, _ in items]
         self._h = ctypes.c_void_p()
+        mode = 1 if tune else 0
+        if variant is not None:
+            mode = -1 - _abi.BATCH_VARIANTS.index(variant)
         _abi.check(self._lib.tfstat_batch_create(ctx._ctx, len(items), ids, wins, _prec(precision),
-                                                 1 if tune else 0, ctypes.byref(self._h)))
+                                                 mode, ctypes.byref(self._h)))
 
     def run(self, timed: bool = False) -> List[List[dict]]:
         """Runs the batch (graph replay, or direct launches timing the fused

@@ -1949,7 +1949,8 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
         if (n_maps < 1) raise(TFSTAT_E_INVAL, "n_maps must be >= 1");
         if (precision != TFSTAT_PREC_FP32 && precision != TFSTAT_PREC_FP64)
             raise(TFSTAT_E_INVAL, "a batch runs in FP32 or FP64");
-        if (tune != 0 && tune != 1) raise(TFSTAT_E_INVAL, "tune must be 0 or 1");
+        if (tune > 1 || tune < -2 * (tfs::kShapeMixed + 1))
+            raise(TFSTAT_E_INVAL, "tune must be 0, 1 or -1 - variant");
         ensure_batch_stream(ctx);
         const std::string sig = batch_signature(ctx, n_maps, ids, wins, precision);
         std::vector<int> variants;
@@ -1966,7 +1967,15 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
         int variant = precision == TFSTAT_PREC_FP64 ? tfs::kShapeD41 : tfs::kShapeMixed;
         int per_cu = 0;
         bool found = false;
-        {
+        if (tune < 0) {
+            // a given variant at its widest launch; the tuning cache is
+            // neither read nor written
+            variant = -1 - tune;
+            if (std::find(variants.begin(), variants.end(), variant) == variants.end())
+                raise(TFSTAT_E_INVAL, "variant not built for this precision");
+            found = true;
+        }
+        if (!found) {
             std::lock_guard<std::mutex> g(ctx->mu);
             auto it = ctx->tuned.find(sig);
             if (it != ctx->tuned.end()) {

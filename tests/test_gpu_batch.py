@@ -219,6 +219,58 @@ def test_batch_holds_atoms_and_rejects_bad_input(ctx):
         ctx.free(aid)
 
 
+def _variant_maps():
+    """Maps that reach every tile kind of the fused kernel: one-bin, five-bin
+    (four-bin group + one-bin tail) and six-bin (+ bin-pair tail) dense
+    maps, a nine-bin map (split form in FP32), a map whose rows are far
+    apart (runs form) and a rectangular map."""
+    maps = []
+    for i, nb in enumerate((1, 5, 6, 9)):
+        atoms = tfsynth.make_atoms(7900 + i, 420 + 60 * i, 0.1, n_bins=nb)
+        maps.append((atoms, tfsynth.regular_window("exp", 3 * T + 11, T, 90 + 7 * i, 2 * T, 3 * T, 33)))
+    atoms = tfsynth.make_atoms(7910, 1500, 0.12, n_bins=3)
+    maps.append((atoms, tfsynth.regular_window("exp", 0, 9 * T, 100, 2 * T, 5 * T, 40)))
+    atoms = tfsynth.make_atoms(7911, 500, 0.1, n_bins=2)
+    maps.append((atoms, tfsynth.regular_window("rect", 0, T, 150, 2 * T, T, 120)))
+    return maps
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_every_fused_variant(ctx, prec):
+    """Each build of the persistent kernel (every tile shape, each at the
+    stand-alone waves per SIMD and one fewer) forced on one batch of maps
+    that reaches every tile kind: each map matches the oracle."""
+    _case("every fused variant " + prec)
+    import paper_1805_05652_amd._abi as abi
+    maps = _variant_maps()
+    refs = []
+    for atoms, win in maps:
+        ref = oracle.fmap_atoms(atoms, win)
+        refs.append((ref, oracle.reduce(ref)))
+    ids = upload_all(ctx, maps)
+    names = ["fp64_r4"] if prec == "fp64" else ["fp32_r8", "fp32_r4_b2", "fp32_r4_b4", "mixed"]
+    names = names + [v + "_lowocc" for v in names]
+    try:
+        for name in names:
+            assert name in abi.BATCH_VARIANTS
+            with ctx.batch(list(zip(ids, [w for _, w in maps])), prec, variant=name) as b:
+                assert b.stats()["variant"] == name
+                got = b.run()
+            for (atoms, win), (ref, (mx, am, lb)), res in zip(maps, refs, got):
+                assert len(res) == atoms.n_bins
+                for bn, r in enumerate(res):
+                    assert abs(r["logB"] - lb[bn]) <= 1e-3, (name, bn, r["logB"], lb[bn])
+                    assert abs(r["max2F"] - mx[bn]) <= TOL[prec] * max(mx[bn], 1.0), (name, bn, r["max2F"], mx[bn])
+                    idx = r["m"] * win.n_tau + r["n"]
+                    assert idx == am[bn] or ref[bn].ravel()[idx] >= (1 - 1e-4) * mx[bn], (name, bn, idx, am[bn])
+        with pytest.raises(RuntimeError):
+            ctx.batch(list(zip(ids, [w for _, w in maps])), prec,
+                      variant="fp32_r8" if prec == "fp64" else "fp64_r4")
+    finally:
+        for aid in ids:
+            ctx.free(aid)
+
+
 def test_full_uneven_batch_64_candidates():
     """The 64-candidate uneven batch at full size, in the launch
     configuration the benchmark times (autotuned): every map equals the
