@@ -99,6 +99,17 @@ def test_rect_small_workload(ctx, prec):
     run_and_check(ctx, atoms, win, prec)
 
 
+@pytest.mark.parametrize("n_t0,n_tau", [(1, 1), (63, 64), (64, 65), (65, 1), (130, 129)])
+def test_rect_tile_edges(ctx, n_t0, n_tau):
+    """Rect tiles are 64 rows x 64 taus with one reduction per tile: grids
+    one row / one tau short of, at and past a tile edge, every cell of the
+    map and the per-bin results against the oracle (two bins)."""
+    _case("rect tile edges %d x %d" % (n_t0, n_tau))
+    atoms = tfsynth.make_atoms(260 + n_t0, 300, 0.1, n_bins=2)
+    win = tfsynth.regular_window("rect", 2 * T + 5, T, n_t0, T + 3, 2 * T, n_tau)
+    run_and_check(ctx, atoms, win, "fp64")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("kind", ["rect", "exp"])
 def test_ragged_grid_with_edges(ctx, prec, kind):
