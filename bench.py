@@ -289,6 +289,11 @@ def bench_batch(args, tf, torch):
     seq_ms = (time.perf_counter() - ts) * 1e3
     same = all(r1 == r2 for a, b in zip(res, seq) for r1, r2 in zip(a, b))
     same = same and timed == res
+    # the kept variant may run a map in other tile shapes than a single call
+    # (same terms, other partial sums): the largest differences per bin
+    d2f = max(abs(r1["max2F"] - r2["max2F"]) / max(abs(r2["max2F"]), 1.0)
+              for a, b in zip(res, seq) for r1, r2 in zip(a, b))
+    dlb = max(abs(r1["logB"] - r2["logB"]) for a, b in zip(res, seq) for r1, r2 in zip(a, b))
     fused_ms = float(np.mean(fused))
     # algorithmic flops of the fused kernel: 4 FMA per exp cell*SFT*bin, 3 FP64
     # FMA (A, B, C) per exp cell*SFT of the maps whose A, B, C it sums (the
@@ -314,7 +319,8 @@ def bench_batch(args, tf, torch):
         "batch": {"variant": st["variant"], "groups": st["groups"], "tiles": st["n_tiles"],
                   "tune_ms": st["tune_ms"], "plan_s": plan_s, "graph_ms": st["last_ms"],
                   "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / ms,
-                  "results_equal_sequential": bool(same)},
+                  "results_equal_sequential": bool(same),
+                  "max_rel_diff_max2F_vs_sequential": d2f, "max_abs_diff_logB_vs_sequential": dlb},
         "roofline": roof,
     }
     batch.close()
