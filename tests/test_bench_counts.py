@@ -65,3 +65,38 @@ def test_workload_counts_match_recipes():
     present, slots = bench.work_counts(atoms, win)
     assert slots == 2162207818
     assert 0.84 * slots < present < 0.86 * slots       # 15% gaps
+
+
+def test_work_counts_brute_force():
+    """Off-slot start times, gaps, windows before, inside and past the data:
+    work_counts equals a per-cell count of the SFT start times and of the
+    slot start times in [t0, t0 + span), cut at the data end."""
+    atoms = tfsynth.make_atoms(11, 120, 0.25, n_bins=2)
+    ts = atoms.timestamps
+    T0 = int(ts[0])
+    t_end = T0 + atoms.t_data
+    t0 = np.array([-3 * T - 5, -1, 0, 7, T + 1, 40 * T + 900, 118 * T, 130 * T], dtype=np.int64)
+    tau = np.array([1, T - 1, T, 2 * T + 3, 17 * T, 200 * T], dtype=np.int64)
+    for kind, mult in (("rect", 1), ("exp", 3)):
+        win = tfsynth.list_window(kind, t0, tau)
+        present = slots = 0
+        for a in t0.tolist():
+            for t in tau.tolist():
+                e = a + mult * t
+                present += sum(1 for s in ts.tolist() if a <= s < e)
+                slots += sum(1 for k in range(atoms.n_slots) if a <= T0 + k * T < min(e, t_end))
+        assert bench.work_counts(atoms, win) == (present * 2, slots * 2), kind
+
+
+def test_mfma_cells_blocks():
+    """The matrix-core share counts exactly the tau blocks of 8 whose
+    shortest band (ceil(3 tau / T_sft) slots) is at least 64."""
+    atoms = _gapless(600, n_bins=3)
+    tau = np.concatenate([np.full(8, 30 * T), np.full(8, 21 * T), [21 * T + 1] * 7 + [10 * T],
+                          np.full(3, 40 * T)]).astype(np.int64)
+    win = tfsynth.list_window("exp", np.arange(20, dtype=np.int64) * T, tau)
+    # blocks: all bands 90 (in), all 63 (out), seven 64 and one 30 (out), three 120 (in)
+    keep = np.r_[np.ones(8, bool), np.zeros(16, bool), np.ones(3, bool)]
+    want = bench.work_counts(atoms, tfsynth.list_window("exp", win.t0, tau[keep]))[0]
+    assert bench.mfma_cells(atoms, win) == want
+    assert 0 < want < bench.work_counts(atoms, win)[0]
