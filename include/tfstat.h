@@ -283,20 +283,29 @@ int tfstat_tiling_config(tfstat_ctx *ctx, int32_t runs_min_spread, int32_t split
  * launch in which every workgroup draws tiles of all maps from a shared
  * list (largest expected cost first), then the per-bin merges.  Every
  * result equals what tfstat_fmap returns for the same map at the same
- * precision (same arithmetic per cell, same tile partials and merge order).
+ * precision (same arithmetic per cell, same tile partials and merge order),
+ * so a map's results do not depend on which other maps share its batch
+ * (tune = 0 or 1; a forced variant, tune = -1 - v, may change tile shapes).
  * No maps are materialised.
  *   n_maps     number of maps; ids[i] and wins[i] describe map i.
- *   precision  TFSTAT_PREC_FP32 or TFSTAT_PREC_FP64 (exponential sums;
- *              rectangular windows always use compensated FP64 prefixes).
- *   tune       0: default tile shapes and launch width; 1: time every
- *              candidate (tile shape x persistent workgroups per CU) on this
- *              batch and keep the fastest; the choice is cached in the
- *              context under the batch's shape signature and reused by
- *              later batches of the same shape; -1 - v: the fused-kernel
- *              variant v of tfstat_batch_stats (0 or 5 for FP64; 1..4 or
- *              6..9 for FP32) at its widest launch, without the tuning
- *              cache (every variant gives the results of its tile shapes,
- *              which lets a caller compare them).
+ *   precision  TFSTAT_PREC_FP32, TFSTAT_PREC_FP64 or TFSTAT_PREC_BF16X3
+ *              (exponential sums; rectangular windows always use compensated
+ *              FP64 prefixes).  In BF16X3 the matrix-core work of all maps
+ *              is one more launch after the persistent one; matrix-core
+ *              shape windows are refused (E_INVAL; tfstat_fmap runs them).
+ *   tune       0: each map's own tile shape, default launch width;
+ *              1: time every candidate that keeps each map's own tile shape
+ *              (the build for the stand-alone kernel's waves per SIMD or one
+ *              fewer x persistent workgroups per CU) on this batch and keep
+ *              the fastest; the choice is cached in the context under the
+ *              batch's shape signature and reused by later batches of the
+ *              same shape.  Results are those of tfstat_fmap either way.
+ *              -1 - v: the fused-kernel variant v of tfstat_batch_stats
+ *              (0 or 5 for FP64; 1..4 or 6..9 for FP32) at its widest
+ *              launch, without the tuning cache; variants other than 0, 5
+ *              (FP64) and 4, 9 (FP32) impose one tile shape on every map, so
+ *              their results agree with tfstat_fmap within rounding only
+ *              (which lets a caller compare the shapes).
  * The plan keeps its workspace in the arena, and its atoms busy, until
  * tfstat_batch_destroy.
  * Errors: E_INVAL, E_GRID, E_NOTFOUND, E_NOMEM, E_DEVICE.
@@ -314,6 +323,8 @@ typedef struct {
     double tune_ms;           /* host time spent tuning (0 if not tuned here) */
     double last_ms;           /* device time of the last run (HIP events) */
     double last_fused_ms;     /* device time of the fused launch in the last timed run */
+    double last_mfma_ms;      /* device time of the matrix-core launch of BF16X3 maps in the
+                                 last timed run (0 without such maps) */
 } tfstat_batch_stats;
 
 int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *ids,

@@ -203,6 +203,16 @@ def fmap_atoms(atoms, win, n_threads: int = 0) -> np.ndarray:
                 atoms.fa, atoms.fb, win.t0, win.tau, n_threads)
 
 
+def cells_atoms(atoms, win, m_idx, n_idx, n_threads: int = 0) -> np.ndarray:
+    """Convenience: 2F at cells (m_idx[i], n_idx[i]) from generator objects,
+    float64 [n_bins, n_sel]."""
+    if win.kind == "shape":
+        return cells_shape(win.shape, win.support, atoms.timestamps, atoms.a2, atoms.b2, atoms.ab,
+                           atoms.fa, atoms.fb, win.t0, win.tau, m_idx, n_idx, n_threads)
+    return cells(win.kind, atoms.timestamps, atoms.a2, atoms.b2, atoms.ab,
+                 atoms.fa, atoms.fb, win.t0, win.tau, m_idx, n_idx, n_threads)
+
+
 def results(atoms, win, twoF: np.ndarray):
     """Per-bin result records {max2F, m, n, t0, tau, logB} from a full map."""
     mx, am, lb = reduce(twoF)

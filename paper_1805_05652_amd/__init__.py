@@ -274,7 +274,7 @@ class Batch:
         _abi.check(self._lib.tfstat_batch_stats_read(self._h, ctypes.byref(st)))
         return dict(variant=_abi.BATCH_VARIANTS[st.variant], groups=st.groups, n_tiles=st.n_tiles,
                     n_results=st.n_results, tune_ms=st.tune_ms, last_ms=st.last_ms,
-                    last_fused_ms=st.last_fused_ms)
+                    last_fused_ms=st.last_fused_ms, last_mfma_ms=st.last_mfma_ms)
 
     def close(self):
         if self._h:

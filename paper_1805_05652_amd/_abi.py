@@ -79,6 +79,7 @@ class BatchStats(ctypes.Structure):
         ("tune_ms", ctypes.c_double),
         ("last_ms", ctypes.c_double),
         ("last_fused_ms", ctypes.c_double),
+        ("last_mfma_ms", ctypes.c_double),
     ]
 
 

@@ -1060,8 +1060,11 @@ __global__ __launch_bounds__(256) void build_x32_kernel(const double *x64, float
 // Exclusive prefix sums over slots (rectangular windows: section 3's running
 // sums turned into O(1) differences per cell), carried as unevaluated
 // double-double pairs so that a window's difference keeps full FP64 accuracy
-// relative to the window sum itself, however long the prefix.
-//   out[k][c] = hi, out[k][C + c] = lo with hi + lo = sum_{j<k} in[j][c].
+// relative to the window sum itself, however long the prefix.  Channels come
+// in groups of four (a^2, b^2, ab, 0; or the four data components of one
+// bin); group g's prefixes are laid out [g][K+1][8]: the four hi terms,
+// then the four lo terms, hi + lo = sum_{j<k} in[j][c], so that one window
+// end of one group is one contiguous 64-byte read.
 // Lane = channel, wave = slot segment.
 // ---------------------------------------------------------------------------
 constexpr int kScanWaves = 16;
@@ -1098,7 +1101,8 @@ __device__ __attribute__((always_inline)) inline void scan_chunk(const double *_
     const int seg = (K + kScanWaves - 1) / kScanWaves;
     const int kb = min(K, wave * seg);
     const int ke = min(K, kb + seg);
-    const size_t row = 2 * (size_t)C;
+    constexpr size_t row = 8;
+    double *o = out + (size_t)(c >> 2) * ((size_t)K + 1) * 8 + (c & 3);   // this channel's hi terms
     // kSU slots' loads are issued before their (sequential) sums
     constexpr int kSU = 8;
     DD sum{0.0, 0.0};
@@ -1119,8 +1123,8 @@ __device__ __attribute__((always_inline)) inline void scan_chunk(const double *_
     for (int w = 0; w < wave; ++w) run = dd_add(run, tot[w][lane]);
     if (c < C) {
         if (wave == 0) {
-            out[c] = 0.0;
-            out[C + c] = 0.0;
+            o[0] = 0.0;
+            o[4] = 0.0;
         }
         int k = kb;
         for (; k + kSU <= ke; k += kSU) {
@@ -1130,14 +1134,14 @@ __device__ __attribute__((always_inline)) inline void scan_chunk(const double *_
 #pragma unroll
             for (int u = 0; u < kSU; ++u) {
                 run = dd_add(run, v[u]);
-                out[(size_t)(k + u + 1) * row + c] = run.h;
-                out[(size_t)(k + u + 1) * row + C + c] = run.l;
+                o[(size_t)(k + u + 1) * row] = run.h;
+                o[(size_t)(k + u + 1) * row + 4] = run.l;
             }
         }
         for (; k < ke; ++k) {
             run = dd_add(run, in[(size_t)k * stride + c]);
-            out[(size_t)(k + 1) * row + c] = run.h;
-            out[(size_t)(k + 1) * row + C + c] = run.l;
+            o[(size_t)(k + 1) * row] = run.h;
+            o[(size_t)(k + 1) * row + 4] = run.l;
         }
     }
 }
@@ -1157,24 +1161,30 @@ __global__ __launch_bounds__(kScanWaves * 64) void scan_batch_kernel(const ScanJ
 
 // ---------------------------------------------------------------------------
 // Rectangular-window cells: window sums as prefix differences, finalize,
-// optional map, per-tile reduction.  Tile = kRectRows rows x 64 taus of one
-// bin: lane = tau, the waves take every fourth row, and each lane keeps a
-// running (max, sum, first argmax) over its cells, so the tile reduces once.
+// optional map, per-tile reduction.  Tile = kRectRows rows x 64 taus x
+// kRectBins bins: lane = tau, the waves take every fourth row; A, B, C and
+// 2 / D of a cell are formed once for its bins, and each lane keeps a
+// running (max, sum, first argmax) per bin, so the tile reduces once.
 // ---------------------------------------------------------------------------
 template <typename PP>
-__device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red *wred,
-                                                                 int bx, int by, int bin) {
+__device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wred)[kRectBins],
+                                                                 int bx, int by, int bg) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = bx * 64 + lane;
     const bool n_ok = n < p.n_tau;
     const int nn = min(n, p.n_tau - 1);
     const int64_t tau = p.tau[nn];
     const int64_t T = p.t_sft;
     const int64_t K = p.K;
-    const int64_t CW = (int64_t)p.n_bins * 4;
-    Red r = red_empty();
-#pragma unroll 1
+    const int bin0 = bg * kRectBins;
+    const int nbg = min(kRectBins, p.n_bins - bin0);
+    const size_t bin_stride = ((size_t)K + 1) * 8;   // prefixes of one bin: [K+1][8]
+    const double *pxb = p.px + (size_t)bin0 * bin_stride;
+    Red r[kRectBins];
+#pragma unroll
+    for (int b = 0; b < kRectBins; ++b) r[b] = red_empty();
+#pragma unroll 2
     for (int i = 0; i < kRectRows / kWaves; ++i) {
         const int m = by * kRectRows + i * kWaves + wave;
         if (m >= p.n_t0) break;
@@ -1182,30 +1192,46 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red *wre
         const int64_t L = tau > rp.delta ? (tau - rp.delta + T - 1) / T : 0;
         const int64_t lo = min(max((int64_t)rp.k0, (int64_t)0), K);
         const int64_t hi = min(max((int64_t)rp.k0 + L, (int64_t)0), K);
-        // window sums from compensated prefixes: (hi_h - hi_l) + (lo_h - lo_l)
+        // window sums from compensated prefixes: (hi_h - lo_h) + (hi_l - lo_l)
         const double *a_hi = p.pabc + hi * 8;
         const double *a_lo = p.pabc + lo * 8;
         const double A = (a_hi[0] - a_lo[0]) + (a_hi[4] - a_lo[4]);
         const double B = (a_hi[1] - a_lo[1]) + (a_hi[5] - a_lo[5]);
         const double C = (a_hi[2] - a_lo[2]) + (a_hi[6] - a_lo[6]);
-        const double *x_hi = p.px + hi * 2 * CW + bin * 4;
-        const double *x_lo = p.px + lo * 2 * CW + bin * 4;
-        double f[4];
+        // 2F = (2 / D) (B |F_a|^2 + A |F_b|^2 - 2 C Re(F_a F_b*)) (eq. F_FaFb);
+        // a degenerate window (D <= rtol A B) gets 2F = 0
+        const double D = A * B - C * C;
+        const double k = D > kDegenerateRtol * A * B ? 2.0 / D : 0.0;
+        const double kA = k * A, kB = k * B, kC = 2.0 * k * C;
+        const long long idx = (long long)m * p.n_tau + n;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) f[c] = (x_hi[c] - x_lo[c]) + (x_hi[CW + c] - x_lo[CW + c]);
-        const double v = twoF_cell(A, B, C, f[0], f[1], f[2], f[3]);
-        if (n_ok) {
-            if (p.twoF) p.twoF[((size_t)bin * p.n_t0 + m) * p.n_tau + n] = (float)v;
-            red_add(r, 0.5 * v, (long long)m * p.n_tau + n);
+        for (int b = 0; b < kRectBins; ++b) {
+            if (b >= nbg) break;
+            const double *x_hi = pxb + b * bin_stride + hi * 8;
+            const double *x_lo = pxb + b * bin_stride + lo * 8;
+            double f[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) f[c] = (x_hi[c] - x_lo[c]) + (x_hi[4 + c] - x_lo[4 + c]);
+            const double v = kB * (f[0] * f[0] + f[1] * f[1]) + kA * (f[2] * f[2] + f[3] * f[3])
+                             - kC * (f[0] * f[2] + f[1] * f[3]);
+            if (n_ok) {
+                if (p.twoF) p.twoF[((size_t)(bin0 + b) * p.n_t0 + m) * p.n_tau + n] = (float)v;
+                red_add(r[b], 0.5 * v, idx);
+            }
         }
     }
-    r = red_wave(r);
-    if (lane == 0) wred[wave] = r;
+#pragma unroll
+    for (int b = 0; b < kRectBins; ++b) {
+        if (b >= nbg) break;
+        const Red w = red_wave(r[b]);
+        if (lane == 0) wred[wave][b] = w;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        Red t = wred[0];
-        for (int w = 1; w < kWaves; ++w) t = red_combine(t, wred[w]);
-        Partial &o = p.part[(size_t)bin * p.n_tiles + by * p.n_tiles_n + bx];
+    if (threadIdx.x < nbg) {
+        const int b = threadIdx.x;
+        Red t = wred[0][b];
+        for (int w = 1; w < kWaves; ++w) t = red_combine(t, wred[w][b]);
+        Partial &o = p.part[(size_t)(bin0 + b) * p.n_tiles + by * p.n_tiles_n + bx];
         o.fmax = t.f;
         o.s = t.s;
         o.idx = t.i;
@@ -1213,7 +1239,7 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red *wre
 }
 
 __global__ __launch_bounds__(256) void rect_kernel(RectParams p) {
-    __shared__ Red wred[kWaves];
+    __shared__ Red wred[kWaves][kRectBins];
     rect_block(p, wred, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
@@ -1299,7 +1325,7 @@ struct FusedSmem {
     static constexpr size_t runs_bytes = V == kShapeD41 ? sizeof(RunSmem<double, 4, 1, kFusedRunsG, true>)
                                          : cmax(sizeof(RunSmem<float, 8, 1, kFusedRunsG, true>),
                                                 sizeof(RunSmem<float, 4, 2, kFusedRunsG, true>));
-    static constexpr size_t bytes = cmax(cmax(exp_bytes, runs_bytes), sizeof(Red) * kWaves);
+    static constexpr size_t bytes = cmax(cmax(exp_bytes, runs_bytes), sizeof(Red) * kWaves * kRectBins);
 };
 
 
@@ -1366,7 +1392,7 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
         const BatchTile t = load_uniform(p.tiles + ti);   // one tile, held in scalar registers
         if (t.kind == 1) {
             auto &rp = const_params(p.rect_jobs + t.job);
-            rect_block(rp, reinterpret_cast<Red *>(smem), t.x, t.y, t.z);
+            rect_block(rp, reinterpret_cast<Red (*)[kRectBins]>(smem), t.x, t.y, t.z);
             continue;
         }
         auto &ep = const_params(p.exp_jobs + t.job);
@@ -1540,7 +1566,7 @@ hipError_t launch_scan(const double *in, int64_t stride, double *out, int32_t K,
 
 hipError_t launch_rect(const RectParams &p, hipStream_t s) {
     const dim3 grid((unsigned)p.n_tiles_n, (unsigned)((p.n_t0 + kRectRows - 1) / kRectRows),
-                    (unsigned)p.n_bins);
+                    (unsigned)((p.n_bins + kRectBins - 1) / kRectBins));
     hipLaunchKernelGGL(rect_kernel, grid, dim3(256), 0, s, p);
     return hipGetLastError();
 }

@@ -24,6 +24,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace tfs {
 
 namespace {
@@ -444,6 +446,306 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
     }
 }
 
+// ---------------------------------------------------------------------------
+// Any t0 grid: weights computed in registers.
+//
+// Work item: 64 t0 rows x 16 bins x 8 taus, one wave per 16 rows, in two
+// passes of 4 taus.  Each wave runs its own K range, from its first row's
+// slot to the furthest band end of its rows, so rows may be any distance
+// apart.  The A operand of one K step is the lane's 8 weights
+//   w_j = exp(-(t_{k+j} - t0_m) / tau) = 2^((d + j) c_T + c_delta),
+//   d = k - k0_m, c_T = -T log2(e) / tau, c_delta = -delta_m log2(e) / tau,
+// zero outside the row's window (0 <= d + j < L_m: the SFT start times in
+// [t0_m, t0_m + 3 tau)), generated as one exp2 and 7 products by
+// exp(-T / tau), then split into bf16 hi + lo.  The row scale and the exact
+// band end of every row are in the weights, so no correction terms remain;
+// A, B, C (FP64, the same weights squared) come from the VALU A/B/C pass.
+// ---------------------------------------------------------------------------
+struct RowsSmem {
+    double abc[4][16][kBlk][3];   // per wave: its rows' folded A, B, C of the block
+    Red wred[4][16];
+};
+
+// The lane's 8 weights of one K step as bf16 hi and lo parts (round to
+// nearest even; lo = bf16(w - hi), exact before its own rounding).  The
+// exponential is the hardware base-2 one: within a window its argument is in
+// (-3 log2(e), 0], far from the range where it would flush to zero.  EDGE:
+// the step may hold slots outside the lane's window [0, L), which weigh 0.
+template <bool EDGE>
+__device__ __attribute__((always_inline)) inline void rows_weights(int d0, float cT, float cD, float rho, int L,
+                                                                 bf16x8 &hi, bf16x8 &lo) {
+    float w[8];
+    w[0] = __builtin_amdgcn_exp2f(fmaf((float)d0, cT, cD));
+#pragma unroll
+    for (int j = 1; j < 8; ++j) w[j] = w[j - 1] * rho;
+    if constexpr (EDGE) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if ((unsigned)(d0 + j) >= (unsigned)L) w[j] = 0.f;
+    }
+    u32x4 h, l;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        const bf16x2 h2 = {(__bf16)w[2 * p], (__bf16)w[2 * p + 1]};
+        const unsigned u = __builtin_bit_cast(unsigned, h2);
+        // hi parts as floats: the low half moved up (a byte permute, so that
+        // the compiler does not convert w again) and the high half masked
+        const float h0 = __uint_as_float(__builtin_amdgcn_perm(0u, u, 0x01000c0cu));
+        const float h1 = __uint_as_float(u & 0xffff0000u);
+        const bf16x2 l2 = {(__bf16)(w[2 * p] - h0), (__bf16)(w[2 * p + 1] - h1)};
+        h[p] = u;
+        l[p] = __builtin_bit_cast(unsigned, l2);
+    }
+    hi = bitcast4<bf16x8>(h);
+    lo = bitcast4<bf16x8>(l);
+}
+
+// Buffer resource of `bytes` bytes at `base` (raw buffer: stride 0, offsets
+// in bytes; reads past the end return zero).
+__device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename PP>
+__device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, RowsSmem &sm, int q, int row_tile,
+                                                                   int col_tile) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nb = p.blk_list[q];
+    const int tile = nb * p.n_row_tiles + row_tile;
+    const int n_t0 = p.n_t0;
+    const int m_w = row_tile * 64 + 16 * wave;   // first row of this wave
+    const int lrow = lane & 15;                  // A row / C column within the 16 tile
+    const int kg = lane >> 4;                    // K group of 8
+    const int bin = col_tile * 16 + lrow;
+    const bool bin_ok = bin < p.n_bins;
+    const int64_t T = p.t_sft;
+
+    // the lane's A row (rows past the grid repeat the last one; never written)
+    const RowPlan ra = p.rows[min(m_w + lrow, n_t0 - 1)];
+    const int k_first = __builtin_amdgcn_readfirstlane(p.rows[min(m_w, n_t0 - 1)].k0);
+
+    // planes [4][kp / 32][bins16][32]: lane's 8 slots of step kb for its bin.
+    // One buffer resource per component and part (scalar registers), the
+    // step's offset in a scalar, the lane's own offset in a vector register:
+    // no vector address arithmetic per load (component planes are < 2^31
+    // bytes, which the planner checks).
+    const uint32_t comp_bytes = (uint32_t)p.bins16 * (uint32_t)p.kp * 2u;
+    const uint32_t step_bytes = (uint32_t)p.bins16 * 64u;
+    const uint32_t lane_off = (uint32_t)((col_tile * 16 + lrow) * 32 + 8 * kg) * 2u;
+    __amdgpu_buffer_rsrc_t rh[4], rl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        rh[c] = plane_rsrc(p.xhi + (size_t)c * p.bins16 * p.kp, comp_bytes);
+        rl[c] = plane_rsrc(p.xlo + (size_t)c * p.bins16 * p.kp, comp_bytes);
+    }
+    auto load_b = [&](int kb, u32x4 *h, u32x4 *l) {
+        const int so = (int)((uint32_t)(kb >> 5) * step_bytes);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            h[c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh[c], (int)lane_off, so, 0));
+            l[c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl[c], (int)lane_off, so, 0));
+        }
+    };
+
+    // A, B, C of the wave's 16 rows x 8 taus, with 2 / D folded in, into the
+    // wave's own LDS region (rows of abc_cell hold whole blocks)
+    for (int e = lane; e < 16 * kBlk; e += 64) {
+        const int r = e / kBlk, t = e % kBlk;
+        const int m = min(m_w + r, n_t0 - 1);
+        const double *src = p.abc_cell + ((size_t)m * p.abc_pitch + (size_t)nb * kBlk + t) * 3;
+        double abc[3] = {src[0], src[1], src[2]};
+        fold_abc(abc, 1.0);
+        sm.abc[wave][r][t][0] = abc[0];
+        sm.abc[wave][r][t][1] = abc[1];
+        sm.abc[wave][r][t][2] = abc[2];
+    }
+
+    Red red = red_empty();
+#pragma unroll 1
+    for (int half = 0; half < kBlk / kNT; ++half) {
+        const int t0 = half * kNT;
+        // the pass's weight constants for the lane's row
+        float cT[kNT], cD[kNT], rho[kNT];
+        int L[kNT];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+            const int n = min(nb * kBlk + t0 + t, p.n_tau - 1);
+            const int64_t tau = p.tau[n];
+            const double inv = 1.4426950408889634 / (double)tau;
+            cT[t] = (float)(-(double)T * inv);
+            cD[t] = (float)(-(double)ra.delta * inv);
+            rho[t] = exp2f(cT[t]);
+            const int64_t span = 3 * tau;
+            L[t] = span > ra.delta ? (int)min((span - ra.delta + T - 1) / T, (int64_t)1 << 30) : 0;
+        }
+        // K range of the wave: its first row's slot to the furthest band end
+        // of its rows (taus increase within a block: the pass's last is the
+        // longest), rounded to an even number of 32-slot steps (B plane
+        // columns kp_data .. kp are zero)
+        int kend = (int)min((int64_t)ra.k0 + L[kNT - 1], (int64_t)p.kp_data);
+        // steps that hold no window edge of any lane and tau: from the last
+        // row's slot to the earliest band end (the pass's first tau)
+        int kin_lo = ra.k0;
+        int kin_hi = (int)min((int64_t)ra.k0 + L[0], (int64_t)1 << 30);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            kend = max(kend, __shfl_xor(kend, o, 64));
+            kin_lo = max(kin_lo, __shfl_xor(kin_lo, o, 64));
+            kin_hi = min(kin_hi, __shfl_xor(kin_hi, o, 64));
+        }
+        kend = __builtin_amdgcn_readfirstlane(kend);
+        kin_lo = __builtin_amdgcn_readfirstlane(kin_lo);
+        kin_hi = __builtin_amdgcn_readfirstlane(kin_hi);
+        const int kb_begin = max(k_first, 0) & ~31;
+        const int kb_data_end = min((kend + 31) & ~31, p.kp_data);
+        const int kb_end = kb_data_end > kb_begin ? kb_begin + ((kb_data_end - kb_begin + 63) & ~63) : kb_begin;
+
+        f32x4 acc[kNT][4];
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        // one K step: per tau, the lane's weights, then 12 products (three
+        // bf16 products of the four data components)
+        auto step = [&](auto edge, int kb, const u32x4 *ch, const u32x4 *cl) {
+            const int d0 = kb + 8 * kg - ra.k0;
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) {
+                bf16x8 ah, al;
+                rows_weights<decltype(edge)::value>(d0, cT[t], cD[t], rho[t], L[t], ah, al);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bitcast4<bf16x8>(ch[c]), acc[t][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bitcast4<bf16x8>(cl[c]), acc[t][c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bitcast4<bf16x8>(ch[c]), acc[t][c], 0, 0, 0);
+            }
+        };
+        if (kb_begin < kb_end) {
+            u32x4 bh[4], bl[4], nh[4], nl[4];
+            load_b(kb_begin, bh, bl);
+            auto run = [&](int kb, const u32x4 *ch, const u32x4 *cl) {
+                if (kb < kin_lo || kb + 32 > kin_hi)
+                    step(std::true_type{}, kb, ch, cl);
+                else
+                    step(std::false_type{}, kb, ch, cl);
+            };
+#pragma unroll 1
+            for (int kb = kb_begin; kb < kb_end; kb += 64) {
+                load_b(kb + 32, nh, nl);
+                run(kb, bh, bl);
+                load_b(min(kb + 64, kb_end - 32), bh, bl);
+                run(kb + 32, nh, nl);
+            }
+        }
+
+        // the folded A, B, C written by other lanes of this wave
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __builtin_amdgcn_wave_barrier();
+        // finalize: lane holds rows 4 kg + r (r < 4) of the wave for `bin`
+        double v2[kNT][4];
+        double fmx = -INFINITY;
+        long long imx = 0x7fffffffffffffffLL;
+#pragma unroll
+        for (int t = 0; t < kNT; ++t) {
+            const int n = nb * kBlk + t0 + t;
+            const bool n_ok = n < p.n_tau;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m_w + 4 * kg + r;
+                v2[t][r] = -INFINITY;
+                if (!n_ok || m >= n_t0 || !bin_ok) continue;
+                const double v = twoF_folded(sm.abc[wave][4 * kg + r][t0 + t], (double)acc[t][0][r],
+                                             (double)acc[t][1][r], (double)acc[t][2][r], (double)acc[t][3][r]);
+                if (p.twoF) p.twoF[((size_t)bin * n_t0 + m) * p.n_tau + n] = (float)v;
+                v2[t][r] = v;
+                const long long idx = (long long)m * p.n_tau + n;
+                if (v > fmx || (v == fmx && idx < imx)) {
+                    fmx = v;
+                    imx = idx;
+                }
+            }
+        }
+        if (fmx != -INFINITY) {
+            double sum = 0.0;
+#pragma unroll
+            for (int t = 0; t < kNT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (v2[t][r] != -INFINITY) sum += (double)__expf((float)(0.5 * (v2[t][r] - fmx)));
+            red = red_combine(red, Red{0.5 * fmx, sum, imx});
+        }
+    }
+
+    // lanes sharing a bin: xor 16, 32; then the four waves in order
+    red = red_combine(red, red_shfl_xor(red, 16));
+    red = red_combine(red, red_shfl_xor(red, 32));
+    if (lane < 16) sm.wred[wave][lane] = red;
+    __syncthreads();
+    if (tid < 16) {
+        const int b = col_tile * 16 + tid;
+        if (b < p.n_bins) {
+            Red tt = sm.wred[0][tid];
+            for (int w = 1; w < 4; ++w) tt = red_combine(tt, sm.wred[w][tid]);
+            Partial &o = p.part[(size_t)b * p.n_tiles + tile];
+            o.fmax = tt.f;
+            o.s = tt.s;
+            o.idx = tt.i;
+        }
+    }
+}
+
+#ifndef TFS_ROWS_WAVES
+#define TFS_ROWS_WAVES 2       // waves per SIMD the register budget targets
+#endif
+
+// XCD-aware task order as in exp_mfma_kernel: column tiles dealt to the XCDs
+// when there are at least 8 of them, otherwise the tau blocks.
+__global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpMfmaRowsParams p) {
+    __shared__ RowsSmem sm;
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7;
+    const int slot = bid >> 3;
+    int q, row_tile, col_tile;
+    if (p.n_col_tiles >= 8) {
+        const int cpx = (p.n_col_tiles + 7) / 8;
+        const int per_block = p.n_row_tiles * cpx;
+        q = slot / per_block;
+        const int rem = slot % per_block;
+        row_tile = rem / cpx;
+        col_tile = (rem % cpx) * 8 + xcd;
+        if (q >= p.n_blocks || col_tile >= p.n_col_tiles) return;
+    } else {
+        const int per_block = p.n_row_tiles * p.n_col_tiles;
+        q = (slot / per_block) * 8 + xcd;
+        if (q >= p.n_blocks) return;
+        const int rem = slot % per_block;
+        row_tile = rem / p.n_col_tiles;
+        col_tile = rem % p.n_col_tiles;
+    }
+    mfma_rows_tile(p, sm, q, row_tile, col_tile);
+}
+
+// Matrix-core work items of many maps (one entry per workgroup).
+__global__ __launch_bounds__(256, TFS_ROWS_WAVES) void mfma_batch_kernel(MfmaBatchParams b) {
+    __shared__ RowsSmem sm;
+    const int e = blockIdx.x;
+    const int job = b.entries[4 * e + 0];
+    const int q = b.entries[4 * e + 1];
+    const int row_tile = b.entries[4 * e + 2];
+    const int col_tile = b.entries[4 * e + 3];
+    mfma_rows_tile(*reinterpret_cast<const __attribute__((address_space(4))) ExpMfmaRowsParams *>(
+                       reinterpret_cast<uintptr_t>(b.jobs + job)),
+                   sm, q, row_tile, col_tile);
+}
+
 // bf16 hi / lo planes from the FP32 atoms x32 [K+1][bins][4], laid out
 // [4 components][kp / 32 steps][bins16][32 slots]: the B operand of one K
 // step for 16 bins is one contiguous kilobyte.
@@ -481,6 +783,27 @@ hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s) {
         grid = (unsigned)(8 * groups * p.n_row_tiles * p.n_col_tiles);
     }
     hipLaunchKernelGGL(exp_mfma_kernel, dim3(grid), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp_mfma_rows(const ExpMfmaRowsParams &p, hipStream_t s) {
+    if (p.n_blocks <= 0) return hipSuccess;
+    if (p.kp < p.kp_data + 32) return hipErrorInvalidValue;   // even-step padding reads up to kp_data + 32
+    unsigned grid;
+    if (p.n_col_tiles >= 8) {
+        const int cpx = (p.n_col_tiles + 7) / 8;
+        grid = (unsigned)(8 * p.n_blocks * p.n_row_tiles * cpx);
+    } else {
+        const int groups = (p.n_blocks + 7) / 8;
+        grid = (unsigned)(8 * groups * p.n_row_tiles * p.n_col_tiles);
+    }
+    hipLaunchKernelGGL(exp_mfma_rows_kernel, dim3(grid), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_batch(const MfmaBatchParams &p, hipStream_t s) {
+    if (p.n_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mfma_batch_kernel, dim3((unsigned)p.n_entries), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

@@ -245,6 +245,9 @@ enum { NK = TFSTAT_K_COUNT };
 constexpr int kMfmaTaus = 8;       // taus per matrix-core work item
 inline int32_t abc_pitch(int32_t n_tau) { return (n_tau + kMfmaTaus - 1) / kMfmaTaus * kMfmaTaus; }
 constexpr int kMfmaMinBand = 64;   // shorter bands stay on the VALU path
+// Exponential BF16X3 maps with fewer bins run the FP32 path: a matrix-core
+// column tile holds 16 bins, and with few bins the VALU sums cost less.
+constexpr int kMfmaMinBins = 4;
 // Tiling threshold of the exponential VALU sums (tfstat_tiling_config):
 // kRunsAuto sends a map to the runs form when its median 64-row tile spans
 // more slots than one LDS stage can stage in rounds of kExpMinStageRound.
@@ -282,6 +285,10 @@ struct Job {
     bool use_recur = false;    // RECUR64: exponential sums by the t0 recurrence
     int32_t recur_stride = 0, recur_k0 = 0, recur_bg = 1;
     bool use_mfma = false;     // BF16X3 on matrix cores for long bands
+    // matrix-core form: true = weights computed per row (exponential
+    // windows, any t0 grid); false = shifted weight tables (shape windows
+    // with rows on consecutive slots)
+    bool mfma_rows = false;
     int n_valu = 0, n_mfma = 0;  // block lists: order[0..n_valu) VALU, then MFMA
     std::vector<int32_t> lg;     // shifted bf16 table length per block (MFMA blocks)
     std::vector<int64_t> gsh_off;
@@ -361,13 +368,29 @@ void plan_job(Job &j) {
             j.recur_bg = at.n_bins >= 4 ? 4 : (at.n_bins >= 2 ? 2 : 1);
         }
     }
-    // Matrix-core path: BF16X3, rows on consecutive slots with one delta.
+    // Matrix-core path (BF16X3).  Exponential windows: any t0 grid, maps of
+    // at least kMfmaMinBins bins whose bf16 component planes stay under
+    // 2^31 bytes.  Shape windows: rows on consecutive slots with one delta.
+    // Either needs a block of 8 taus whose shortest band is long enough (the
+    // band grows with tau, so block b's shortest is that of its first tau).
     j.use_mfma = false;
-    if (is_exp && j.prec == TFSTAT_PREC_BF16X3 && j.rows[0].k0 >= 0) {
-        bool ok = true;
-        for (int m = 1; m < n_t0 && ok; ++m)
-            ok = j.rows[m].k0 == j.rows[0].k0 + m && j.rows[m].delta == j.rows[0].delta;
-        j.use_mfma = ok;
+    j.mfma_rows = false;
+    if (is_exp && j.prec == TFSTAT_PREC_BF16X3) {
+        bool ok;
+        if (is_shape) {
+            ok = j.rows[0].k0 >= 0;
+            for (int m = 1; m < n_t0 && ok; ++m)
+                ok = j.rows[m].k0 == j.rows[0].k0 + m && j.rows[m].delta == j.rows[0].delta;
+        } else {
+            const int64_t bins16 = (at.n_bins + 15) / 16 * 16;
+            const int64_t kp = ((int64_t)at.K + 31) / 32 * 32 + 32;
+            ok = at.n_bins >= kMfmaMinBins && bins16 * kp * 2 < ((int64_t)1 << 31);
+            j.mfma_rows = ok;
+        }
+        bool long_block = false;
+        for (int n = 0; n < n_tau && ok && !long_block; n += kMfmaTaus) long_block = j.lcol[n] >= kMfmaMinBand;
+        j.use_mfma = ok && long_block;
+        if (!j.use_mfma) j.mfma_rows = false;
     }
     if (is_exp && j.use_recur) {
         j.NB = 0;
@@ -457,6 +480,7 @@ void plan_job(Job &j) {
             j.order = lv;
             j.order.insert(j.order.end(), lm.begin(), lm.end());
             j.lg.assign(j.NB, 0);
+            if (j.mfma_rows) lm.clear();   // weights computed in the kernel: no tables
             j.gsh_off.assign(j.NB, 0);
             j.gsh_total = 0;
             j.gsh_max = 0;
@@ -708,12 +732,41 @@ tfs::ExpValuParams exp_params(Job &j) {
     p.twoF = j.twoF;
     p.part = ws_ptr<tfs::Partial>(j, j.off_part);
     p.abc_out = nullptr;
-    if (j.split) {
+    if (j.split || (j.use_mfma && j.n_mfma > 0)) {
+        // A, B, C of every cell from the A/B/C pass (F_a/F_b-only tiles)
         p.abc_out = ws_ptr<double>(j, j.off_abc);
         p.abc_pitch = abc_pitch((int32_t)j.win.tau.size());
     }
     p.scale_rows = j.win.type == TFSTAT_WIN_EXP ? 1 : 0;
     return p;
+}
+
+// Matrix-core parameters of a map planned for the per-row weight form;
+// blk_list: the device list of its matrix-core blocks.
+tfs::ExpMfmaRowsParams mfma_rows_params(Job &j, const int32_t *blk_list) {
+    const AtomsSet &at = *j.at;
+    tfs::ExpMfmaRowsParams q{};
+    q.n_bins = at.n_bins;
+    q.bins16 = at.bins16;
+    q.kp = at.kp;
+    q.kp_data = (at.K + 31) & ~31;
+    q.n_t0 = (int32_t)j.win.t0.size();
+    q.n_tau = (int32_t)j.win.tau.size();
+    q.n_row_tiles = j.n_row_tiles;
+    q.n_col_tiles = at.bins16 / 16;
+    q.n_blocks = j.n_mfma;
+    q.n_tiles = j.n_tiles;
+    q.t_sft = at.t_sft;
+    q.rows = ws_ptr<tfs::RowPlan>(j, j.off_rows);
+    q.tau = ws_ptr<int64_t>(j, j.off_tau);
+    q.blk_list = blk_list;
+    q.xhi = at.xhi;
+    q.xlo = at.xlo;
+    q.abc_cell = ws_ptr<double>(j, j.off_abc);
+    q.abc_pitch = abc_pitch(q.n_tau);
+    q.twoF = j.twoF;
+    q.part = ws_ptr<tfs::Partial>(j, j.off_part);
+    return q;
 }
 
 tfs::RectParams rect_params(Job &j) {
@@ -742,6 +795,58 @@ tfs::MergeParams merge_params(Job &j) {
     mp.part = ws_ptr<tfs::Partial>(j, j.off_part);
     mp.out = ws_ptr<tfs::BinResultDev>(j, j.off_res);
     return mp;
+}
+
+// The matrix-core form with shifted weight tables (shape windows whose rows
+// lie on consecutive slots): the tables, then the kernel, on stream s.
+void enqueue_mfma_tables(tfstat_ctx *ctx, Job &j, const tfs::WeightParams &wp, const tfs::ExpValuParams &pa,
+                     hipStream_t s) {
+    const AtomsSet &at = *j.at;
+    const int n_t0 = (int)j.win.t0.size();
+    const int n_tau = (int)j.win.tau.size();
+    tfs::ExpMfmaParams q{};
+    q.n_bins = at.n_bins;
+    q.bins16 = at.bins16;
+    q.kp = at.kp;
+    q.kp_data = (at.K + 31) & ~31;
+    q.n_t0 = n_t0;
+    q.n_tau = n_tau;
+    q.n_row_tiles = j.n_row_tiles;
+    q.n_col_tiles = at.bins16 / 16;
+    q.n_blocks = j.n_mfma;
+    q.n_tiles = j.n_tiles;
+    q.k0_first = j.rows[0].k0;
+    // the row scale exp(-delta / tau) of exponential windows; shape
+    // windows carry their offset in the tables
+    q.delta = j.win.type == TFSTAT_WIN_EXP ? j.rows[0].delta : 0;
+    q.tau = ws_ptr<int64_t>(j, j.off_tau);
+    q.lblk = wp.lblk;
+    q.blk_off = wp.blk_off;
+    q.blk_list = pa.blk_list;
+    q.lg = ws_ptr<int32_t>(j, j.off_lg);
+    q.gsh_off = ws_ptr<int64_t>(j, j.off_gshoff);
+    q.gsh = ws_ptr<unsigned short>(j, j.off_gsh);
+    tfs::ShiftTableParams sp{};
+    sp.n_blocks = j.n_mfma;
+    sp.blk_list = pa.blk_list;
+    sp.lblk = wp.lblk;
+    sp.lg = q.lg;
+    sp.blk_off = wp.blk_off;
+    sp.gsh_off = q.gsh_off;
+    sp.g32 = wp.g32;
+    sp.gsh = ws_ptr<unsigned short>(j, j.off_gsh);
+    record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, true);
+    hip_check(tfs::launch_shift_tables(sp, j.gsh_max, s), "shift tables kernel");
+    record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, false);
+    q.xhi = at.xhi;
+    q.xlo = at.xlo;
+    q.abc_cell = pa.abc_out;
+    q.abc_pitch = pa.abc_pitch;
+    q.twoF = j.twoF;
+    q.part = ws_ptr<tfs::Partial>(j, j.off_part);
+    record_kernel(ctx, j, TFSTAT_K_MFMA, s, true);
+    hip_check(tfs::launch_exp_mfma(q, s), "exp mfma kernel");
+    record_kernel(ctx, j, TFSTAT_K_MFMA, s, false);
 }
 
 // Enqueues every step of the map on stream s (tables upload, kernels,
@@ -834,49 +939,14 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
                 hip_check(tfs::launch_exp_fonly(pf, (at.n_bins + 3) / 4, s), "exp F kernel");
                 record_kernel(ctx, j, TFSTAT_K_EXP, s, false);
             }
-            tfs::ExpMfmaParams q{};
-            q.n_bins = at.n_bins;
-            q.bins16 = at.bins16;
-            q.kp = at.kp;
-            q.kp_data = (at.K + 31) & ~31;
-            q.n_t0 = n_t0;
-            q.n_tau = n_tau;
-            q.n_row_tiles = j.n_row_tiles;
-            q.n_col_tiles = at.bins16 / 16;
-            q.n_blocks = j.n_mfma;
-            q.n_tiles = j.n_tiles;
-            q.k0_first = j.rows[0].k0;
-            // the row scale exp(-delta / tau) of exponential windows; shape
-            // windows carry their offset in the tables
-            q.delta = j.win.type == TFSTAT_WIN_EXP ? j.rows[0].delta : 0;
-            q.tau = tau;
-            q.lblk = wp.lblk;
-            q.blk_off = wp.blk_off;
-            q.blk_list = pa.blk_list;
-            q.lg = ws_ptr<int32_t>(j, j.off_lg);
-            q.gsh_off = ws_ptr<int64_t>(j, j.off_gshoff);
-            q.gsh = ws_ptr<unsigned short>(j, j.off_gsh);
-            tfs::ShiftTableParams sp{};
-            sp.n_blocks = j.n_mfma;
-            sp.blk_list = pa.blk_list;
-            sp.lblk = wp.lblk;
-            sp.lg = q.lg;
-            sp.blk_off = wp.blk_off;
-            sp.gsh_off = q.gsh_off;
-            sp.g32 = wp.g32;
-            sp.gsh = ws_ptr<unsigned short>(j, j.off_gsh);
-            record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, true);
-            hip_check(tfs::launch_shift_tables(sp, j.gsh_max, s), "shift tables kernel");
-            record_kernel(ctx, j, TFSTAT_K_WEIGHTS, s, false);
-            q.xhi = at.xhi;
-            q.xlo = at.xlo;
-            q.abc_cell = pa.abc_out;
-            q.abc_pitch = pa.abc_pitch;
-            q.twoF = j.twoF;
-            q.part = part;
-            record_kernel(ctx, j, TFSTAT_K_MFMA, s, true);
-            hip_check(tfs::launch_exp_mfma(q, s), "exp mfma kernel");
-            record_kernel(ctx, j, TFSTAT_K_MFMA, s, false);
+            if (j.mfma_rows) {
+                tfs::ExpMfmaRowsParams q = mfma_rows_params(j, pa.blk_list);
+                record_kernel(ctx, j, TFSTAT_K_MFMA, s, true);
+                hip_check(tfs::launch_exp_mfma_rows(q, s), "exp mfma kernel");
+                record_kernel(ctx, j, TFSTAT_K_MFMA, s, false);
+            } else {
+                enqueue_mfma_tables(ctx, j, wp, pa, s);
+            }
         }
     } else {
         double *pabc = ws_ptr<double>(j, j.off_pabc);
@@ -990,13 +1060,15 @@ struct tfstat_batch {
     const tfs::ScanJob *scan_jobs = nullptr;
     int n_scan = 0;
     tfs::MergeBatchParams mbp{};
-    tfs::AbcBatchParams abp{};       // A/B/C pre-pass of the split-form maps
+    tfs::AbcBatchParams abp{};       // A/B/C pre-pass of the split-form and matrix-core maps
+    tfs::MfmaBatchParams mfp{};      // matrix-core work of the BF16X3 maps
     tfs::BinResultDev *res_dev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;    // around each graph launch
-    hipEvent_t evf0 = nullptr, evf1 = nullptr;  // recorded in the graph around the fused launch
-    double tune_ms = 0.0, last_ms = 0.0, last_fused_ms = 0.0;
+    hipEvent_t evf0 = nullptr, evf1 = nullptr;  // around the fused launch (timed runs)
+    hipEvent_t evm1 = nullptr;                  // after the matrix-core launch (timed runs)
+    double tune_ms = 0.0, last_ms = 0.0, last_fused_ms = 0.0, last_mfma_ms = 0.0;
     bool holds_atoms = false;
 };
 
@@ -1019,7 +1091,7 @@ void batch_drop_graph(tfstat_batch *b) {
 
 void batch_release(tfstat_ctx *ctx, tfstat_batch *b) {
     batch_drop_graph(b);
-    for (hipEvent_t *e : {&b->ev0, &b->ev1, &b->evf0, &b->evf1}) {
+    for (hipEvent_t *e : {&b->ev0, &b->ev1, &b->evf0, &b->evf1, &b->evm1}) {
         if (*e) ctx->events.put(*e);
         *e = nullptr;
     }
@@ -1048,18 +1120,27 @@ int job_shape(const Job &j) {
 // ctx->mu.
 bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bool have_lock) {
     const int32_t n = (int32_t)b->jobs.size();
-    std::vector<int> shape(n, -1), eidx(n, -1), ridx(n, -1);
-    int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0, n_abc = 0;
+    std::vector<int> shape(n, -1), eidx(n, -1), ridx(n, -1), midx(n, -1);
+    int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0, n_abc = 0, n_mfma_maps = 0;
+    size_t n_mfma_entries = 0;
     int32_t max_chunks = 1;
     b->res_off.assign(n, 0);
     b->n_results = 0;
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
         if (banded(j.win.type)) {
+            if (j.use_mfma && !j.mfma_rows)
+                raise(TFSTAT_E_INVAL, "a batch runs no matrix-core shape windows (use tfstat_fmap)");
             shape[i] = job_shape(j);
             eidx[i] = n_exp++;
             n_went += j.NB;
             if (j.split) n_abc += j.n_valu * j.n_row_tiles;
+            if (j.use_mfma) {
+                // A/B/C of every block; matrix-core work of the long-band blocks
+                n_abc += (j.n_valu + j.n_mfma) * j.n_row_tiles;
+                midx[i] = n_mfma_maps++;
+                n_mfma_entries += (size_t)j.n_mfma * j.n_row_tiles * (j.at->bins16 / 16);
+            }
             max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
         } else {
             ridx[i] = n_rect++;
@@ -1081,30 +1162,34 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
         if (eidx[i] >= 0) {
-            // split maps: F_a/F_b-only tiles of bin pairs
-            const int bgs = j.split ? (j.at->n_bins + 1) / 2 : j.n_groups + (j.tail2 ? 1 : 0);
+            // split maps, and the VALU blocks of matrix-core maps:
+            // F_a/F_b-only tiles of bin pairs
+            const bool fonly = j.split || j.use_mfma;
+            const int bgs = fonly ? (j.at->n_bins + 1) / 2 : j.n_groups + (j.tail2 ? 1 : 0);
             const size_t per = (size_t)j.n_row_tiles * bgs;
             // a runs tile takes four blocks, each over its whole band on one
             // wave: about four times the time of one block's tile
             const int step = j.runs ? 4 : 1;
-            const int per_step = j.split ? 4 * 2 : 3 + 4 * j.BG;   // FMAs per lane, slot and tau
+            const int per_step = fonly ? 4 * 2 : 3 + 4 * j.BG;   // FMAs per lane, slot and tau
             for (int q = 0; q < j.n_valu; q += step)
                 groups_e.push_back({i, q, (double)(j.lblk[j.order[q]] + 1) * j.R * per_step * step});
             n_tiles_total += per * ((j.n_valu + step - 1) / step);
         } else {
             const int ny = ((int)j.win.t0.size() + tfs::kRectRows - 1) / tfs::kRectRows;
-            n_tiles_total += (size_t)ny * j.n_tiles_n * j.at->n_bins;
+            n_tiles_total += (size_t)ny * j.n_tiles_n * ((j.at->n_bins + tfs::kRectBins - 1) / tfs::kRectBins);
         }
     }
-    if (n_tiles_total > (size_t)INT32_MAX / 2) raise(TFSTAT_E_INVAL, "batch has too many tiles");
+    if (n_tiles_total > (size_t)INT32_MAX / 2 || n_mfma_entries > (size_t)INT32_MAX / 2)
+        raise(TFSTAT_E_INVAL, "batch has too many tiles");
     std::stable_sort(groups_e.begin(), groups_e.end(),
                      [](const Group &a, const Group &c) { return a.cost > c.cost; });
     std::vector<tfs::BatchTile> tiles;
     tiles.reserve(n_tiles_total);
     for (const Group &g : groups_e) {
         const Job &j = *b->jobs[g.map];
-        const int kind = j.runs ? 2 : (j.split ? 3 : 0);
-        const int ng = j.split ? (j.at->n_bins + 1) / 2 : j.n_groups;
+        const bool fonly = j.split || j.use_mfma;
+        const int kind = j.runs ? 2 : (fonly ? 3 : 0);
+        const int ng = fonly ? (j.at->n_bins + 1) / 2 : j.n_groups;
         for (int rt = 0; rt < j.n_row_tiles; ++rt) {
             for (int gidx = 0; gidx < ng; ++gidx)
                 tiles.push_back(tfs::BatchTile{kind, eidx[g.map], g.q, rt, gidx, shape[g.map]});
@@ -1123,8 +1208,8 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
         const int ny = ((int)j.win.t0.size() + tfs::kRectRows - 1) / tfs::kRectRows;
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < j.n_tiles_n; ++x)
-                for (int bin = 0; bin < j.at->n_bins; ++bin)
-                    tiles.push_back(tfs::BatchTile{1, ridx[i], x, y, bin, 0});
+                for (int bg = 0; bg < (j.at->n_bins + tfs::kRectBins - 1) / tfs::kRectBins; ++bg)
+                    tiles.push_back(tfs::BatchTile{1, ridx[i], x, y, bg, 0});
     }
     b->n_tiles = (int)tiles.size();
 
@@ -1151,6 +1236,8 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     const size_t off_ajob = take(sizeof(int32_t) * n_abc);
     const size_t off_ax = take(sizeof(int32_t) * n_abc);
     const size_t off_ay = take(sizeof(int32_t) * n_abc);
+    const size_t off_mfp = take(sizeof(tfs::ExpMfmaRowsParams) * n_mfma_maps);
+    const size_t off_ment = take(sizeof(int32_t) * 4 * n_mfma_entries);
     const size_t desc_end = o;
     const size_t off_counter = take(sizeof(int32_t));
     const size_t off_res = take(sizeof(tfs::BinResultDev) * b->n_results);
@@ -1188,7 +1275,10 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     auto *ajob = reinterpret_cast<int32_t *>(hptr(off_ajob));
     auto *ax = reinterpret_cast<int32_t *>(hptr(off_ax));
     auto *ay = reinterpret_cast<int32_t *>(hptr(off_ay));
+    auto *mfp = reinterpret_cast<tfs::ExpMfmaRowsParams *>(hptr(off_mfp));
+    auto *ment = reinterpret_cast<int32_t *>(hptr(off_ment));
     int we = 0, se = 0, me = 0, ae = 0;
+    size_t mfe = 0;
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
         if (eidx[i] >= 0) {
@@ -1199,15 +1289,30 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
                 wblk[we] = nb;
                 ++we;
             }
-            if (j.split) {
-                // longest bands first, as in the tile list
-                for (int q = 0; q < j.n_valu; ++q)
+            if (j.split || j.use_mfma) {
+                // longest bands first, as in the tile list (matrix-core maps:
+                // every block, the matrix-core ones included)
+                for (int q = 0; q < j.n_valu + j.n_mfma; ++q)
                     for (int rt = 0; rt < j.n_row_tiles; ++rt) {
                         ajob[ae] = eidx[i];
                         ax[ae] = q;
                         ay[ae] = rt;
                         ++ae;
                     }
+            }
+            if (j.use_mfma) {
+                const int32_t *blk = reinterpret_cast<const int32_t *>(ws_ptr<char>(j, j.off_order)) + j.n_valu;
+                mfp[midx[i]] = mfma_rows_params(j, blk);
+                const int n_ct = j.at->bins16 / 16;
+                for (int q = 0; q < j.n_mfma; ++q)
+                    for (int rt = 0; rt < j.n_row_tiles; ++rt)
+                        for (int ct = 0; ct < n_ct; ++ct) {
+                            ment[4 * mfe + 0] = midx[i];
+                            ment[4 * mfe + 1] = q;
+                            ment[4 * mfe + 2] = rt;
+                            ment[4 * mfe + 3] = ct;
+                            ++mfe;
+                        }
             }
         } else {
             rp[ridx[i]] = rect_params(j);
@@ -1245,6 +1350,9 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     b->abp.x = reinterpret_cast<const int32_t *>(dptr(off_ax));
     b->abp.y = reinterpret_cast<const int32_t *>(dptr(off_ay));
     b->abp.n_entries = n_abc;
+    b->mfp.jobs = reinterpret_cast<const tfs::ExpMfmaRowsParams *>(dptr(off_mfp));
+    b->mfp.entries = reinterpret_cast<const int32_t *>(dptr(off_ment));
+    b->mfp.n_entries = (int32_t)mfe;
     b->mbp.jobs = reinterpret_cast<const tfs::MergeParams *>(dptr(off_mp));
     b->mbp.job = reinterpret_cast<const int32_t *>(dptr(off_mjob));
     b->mbp.map = reinterpret_cast<const int32_t *>(dptr(off_mmap));
@@ -1259,7 +1367,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     }
     hip_check(hipMemcpyAsync(ws + desc_begin, hd, desc_bytes, hipMemcpyHostToDevice, s), "upload descriptors");
     if (sync) hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    for (hipEvent_t *e : {&b->ev0, &b->ev1, &b->evf0, &b->evf1})
+    for (hipEvent_t *e : {&b->ev0, &b->ev1, &b->evf0, &b->evf1, &b->evm1})
         if (!*e) *e = ctx->events.get();
     return true;
 }
@@ -1280,6 +1388,8 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
             b->jobs.push_back(j.get());
         }
         b->holds_atoms = true;
+        if (prec == TFSTAT_PREC_BF16X3)
+            for (auto &j : b->owned) ensure_planes(ctx, j->at);
     }
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
@@ -1314,6 +1424,8 @@ hipError_t batch_enqueue(tfstat_batch *b, hipStream_t s, bool timed) {
     if (e == hipSuccess && timed) e = hipEventRecord(b->evf0, s);
     if (e == hipSuccess) e = tfs::launch_fused(b->fp, b->variant, b->groups, s);
     if (e == hipSuccess && timed) e = hipEventRecord(b->evf1, s);
+    if (e == hipSuccess) e = tfs::launch_mfma_batch(b->mfp, s);
+    if (e == hipSuccess && timed) e = hipEventRecord(b->evm1, s);
     if (e == hipSuccess) e = tfs::launch_merge_batch(b->mbp, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->pin, b->res_dev, sizeof(tfs::BinResultDev) * b->n_results,
@@ -1345,11 +1457,13 @@ void batch_run_timed(tfstat_ctx *ctx, tfstat_batch *b) {
     hip_check(batch_enqueue(b, s, true), "batch launch");
     hip_check(hipEventRecord(b->ev1, s), "hipEventRecord");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    float ms = 0.f, fms = 0.f;
+    float ms = 0.f, fms = 0.f, mms = 0.f;
     hip_check(hipEventElapsedTime(&ms, b->ev0, b->ev1), "hipEventElapsedTime");
     hip_check(hipEventElapsedTime(&fms, b->evf0, b->evf1), "hipEventElapsedTime");
+    hip_check(hipEventElapsedTime(&mms, b->evf1, b->evm1), "hipEventElapsedTime");
     b->last_ms = ms;
     b->last_fused_ms = fms;
+    b->last_mfma_ms = b->mfp.n_entries > 0 ? mms : 0.0;
 }
 
 void batch_launch(tfstat_ctx *ctx, tfstat_batch *b) {
@@ -1405,13 +1519,17 @@ double est_work(const Job &j) {
     const double cells_bins = (double)j.win.t0.size() * (double)j.at->n_bins;
     if (!banded(j.win.type)) return cells_bins * (double)j.win.tau.size();
     double band = 0.0;   // sum over taus of the band length, from the block tables
-    for (int b = 0; b < j.NB; ++b) band += (double)j.lblk[b] * j.R;
+    for (int q = 0; q < j.NB; ++q) {
+        // matrix-core blocks: about a quarter of the VALU time per term
+        const double w = q >= j.n_valu ? 0.25 : 1.0;
+        band += w * (double)j.lblk[j.order[q]] * j.R;
+    }
     return cells_bins * band;
 }
 
 bool fusable(const Job &j) {
-    return (j.prec == TFSTAT_PREC_FP32 || j.prec == TFSTAT_PREC_FP64) && !j.use_mfma && !j.use_recur &&
-           est_work(j) <= kServeFuseMaxWork;
+    return (j.prec == TFSTAT_PREC_FP32 || j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_BF16X3) &&
+           !(j.use_mfma && !j.mfma_rows) && !j.use_recur && est_work(j) <= kServeFuseMaxWork;
 }
 
 void worker_loop(tfstat_ctx *ctx) {
@@ -1812,8 +1930,10 @@ int tfstat_logB(tfstat_ctx *ctx, const float *twoF_dev, int32_t n_maps, int32_t 
     return guarded([&] {
         if (!ctx || !twoF_dev || !logB_host) raise(TFSTAT_E_INVAL, "null argument");
         if (n_maps < 1 || n_t0 < 1 || n_tau < 1) raise(TFSTAT_E_INVAL, "sizes must be >= 1");
+        if (n_maps > 65535) raise(TFSTAT_E_INVAL, "n_maps must be <= 65535");
         const int64_t cells = (int64_t)n_t0 * n_tau;
         const int64_t cpt = 16384;
+        if ((cells + cpt - 1) / cpt > 65535) raise(TFSTAT_E_INVAL, "maps of more than 2^30 cells");
         const int32_t n_tiles = (int32_t)((cells + cpt - 1) / cpt);
         const size_t part_b = round_up(sizeof(tfs::Partial) * (size_t)n_tiles * n_maps, 256);
         const size_t res_b = sizeof(tfs::BinResultDev) * n_maps;
@@ -1947,12 +2067,14 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
     return guarded([&] {
         if (!ctx || !ids || !wins || !out) raise(TFSTAT_E_INVAL, "null argument");
         if (n_maps < 1) raise(TFSTAT_E_INVAL, "n_maps must be >= 1");
-        if (precision != TFSTAT_PREC_FP32 && precision != TFSTAT_PREC_FP64)
-            raise(TFSTAT_E_INVAL, "a batch runs in FP32 or FP64");
+        if (precision != TFSTAT_PREC_FP32 && precision != TFSTAT_PREC_FP64 && precision != TFSTAT_PREC_BF16X3)
+            raise(TFSTAT_E_INVAL, "a batch runs in FP32, FP64 or BF16X3");
         if (tune > 1 || tune < -2 * (tfs::kShapeMixed + 1))
             raise(TFSTAT_E_INVAL, "tune must be 0, 1 or -1 - variant");
         ensure_batch_stream(ctx);
         const std::string sig = batch_signature(ctx, n_maps, ids, wins, precision);
+        // Builds a caller may force (tune = -1 - v): every tile shape of the
+        // precision, at the stand-alone waves per SIMD and one fewer.
         std::vector<int> variants;
         for (int m = 0; m < 2; ++m) {
             const int base = m * (tfs::kShapeMixed + 1);
@@ -1963,6 +2085,12 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
                     variants.push_back(base + sh);
             }
         }
+        // Builds the autotuner may keep: only those that give every map its
+        // own tile shape (the one tfstat_fmap plans), at either occupancy.
+        // Their arithmetic per cell is the stand-alone kernel's, so a map's
+        // results never depend on which other maps share its batch.
+        const int own = precision == TFSTAT_PREC_FP64 ? tfs::kShapeD41 : tfs::kShapeMixed;
+        const std::vector<int> tunable = {own, own + tfs::kShapeMixed + 1};
         double tune_ms = 0.0;
         int variant = precision == TFSTAT_PREC_FP64 ? tfs::kShapeD41 : tfs::kShapeMixed;
         int per_cu = 0;
@@ -1985,11 +2113,12 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
             }
         }
         if (tune == 1 && !found) {
-            // Autotuner: every tile shape x every persistent width that fits;
-            // the fastest of three graph replays after one warm-up counts.
+            // Autotuner: each build that keeps the maps' own tile shapes x
+            // every persistent width that fits; the fastest of three graph
+            // replays after one warm-up counts.
             const auto t_start = std::chrono::steady_clock::now();
             double best = 1e300;
-            for (int v : variants) {
+            for (int v : tunable) {
                 const int occ = tfs::fused_groups_per_cu(v);
                 if (occ < 1) continue;
                 tfstat_batch cand;
@@ -2069,6 +2198,7 @@ int tfstat_batch_stats_read(const tfstat_batch *b, tfstat_batch_stats *out) {
         out->tune_ms = b->tune_ms;
         out->last_ms = b->last_ms;
         out->last_fused_ms = b->last_fused_ms;
+        out->last_mfma_ms = b->last_mfma_ms;
         return (int)TFSTAT_OK;
     });
 }

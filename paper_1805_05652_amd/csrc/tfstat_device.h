@@ -106,6 +106,40 @@ struct ExpMfmaParams {
     Partial *part;
 };
 
+// Exponential-window F_a, F_b on bf16 matrix cores for any t0 grid.  Each
+// wave computes the window weights exp(-(t_k - t0_m) / tau) of its own 16
+// rows in registers, so rows may start at any slot k0_m with any offset
+// delta_m (the row scale and each row's exact band end are in the weights).
+struct ExpMfmaRowsParams {
+    int32_t n_bins, bins16;   // bins, rounded up to 16
+    int32_t kp;               // plane pitch (slots), multiple of 32
+    int32_t kp_data;          // round_up(K, 32): slots that may hold data
+    int32_t n_t0, n_tau;
+    int32_t n_row_tiles;      // ceil(n_t0 / 64)
+    int32_t n_col_tiles;      // bins16 / 16
+    int32_t n_blocks;         // blocks in blk_list
+    int32_t n_tiles;          // partial slots per bin
+    int64_t t_sft;
+    const RowPlan *rows;      // [n_t0]
+    const int64_t *tau;       // [n_tau]
+    const int32_t *blk_list;  // [n_blocks] blocks of 8 taus
+    const unsigned short *xhi, *xlo;  // bf16 planes [4][kp / 32][bins16][32]
+    const double *abc_cell;   // [n_t0][abc_pitch][3] (scaled, exact band)
+    int32_t abc_pitch;        // n_tau rounded up to 8
+    int32_t pad;
+    float *twoF;
+    Partial *part;
+};
+
+// Matrix-core work of many maps in one launch: entry e is {map, position in
+// the map's blk_list, 64-row tile, 16-bin column tile}.
+struct MfmaBatchParams {
+    const ExpMfmaRowsParams *jobs;
+    const int32_t *entries;   // [n_entries][4]
+    int32_t n_entries;
+    int32_t pad;
+};
+
 struct ShiftTableParams {
     int32_t n_blocks;
     int32_t pad0;
@@ -166,7 +200,7 @@ struct RectParams {
     const RowPlan *rows;
     const int64_t *tau;
     const double *pabc;       // [K+1][8] exclusive prefix: 4 hi then 4 lo terms
-    const double *px;         // [K+1][2][n_bins*4]: hi terms then lo terms
+    const double *px;         // [n_bins][K+1][8]: per bin, 4 hi then 4 lo terms
     float *twoF;
     Partial *part;
 };
@@ -203,7 +237,8 @@ inline void shape_dims(int shape, int *prec, int *R, int *BG) {
     *BG = t[shape][2];
 }
 
-constexpr int kRectRows = 64;   // rows per rect tile (x 64 taus of one bin)
+constexpr int kRectRows = 64;   // rows per rect tile (x 64 taus x kRectBins bins)
+constexpr int kRectBins = 4;    // bins per rect tile
 
 struct BatchTile {
     int32_t kind;    // 0: exponential, 1: rectangular, 2: exponential, rows far apart,
@@ -212,7 +247,7 @@ struct BatchTile {
     int32_t job;     // index into FusedParams::exp_jobs or ::rect_jobs
     int32_t x;       // exp: position in blk_list (kind 2: first of four); rect: tau tile (64 taus)
     int32_t y;       // exp: 64-row tile; rect: kRectRows-row tile
-    int32_t z;       // exp: bin group; rect: bin
+    int32_t z;       // exp: bin group; rect: group of kRectBins bins
     int32_t shape;   // exp: ExpShape of the job (a four-bin map's tail: kShapeF42, kShapeF41)
 };
 
@@ -296,6 +331,8 @@ hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, int 
 hipError_t launch_exp_fonly(const ExpValuParams &p, int n_groups, hipStream_t s);
 hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s);
 hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s);
+hipError_t launch_exp_mfma_rows(const ExpMfmaRowsParams &p, hipStream_t s);
+hipError_t launch_mfma_batch(const MfmaBatchParams &p, hipStream_t s);
 hipError_t launch_exp_recur(const RecurParams &p, int BG, hipStream_t s);
 hipError_t launch_shift_tables(const ShiftTableParams &p, int64_t max_entries, hipStream_t s);
 // Entries per shifted table (one tau, part and shift) for a band of lblk.

@@ -1,0 +1,81 @@
+"""Comparison helpers of the GPU parity tests (HIP path against the FP64
+CPU oracle).
+
+Tolerances (floating point):
+  * 2F: |2F_gpu - 2F_oracle| <= tol * max(2F_oracle, 1), tol = 1e-4 for FP32
+    and bf16x3 sums, 1e-9 for FP64 sums; stored maps are float32, so map
+    comparisons also allow their rounding (2^-23 relative);
+  * logB: absolute 1e-3;
+  * argmax: exact, or a near-tie: 2F_oracle at the GPU's argmax is at least
+    (1 - 1e-4) * max 2F_oracle;
+  * degenerate cells (2F = 0 in the oracle) are exactly 0 on the GPU.
+"""
+import numpy as np
+
+import oracle
+
+F32_MAP = 2.0 ** -23
+TOL = {"fp32": 1e-4, "fp64": 1e-9, "bf16x3": 1e-4, "recur64": 1e-8}
+LOGB_TOL = 1e-3
+NEAR_TIE = 1e-4
+
+
+def check_map(got, ref, tol):
+    """Every cell of got (GPU, float32 map) against ref (oracle, float64)."""
+    got = np.asarray(got, dtype=np.float64)
+    assert got.shape == ref.shape
+    zero = ref == 0.0
+    assert np.all(got[zero] == 0.0), "degenerate cells differ"
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    bound = tol + F32_MAP
+    worst = np.unravel_index(np.argmax(err), err.shape)
+    assert err.max() <= bound, ("max rel err %.3e at %s: gpu %r oracle %r"
+                                % (err.max(), worst, got[worst], ref[worst]))
+    return float(err.max())
+
+
+def check_results(res, ref_map, win, tol):
+    """Per-bin results (max 2F, argmax, logB) against the oracle's reduction
+    of its full map."""
+    mx, am, lb = oracle.reduce(ref_map)
+    assert len(res) == ref_map.shape[0]
+    for b, r in enumerate(res):
+        assert abs(r["logB"] - lb[b]) <= LOGB_TOL, (b, r["logB"], lb[b])
+        assert abs(r["max2F"] - mx[b]) <= tol * max(mx[b], 1.0), (b, r["max2F"], mx[b])
+        flat = ref_map[b].ravel()
+        idx = r["m"] * win.n_tau + r["n"]
+        assert idx == am[b] or flat[idx] >= (1 - NEAR_TIE) * mx[b], (b, idx, am[b])
+        assert r["t0"] == win.t0[r["m"]] and r["tau"] == win.tau[r["n"]]
+
+
+def sample_cells(rng, win, n):
+    """n random cells plus the four corners and the centre."""
+    m = rng.integers(0, win.n_t0, size=n)
+    k = rng.integers(0, win.n_tau, size=n)
+    m = np.concatenate([m, [0, 0, win.n_t0 - 1, win.n_t0 - 1, win.n_t0 // 2]])
+    k = np.concatenate([k, [0, win.n_tau - 1, 0, win.n_tau - 1, win.n_tau // 2]])
+    return m.astype(np.int32), k.astype(np.int32)
+
+
+def check_sampled(twoF_dev, res, atoms, win, tol, rng, n=200):
+    """Maps too large for the full oracle: the GPU map at sampled cells and
+    at every bin's GPU argmax cell against oracle.cells; the GPU max 2F is
+    the oracle's value at the GPU argmax (within tol), and no sampled cell's
+    oracle value exceeds the GPU max 2F by more than tol.  Returns the
+    largest relative error."""
+    import torch
+    mi, ni = sample_cells(rng, win, n)
+    am = np.array([r["m"] for r in res], dtype=np.int32)
+    an = np.array([r["n"] for r in res], dtype=np.int32)
+    mi = np.concatenate([mi, am])
+    ni = np.concatenate([ni, an])
+    ref = oracle.cells_atoms(atoms, win, mi, ni)
+    dev = twoF_dev[:, torch.from_numpy(mi.astype(np.int64)).to(twoF_dev.device),
+                   torch.from_numpy(ni.astype(np.int64)).to(twoF_dev.device)]
+    err = check_map(dev.cpu().numpy(), ref, tol)
+    n_rand = mi.shape[0] - am.shape[0]
+    for b, r in enumerate(res):
+        at = ref[b, n_rand + b]
+        assert abs(r["max2F"] - at) <= tol * max(at, 1.0), (b, r["max2F"], at)
+        assert ref[b, :].max() <= r["max2F"] + tol * max(r["max2F"], 1.0), (b, ref[b].max(), r["max2F"])
+    return err

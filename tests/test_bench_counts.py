@@ -90,8 +90,9 @@ def test_work_counts_brute_force():
 
 def test_mfma_cells_blocks():
     """The matrix-core share counts exactly the tau blocks of 8 whose
-    shortest band (ceil(3 tau / T_sft) slots) is at least 64."""
-    atoms = _gapless(600, n_bins=3)
+    shortest band (ceil(3 tau / T_sft) slots for rows on slot starts) is at
+    least 64, for maps of at least 4 bins; fewer bins run on the VALU."""
+    atoms = _gapless(600, n_bins=5)
     tau = np.concatenate([np.full(8, 30 * T), np.full(8, 21 * T), [21 * T + 1] * 7 + [10 * T],
                           np.full(3, 40 * T)]).astype(np.int64)
     win = tfsynth.list_window("exp", np.arange(20, dtype=np.int64) * T, tau)
@@ -100,3 +101,22 @@ def test_mfma_cells_blocks():
     want = bench.work_counts(atoms, tfsynth.list_window("exp", win.t0, tau[keep]))[0]
     assert bench.mfma_cells(atoms, win) == want
     assert 0 < want < bench.work_counts(atoms, win)[0]
+    assert bench.mfma_cells(_gapless(600, n_bins=3), win) == 0
+    assert bench.mfma_cells(atoms, tfsynth.list_window("rect", win.t0, tau)) == 0
+
+
+def test_mfma_taus_offsets_and_data_end():
+    """Rows off the slot grid shorten the band by the largest offset: with
+    3 tau = 64 T - 600 s, a row on a slot start holds 64 slot starts in
+    [t0, t0 + 3 tau), a row 1799 s before a slot start only 63.  Bands are
+    capped at the data end seen from the earliest row."""
+    atoms = _gapless(600, n_bins=4)
+    tau = np.full(8, (64 * T - 600) // 3, dtype=np.int64)
+    assert 3 * tau[0] == 64 * T - 600
+    assert bench.mfma_taus(atoms, tfsynth.list_window("exp", np.array([0, T]), tau)).all()
+    assert not bench.mfma_taus(atoms, tfsynth.list_window("exp", np.array([0, T + 1]), tau)).any()
+    # rows near the data end: 600 - 540 = 60 slots left
+    assert not bench.mfma_taus(atoms, tfsynth.list_window("exp", np.array([540 * T, 550 * T]),
+                                                          np.full(8, 100 * T))).any()
+    assert bench.mfma_taus(atoms, tfsynth.list_window("exp", np.array([530 * T, 550 * T]),
+                                                      np.full(8, 100 * T))).all()

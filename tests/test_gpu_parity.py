@@ -18,9 +18,9 @@ import tfsynth
 
 pytestmark = pytest.mark.gpu
 
+from checks import TOL, check_map, check_results
+
 T = tfsynth.T_SFT
-F32_MAP = 2.0 ** -23
-TOL = {"fp32": 1e-4, "fp64": 1e-9, "bf16x3": 1e-4, "recur64": 1e-8}
 
 
 @pytest.fixture(scope="module")
@@ -50,30 +50,6 @@ class tiling:
 
     def __exit__(self, *exc):
         self.ctx.tiling_config(-1, -1)
-
-
-def check_map(got, ref, tol):
-    got = np.asarray(got, dtype=np.float64)
-    assert got.shape == ref.shape
-    zero = ref == 0.0
-    assert np.all(got[zero] == 0.0), "degenerate cells differ"
-    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
-    bound = tol + F32_MAP
-    worst = np.unravel_index(np.argmax(err), err.shape)
-    assert err.max() <= bound, ("max rel err %.3e at %s: gpu %r oracle %r"
-                                % (err.max(), worst, got[worst], ref[worst]))
-    return float(err.max())
-
-
-def check_results(res, ref_map, win, tol):
-    mx, am, lb = oracle.reduce(ref_map)
-    for b, r in enumerate(res):
-        assert abs(r["logB"] - lb[b]) <= 1e-3, (b, r["logB"], lb[b])
-        assert abs(r["max2F"] - mx[b]) <= tol * max(mx[b], 1.0), (b, r["max2F"], mx[b])
-        flat = ref_map[b].ravel()
-        idx = r["m"] * win.n_tau + r["n"]
-        assert idx == am[b] or flat[idx] >= (1 - 1e-4) * mx[b], (b, idx, am[b])
-        assert r["t0"] == win.t0[r["m"]] and r["tau"] == win.tau[r["n"]]
 
 
 def run_and_check(ctx, atoms, win, prec):
@@ -349,15 +325,6 @@ def test_loud_injection_argmax(ctx):
 # Full-size workloads, in the launch configuration the benchmark times
 # ---------------------------------------------------------------------------
 
-def _sample_cells(rng, win, n):
-    m = rng.integers(0, win.n_t0, size=n)
-    k = rng.integers(0, win.n_tau, size=n)
-    # corners and edges
-    m = np.concatenate([m, [0, 0, win.n_t0 - 1, win.n_t0 - 1, win.n_t0 // 2]])
-    k = np.concatenate([k, [0, win.n_tau - 1, 0, win.n_tau - 1, win.n_tau // 2]])
-    return m.astype(np.int32), k.astype(np.int32)
-
-
 def test_full_exp_1bin_fp32(ctx):
     """5000 slots, 1000 x 1000 grid, tau to 30 days: every cell against the
     oracle's full map, and the per-bin results."""
@@ -376,30 +343,30 @@ def test_full_exp_1bin_fp32(ctx):
     print("full exp 1 bin: max rel err %.3e" % err, flush=True)
 
 
-def test_full_exp_256_bins_sampled(ctx):
-    """256 bins sharing antenna atoms, 2000 slots, 500 x 500 grid: sampled
-    cells of every bin against the oracle."""
-    _case("full exp 256 bins fp32 sampled")
+@pytest.fixture(scope="module")
+def exp256_oracle():
+    """The 256-bin exponential workload and its full FP64 oracle map (every
+    cell of every bin: 4.3e10 cells*SFTs*bins, computed once per module)."""
     atoms, win = tfsynth.workload_exp_bins()
+    ref = oracle.fmap_atoms(atoms, win)
+    return atoms, win, ref
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_full_exp_256_bins_every_cell(ctx, exp256_oracle, prec):
+    """256 bins sharing antenna atoms, 2000 slots, 500 x 500 grid: every cell
+    of every bin against the oracle's full map at the 2F tolerance, and the
+    per-bin max 2F, argmax and logB against the oracle's reduction."""
+    _case("full exp 256 bins every cell " + prec)
+    atoms, win, ref = exp256_oracle
     aid = ctx.upload_atoms(atoms)
     try:
-        res, twoF = ctx.fmap(aid, win, "fp32", want_map=True)
+        res, twoF = ctx.fmap(aid, win, prec, want_map=True)
     finally:
         ctx.free(aid)
-    got = twoF.cpu().numpy()
-    rng = np.random.default_rng(17)
-    mi, ni = _sample_cells(rng, win, 400)
-    ref = oracle.cells("exp", atoms.timestamps, atoms.a2, atoms.b2, atoms.ab, atoms.fa, atoms.fb,
-                       win.t0, win.tau, mi, ni)
-    sel = got[:, mi, ni]
-    check_map(sel, ref, 1e-4)
-    # results agree with the GPU's own map (reductions at full size)
-    mx = got.reshape(got.shape[0], -1).max(axis=1)
-    for b in range(atoms.n_bins):
-        assert abs(res[b]["max2F"] - mx[b]) <= 1e-6 * max(mx[b], 1.0)
-        F = got[b].astype(np.float64).ravel() / 2
-        lb = F.max() + np.log(np.exp(F - F.max()).sum()) - np.log(F.size)
-        assert abs(res[b]["logB"] - lb) <= 1e-4
+    err = check_map(twoF.cpu().numpy(), ref, TOL[prec])
+    check_results(res, ref, win, TOL[prec])
+    print("full exp 256 bins %s: max rel err %.3e over %d cells" % (prec, err, ref.size), flush=True)
 
 
 @pytest.mark.parametrize("case", ["offset", "tail", "sparse_rows"])
@@ -420,31 +387,53 @@ def test_bf16x3_ragged(ctx, case):
     print("bf16x3 %s: max rel err %.3e" % (case, err), flush=True)
 
 
-def test_full_exp_256_bins_bf16x3(ctx):
-    """256 bins on matrix cores against the oracle on sampled cells, and
-    against the FP32 VALU form on the whole map."""
-    _case("full exp 256 bins bf16x3")
-    atoms, win = tfsynth.workload_exp_bins()
+def _kernel_launches(ctx, fn):
+    ctx.profile_reset()
+    ctx.profile(True)
+    try:
+        out = fn()
+    finally:
+        ctx.profile(False)
+    return out, ctx.profile_read()
+
+
+@pytest.mark.parametrize("case", ["linspace", "stride7", "before_after", "bins5", "bins37", "bins3_valu",
+                                  "one_row_tile", "long_and_short"])
+def test_bf16x3_any_grid(ctx, case):
+    """Matrix cores for exponential windows on any t0 grid (weights computed
+    per row): linspace rows with their own offsets, rows 7 slots apart, rows
+    before and after the data, ragged bin counts (partial 16-bin column
+    tiles), a map of fewer than 4 bins (FP32 path), a single partial row
+    tile, and tau blocks with short bands (FP32 F-only tiles) beside long
+    ones.  Every cell and the per-bin results against the oracle."""
+    _case("bf16x3 any grid " + case)
+    n_bins = {"bins5": 5, "bins37": 37, "bins3_valu": 3}.get(case, 24)
+    atoms = tfsynth.make_atoms(811, 1400, 0.12, n_bins=n_bins,
+                               injections=[tfsynth.Injection(min(4, n_bins - 1), "exp", 300 * T, 60 * T, 1.0)])
+    if case in ("linspace", "bins5", "bins37", "bins3_valu"):
+        win = tfsynth.linspace_grid(atoms, "exp", 260, 110)
+    elif case == "stride7":
+        win = tfsynth.regular_window("exp", 333, 7 * T, 150, 2 * T, 5 * T + 17, 70)
+    elif case == "before_after":
+        win = tfsynth.regular_window("exp", -40 * T - 11, 13 * T, 140, 3 * T, 9 * T + 1, 60)
+    elif case == "one_row_tile":
+        win = tfsynth.regular_window("exp", 100 * T + 7, 3 * T, 37, 40 * T, 11 * T, 21)
+    else:
+        tau = np.concatenate([np.arange(2, 30) * T + 11, np.arange(30, 80, 2) * T + 3, [900 * T, 1500 * T]])
+        win = tfsynth.list_window("exp", 5 + np.arange(0, 1300, 9) * T, tau)
     aid = ctx.upload_atoms(atoms)
     try:
-        res, twoF = ctx.fmap(aid, win, "bf16x3", want_map=True)
-        res32, twoF32 = ctx.fmap(aid, win, "fp32", want_map=True)
+        (res, twoF), prof = _kernel_launches(ctx, lambda: ctx.fmap(aid, win, "bf16x3", want_map=True))
+        ref = oracle.fmap_atoms(atoms, win)
+        err = check_map(twoF.cpu().numpy(), ref, TOL["bf16x3"])
+        check_results(res, ref, win, TOL["bf16x3"])
+        assert (prof["mfma"][0] > 0) == (case != "bins3_valu"), prof["mfma"]
+        # the same map again: bitwise repeatable
+        res2, _ = ctx.fmap(aid, win, "bf16x3")
+        assert res2 == res
     finally:
         ctx.free(aid)
-    got = twoF.cpu().numpy()
-    rng = np.random.default_rng(29)
-    mi, ni = _sample_cells(rng, win, 400)
-    ref = oracle.cells("exp", atoms.timestamps, atoms.a2, atoms.b2, atoms.ab, atoms.fa, atoms.fb,
-                       win.t0, win.tau, mi, ni)
-    err = check_map(got[:, mi, ni], ref, 1e-4)
-    g32 = twoF32.cpu().numpy().astype(np.float64)
-    dev = np.abs(got - g32) / np.maximum(g32, 1.0)
-    print("bf16x3 256 bins: max rel err vs oracle (sampled) %.3e, vs fp32 map %.3e"
-          % (err, dev.max()), flush=True)
-    assert dev.max() <= 2e-4
-    for b in range(atoms.n_bins):
-        assert abs(res[b]["logB"] - res32[b]["logB"]) <= 1e-3
-        assert abs(res[b]["max2F"] - res32[b]["max2F"]) <= 2e-4 * max(res32[b]["max2F"], 1.0)
+    print("bf16x3 %s: max rel err %.3e" % (case, err), flush=True)
 
 
 @pytest.mark.parametrize("case", ["stride1", "stride3_delta", "past_end", "before_data", "bins5",
@@ -492,6 +481,8 @@ def test_full_exp_1bin_recur64(ctx):
 
 
 def test_full_rect_workload_results(ctx):
+    """Rectangular window over the 256-bin atoms, 500 x 500 grid: every cell
+    and the per-bin results against the oracle."""
     _case("full rect 256 bins")
     atoms, win = tfsynth.workload_exp_bins()
     win = tfsynth.regular_window("rect", 0, T, 500, 2 * T, T, 500)
@@ -500,11 +491,9 @@ def test_full_rect_workload_results(ctx):
         res, twoF = ctx.fmap(aid, win, "fp64", want_map=True)
     finally:
         ctx.free(aid)
-    rng = np.random.default_rng(19)
-    mi, ni = _sample_cells(rng, win, 400)
-    ref = oracle.cells("rect", atoms.timestamps, atoms.a2, atoms.b2, atoms.ab, atoms.fa, atoms.fb,
-                       win.t0, win.tau, mi, ni)
-    check_map(twoF.cpu().numpy()[:, mi, ni], ref, 1e-9)
+    ref = oracle.fmap_atoms(atoms, win)
+    check_map(twoF.cpu().numpy(), ref, TOL["fp64"])
+    check_results(res, ref, win, TOL["fp64"])
 
 
 # ---------------------------------------------------------------------------

@@ -16,7 +16,10 @@ mathematics, each by a route that does not reuse the oracle's own formula:
     time shifts;
   * chi-square with 4 degrees of freedom of 2F in Gaussian noise, and the
     non-central mean 4 + lambda for injected signals;
-  * closed forms of the marginalised log Bayes factor.
+  * closed forms of the marginalised log Bayes factor;
+  * the selected-cell entry points (cells, cells_shape), which the
+    full-size GPU tests use as their reference, against the full map at the
+    same cells and against numerical likelihood maximisation.
 """
 from fractions import Fraction
 
@@ -523,3 +526,81 @@ def test_shape_sampled_exponential_approaches_exp_window():
     got = _shape_map(atoms, shp)
     assert np.all((got == 0) == (ref == 0))
     assert np.max(np.abs(got - ref) / np.maximum(ref, 1.0)) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Selected cells: the reference of the full-size GPU tests
+# ---------------------------------------------------------------------------
+
+def _cell_sample(rng, win, n):
+    m = rng.integers(0, win.n_t0, size=n)
+    k = rng.integers(0, win.n_tau, size=n)
+    m = np.concatenate([m, [0, 0, win.n_t0 - 1, win.n_t0 - 1]])
+    k = np.concatenate([k, [0, win.n_tau - 1, 0, win.n_tau - 1]])
+    return m.astype(np.int32), k.astype(np.int32)
+
+
+@pytest.mark.parametrize("kind", ["rect", "exp", "shape"])
+def test_cells_equal_full_map_at_same_cells(kind):
+    """oracle.cells / oracle.cells_shape return exactly the full map's value
+    at every selected (m, n), for every bin, on a ragged grid (t0 before,
+    inside and after the data, off the slot grid; tau below one SFT and past
+    the data) with an injection and gaps."""
+    atoms = tfsynth.make_atoms(61, 240, 0.15, n_bins=5,
+                               injections=[tfsynth.Injection(3, "exp", 50 * T, 20 * T, 1.5)])
+    rng = np.random.default_rng(62)
+    t0 = np.unique(np.concatenate([[-3 * T - 5, 0, 7], rng.integers(0, 240 * T, size=70),
+                                   [240 * T + 11]]))
+    tau = np.unique(np.concatenate([[T - 1, 2 * T], rng.integers(2 * T, 150 * T, size=40),
+                                    [300 * T]]))
+    base = tfsynth.list_window("rect" if kind == "rect" else "exp", t0, tau)
+    if kind == "shape":
+        x = np.linspace(0.0, 4.0, 129)
+        # every t0 one offset from the slot grid is not needed by the oracle
+        base = tfsynth.shape_window(base, x * np.exp(1.0 - x), (4, 1))
+    full = oracle.fmap_atoms(atoms, base)
+    mi, ni = _cell_sample(rng, base, 300)
+    sel = oracle.cells_atoms(atoms, base, mi, ni)
+    assert sel.shape == (atoms.n_bins, mi.shape[0])
+    assert np.array_equal(sel, full[:, mi, ni])
+    # threads change no arithmetic
+    assert np.array_equal(oracle.cells_atoms(atoms, base, mi, ni, n_threads=1), sel)
+
+
+def test_cells_against_likelihood_maximisation():
+    """A few selected cells of each window type against numerical
+    maximisation of the per-SFT likelihood ratio (weights from the
+    definition), independent of the closed form."""
+    atoms = tfsynth.make_atoms(63, 16, 0.0, n_bins=2,
+                               injections=[tfsynth.Injection(1, "rect", 3 * T, 6 * T, 1.3)])
+    t0s = np.array([0, T, 3 * T + 200, 5 * T], dtype=np.int64)
+    taus = np.array([2 * T + 5, 4 * T, 9 * T], dtype=np.int64)
+    mi = np.array([0, 1, 2, 3, 2], dtype=np.int32)
+    ni = np.array([2, 0, 1, 2, 2], dtype=np.int32)
+    for kind in ("rect", "exp", "shape"):
+        if kind == "shape":
+            win = tfsynth.shape_window(tfsynth.list_window("exp", t0s, taus),
+                                       np.array([1.0, 0.5, 0.0]), (2, 1))
+        else:
+            win = tfsynth.list_window(kind, t0s, taus)
+        got = oracle.cells_atoms(atoms, win, mi, ni)
+        for i, (m, n) in enumerate(zip(mi, ni)):
+            t0, tau = int(t0s[m]), int(taus[n])
+            if kind == "shape":
+                w = _shape_brute(atoms, t0, tau, lambda x: 1.0 - x / 2.0, t0 + 2 * tau)
+            else:
+                w = _window_weights(kind, atoms.timestamps, t0, tau)
+            for b in range(2):
+                if (w > 0).sum() < 2:
+                    assert got[b, i] == 0.0
+                    continue
+                bf = _brute_force_2F_weights(atoms, b, w)
+                assert got[b, i] == pytest.approx(bf, rel=1e-6, abs=1e-8), (kind, m, n, b)
+
+
+def test_cells_reject_out_of_range_indices():
+    atoms = tfsynth.make_atoms(65, 20, 0.0)
+    win = tfsynth.regular_window("exp", 0, T, 4, 2 * T, T, 3)
+    for mi, ni in (([4], [0]), ([0], [3]), ([-1], [0])):
+        with pytest.raises(ValueError):
+            oracle.cells_atoms(atoms, win, np.array(mi), np.array(ni))

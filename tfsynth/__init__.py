@@ -297,8 +297,13 @@ def request_stream(seed: int, rate_hz: float, duration_s: float,
     return out
 
 
+def request_window(atoms: Atoms, req: dict) -> Window:
+    """The request's grid (window type, N_t0 x N_tau, linspace) over `atoms`;
+    grid sizes are capped at the atoms' slots - 1."""
+    return linspace_grid(atoms, req["kind"], min(req["n_t0"], atoms.n_slots - 1),
+                         min(req["n_tau"], atoms.n_slots - 1))
+
+
 def request_atoms(req: dict):
     atoms = make_atoms(req["seed"], req["n_slots"], 0.10, req["n_bins"])
-    win = linspace_grid(atoms, req["kind"], min(req["n_t0"], req["n_slots"] - 1),
-                        min(req["n_tau"], req["n_slots"] - 1))
-    return atoms, win
+    return atoms, request_window(atoms, req)
