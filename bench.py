@@ -12,13 +12,16 @@ its window, truncated at the data end (the paper's N_sums of appendix A,
 eq. Nsums-exp, counted over present SFTs).
 
 The same JSON line also carries, unless --no-extras:
-  exp_256_bins   256 bins sharing one set of antenna atoms, bf16 hi + lo on
-                 matrix cores against the plain FP32 form, each with its 2F
-                 error against the oracle on sampled cells;
+  exp_256_bins   256 bins sharing one set of antenna atoms, split hi + lo
+                 half-precision (f16x3) and bf16 (bf16x3) parts on matrix
+                 cores against the plain FP32 form, each with its 2F error
+                 against the oracle on sampled cells;
   uneven_batch   64 uneven candidates as one batch (one captured graph, one
-                 persistent fused launch) against one map per call;
-  serving        a Poisson request stream with continuous batching, p50/p99,
-                 a load ramp and the sequential FP32 baseline;
+                 persistent fused launch, one matrix-core launch) in FP32,
+                 F16X3 and BF16X3, against one map per call;
+  serving        a Poisson request stream (F16X3 requests) with continuous
+                 batching, p50/p99, a load ramp and the sequential plain FP32
+                 baseline;
   cpu_baseline   the FP64 oracle on the host cores (all threads and one).
 
 Prints ONE JSON line.  Options:
@@ -26,7 +29,7 @@ Prints ONE JSON line.  Options:
   --steps K      timed steps (default 20)
   --warmup W     untimed steps (default 3)
   --workload     exp1bin (default) | exp256 | rect | rect256 | batch
-  --prec         fp32 (default) | fp64 | bf16x3 | recur64
+  --prec         fp32 (default) | fp64 | f16x3 | bf16x3 | recur64
   --no-extras, --no-cpu-baseline, --serve-seconds S (0 skips serving)
 """
 from __future__ import annotations
@@ -48,12 +51,15 @@ import tfsynth  # noqa: E402
 T = tfsynth.T_SFT
 PEAK_ALU_TFLOPS = 78.6    # non-packed FP32 and FP64 vector FMA, 256 CU x 64 lanes x 2 x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
-PEAK_BF16_TFLOPS = 2500.0  # dense bf16 matrix cores
+PEAK_BF16_TFLOPS = 2500.0  # dense bf16 and fp16 matrix cores
+MATRIX_PRECS = ("f16x3", "bf16x3")
+DTYPES = {"fp32": "f32+f64", "fp64": "f64", "bf16x3": "bf16x3(f32 acc)+f64", "f16x3": "f16x3(f32 acc)+f64",
+          "recur64": "f64"}
 
 
 def mfma_taus(atoms, win, taus_per_block: int = 8, min_band: int = 64, min_bins: int = 4):
     """Boolean mask of the taus whose sums run on the matrix cores in
-    BF16X3 -- the library's planning rule restated: exponential windows of at
+    F16X3 or BF16X3 -- the library's planning rule restated: exponential windows of at
     least 4 bins; blocks of 8 consecutive taus whose shortest band (the
     slots of [t0, t0 + 3 tau) over the row with the largest offset from the
     slot grid, capped at the data end) is at least 64 slots."""
@@ -330,7 +336,7 @@ def sampled_error(twoF, res, atoms, win, n_cells: int, seed: int):
 def roofline_for(atoms, win, prec, prof, workload):
     """Roofline of the dominant kernel of one map computation from the
     per-kernel HIP-event times of the timed steps."""
-    mfma = win.kind == "exp" and prec == "bf16x3" and prof["mfma"][0] > 0
+    mfma = win.kind == "exp" and prec in MATRIX_PRECS and prof["mfma"][0] > 0
     recur = win.kind == "exp" and prec == "recur64" and prof["recur"][0] > 0
     dom = "mfma" if mfma else ("recur" if recur else ("exp" if win.kind == "exp" else "rect"))
     n_launch, k_ms = prof[dom]
@@ -348,8 +354,9 @@ def roofline_for(atoms, win, prec, prof, workload):
                 "unit": "TFLOP/s"}
     elif mfma:
         # 4 complex-by-real MACs = 8 flops per cell*SFT*bin, issued as three
-        # bf16 products (hi*hi + hi*lo + lo*hi): 24 bf16 flops, counted over
-        # the tau blocks the matrix-core kernel runs
+        # half-precision or bf16 products (hi*hi + hi*lo + lo*hi): 24
+        # matrix-core flops, counted over the tau blocks the matrix-core
+        # kernel runs
         long_cells = mfma_cells(atoms, win)
         flops = 24.0 * long_cells
         roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_BF16_TFLOPS,
@@ -404,10 +411,10 @@ def time_map(ctx, aid, atoms, win, prec, twoF, steps, warmup, workload):
 
 def bench_exp256(args, tf, torch):
     """256 frequency bins sharing one set of antenna atoms (2000 slots, 10%
-    gaps, 500 x 500 grid, map written): the batched mixed-precision form
-    (bf16 hi + lo on matrix cores, FP32 accumulation, A/B/C/D in FP64)
-    against the plain FP32 VALU form, each with its largest 2F error
-    against the FP64 oracle on sampled cells."""
+    gaps, 500 x 500 grid, map written): the batched mixed-precision forms
+    (split hi + lo half-precision or bf16 parts on matrix cores, FP32
+    accumulation, A/B/C/D in FP64) against the plain FP32 VALU form, each
+    with its largest 2F error against the FP64 oracle on sampled cells."""
     atoms, win = tfsynth.workload_exp_bins()
     present, slots = work_counts(atoms, win)
     ctx = tf.Context(0, arena_bytes=2 << 30)
@@ -416,14 +423,15 @@ def bench_exp256(args, tf, torch):
     out = {"workload": "exp window, 256 bins sharing a,b, 2000 slots (10% gaps), 500 t0 x 500 tau "
                        "(2 .. 501 T_sft), map written",
            "cells_sfts_bins": present, "cells_slots_bins": slots, "unit": "cells*SFTs*bins/s"}
-    for prec in ("bf16x3", "fp32"):
+    for prec in ("f16x3", "bf16x3", "fp32"):
         r = time_map(ctx, aid, atoms, win, prec, twoF, args.steps, args.warmup, "exp256")
         err, n = sampled_error(twoF, r["res"], atoms, win, 2000, 2561)
         out[prec] = {"ms_per_step": r["ms_per_step"], "value": r["value"], "roofline": r["roofline"],
                      "kernels_ms": r["kernels_ms"],
                      "max_rel_err_2F_vs_oracle": err,
                      "oracle_cells_compared": "%d cells x 256 bins (random + each bin's argmax)" % n}
-    out["speedup_bf16x3_vs_fp32"] = out["fp32"]["ms_per_step"] / out["bf16x3"]["ms_per_step"]
+    for prec in MATRIX_PRECS:
+        out["speedup_%s_vs_fp32" % prec] = out["fp32"]["ms_per_step"] / out[prec]["ms_per_step"]
     ctx.free(aid)
     ctx.close()
     return out
@@ -433,8 +441,8 @@ def bench_batch(args, tf, torch, prec):
     """The uneven batch: 64 follow-up candidates (slots log-uniform in
     [500, 8000], gaps U[0, 0.3], grids U{100..1500}^2, 1..16 bins, rect and
     exp alternating) as one planned batch -- one captured graph with one
-    persistent fused launch per step (and, in BF16X3, one matrix-core launch
-    for the long-band blocks of maps of 4 or more bins) -- against the same
+    persistent fused launch per step (and, in F16X3 / BF16X3, one matrix-core
+    launch for the long-band blocks of maps of 4 or more bins) -- against the same
     maps computed one map per call.  Returns the record of the step."""
     cands = [tfsynth.candidate(i) for i in range(64)]
     exp_present = exp_slots = rect_cells = 0
@@ -446,10 +454,10 @@ def bench_batch(args, tf, torch, prec):
             p, sl = work_counts(a, w)
             exp_present += p
             exp_slots += sl
-            mc = mfma_cells(a, w) if prec == "bf16x3" else 0
+            mc = mfma_cells(a, w) if prec in MATRIX_PRECS else 0
             mfma_present += mc
             valu_present += p - mc
-            if not split_form(a, w, "fp32" if prec == "bf16x3" else prec) and mc == 0:
+            if not split_form(a, w, "fp32" if prec in MATRIX_PRECS else prec) and mc == 0:
                 abc_cells_sfts += p // a.n_bins
         else:
             rect_cells += w.n_t0 * w.n_tau * a.n_bins
@@ -520,8 +528,8 @@ def bench_batch(args, tf, torch, prec):
         "max_rel_err_2F_vs_oracle": err,
         "oracle_cells_compared": "%d cell-bins (64 random cells + each bin's argmax, every map)" % n_cmp,
     }
-    if prec == "bf16x3":
-        # the matrix-core launch: 24 bf16 flops per cell*SFT*bin it sums
+    if prec in MATRIX_PRECS:
+        # the matrix-core launch: 24 matrix-core flops per cell*SFT*bin it sums
         roof_m = {"bound": "mfma", "achieved": 24.0 * mfma_present / (mfma_ms * 1e-3) / 1e12,
                   "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "kernel": "mfma_batch",
                   "kernel_avg_ms": mfma_ms, "cells_sfts_bins": mfma_present, "traffic": None}
@@ -549,14 +557,14 @@ def main(argv=None):
                     help="skip timing the recurrence form of the same map")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline only: skip the 256-bin and uneven-batch records")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "bf16x3", "recur64"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64", "f16x3", "bf16x3", "recur64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-map", action="store_true",
                     help="do not write the 2F map (per-bin results only)")
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="length of the served request stream (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-prec", default="fp32", choices=["fp32", "fp64", "bf16x3", "recur64"])
+    ap.add_argument("--serve-prec", default="f16x3", choices=["fp32", "fp64", "f16x3", "bf16x3", "recur64"])
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the map, time a plain device-to-device copy of this many "
                          "bytes (calibrates HBM byte counters)")
@@ -587,14 +595,14 @@ def main(argv=None):
 
     metric = "F-map cells*SFTs/s (exp window) and served maps/s with p50/p99 latency"
     if args.workload == "batch":
-        if args.prec not in ("fp32", "fp64", "bf16x3"):
-            print("bench.py: the batch runs in fp32, fp64 or bf16x3", file=sys.stderr)
+        if args.prec not in ("fp32", "fp64", "f16x3", "bf16x3"):
+            print("bench.py: the batch runs in fp32, fp64, f16x3 or bf16x3", file=sys.stderr)
             return 2
         b = bench_batch(args, tf, torch, args.prec)
         out = {"metric": metric, "value": b.pop("value"), "unit": b.pop("unit"), "n_gpus": 1,
                "steps": args.steps, "warmup": args.warmup, "ms_per_step": b.pop("ms_per_step"),
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-               "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16x3": "bf16x3(f32 acc)+f64"}[args.prec],
+               "dtype": DTYPES[args.prec],
                "data": "synthetic",
                "roofline": b.pop("roofline"),
                "config": {"workload": b.pop("workload"), "parallelism": "single GPU"}, "batch": b}
@@ -619,8 +627,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32+f64", "fp64": "f64", "bf16x3": "bf16x3(f32 acc)+f64",
-                  "recur64": "f64"}[args.prec],
+        "dtype": DTYPES[args.prec],
         "data": "synthetic",
         "config": {"workload": desc, "n_slots": atoms.n_slots, "n_sft": atoms.n_sft,
                    "n_t0": win.n_t0, "n_tau": win.n_tau, "n_bins": atoms.n_bins,
@@ -651,8 +658,9 @@ def main(argv=None):
     if args.workload == "exp1bin" and not args.no_extras:
         ctx.close()
         out["exp_256_bins"] = bench_exp256(args, tf, torch)
-        ub = {"fp32": bench_batch(args, tf, torch, "fp32"), "bf16x3": bench_batch(args, tf, torch, "bf16x3")}
-        ub["speedup_bf16x3_vs_fp32"] = ub["fp32"]["ms_per_step"] / ub["bf16x3"]["ms_per_step"]
+        ub = {p: bench_batch(args, tf, torch, p) for p in ("fp32",) + MATRIX_PRECS}
+        for p in MATRIX_PRECS:
+            ub["speedup_%s_vs_fp32" % p] = ub["fp32"]["ms_per_step"] / ub[p]["ms_per_step"]
         out["uneven_batch"] = ub
         ctx = tf.Context(0, arena_bytes=24 << 30)
     if args.serve_seconds > 0:

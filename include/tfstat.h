@@ -77,11 +77,25 @@ typedef enum {
  *   FP64   : F_a, F_b sums in FP64.
  *   FP32   : F_a, F_b sums in FP32 (the paper's single precision).
  *   BF16X3 : F_a, F_b sums on bf16 matrix cores with split hi + lo operands
- *            (three products) and FP32 accumulation, for exponential windows
- *            whose t0 rows fall on consecutive slots with one common offset
- *            (dt0 = t_sft); groups of 8 taus holding a band shorter than
- *            64 slots, and every other grid, run the FP32 path.  The first BF16X3 call on an atoms set
- *            builds its bf16 planes (16 bytes per slot and bin of arena).
+ *            (three products: hi*hi + hi*lo + lo*hi) and FP32 accumulation
+ *            (section 3, exponential case: every cell is one banded
+ *            contraction over the SFTs, shared by all bins), for
+ *            exponential-window maps of 4 or more bins on any t0 grid, and
+ *            for shape windows whose t0 rows fall on consecutive slots with
+ *            one common offset.  Blocks of 8 taus whose shortest band is
+ *            under 64 slots, maps of fewer bins and other shape-window
+ *            grids run the FP32 sums.  bf16 hi + lo keeps 16 significant
+ *            bits per operand (relative residual up to 2^-17), so 2F can
+ *            miss a 1e-4 relative bound on a few cells of badly conditioned
+ *            windows; F16X3 meets it.  The first call on an atoms set builds
+ *            its bf16 planes (16 bytes per slot and bin of arena).
+ *   F16X3  : as BF16X3 with IEEE half-precision hi + lo parts (22
+ *            significant bits per operand, relative residual up to 2^-23),
+ *            the data columns scaled by powers of two (one per bin and
+ *            component, undone exactly in FP64) and the weights by 2^4, so
+ *            that no part leaves the half-precision range.  Exponential
+ *            windows only: shape windows run the FP32 sums.  Builds its own
+ *            planes on first use (16 bytes per slot and bin).
  *   RECUR64: exponential windows on a regular t0 grid whose step is a whole
  *            number of SFT slots (at most 64): every sum in FP64 by the exact
  *            recurrence of the window sums from one t0 to the next, O(1)
@@ -94,7 +108,8 @@ typedef enum {
     TFSTAT_PREC_FP64 = 0,
     TFSTAT_PREC_FP32 = 1,
     TFSTAT_PREC_BF16X3 = 2,
-    TFSTAT_PREC_RECUR64 = 3
+    TFSTAT_PREC_RECUR64 = 3,
+    TFSTAT_PREC_F16X3 = 4
 } tfstat_precision;
 
 /*
@@ -211,6 +226,19 @@ int tfstat_logB(tfstat_ctx *ctx, const float *twoF_dev, int32_t n_maps,
                 int32_t n_t0, int32_t n_tau, double *logB_host);
 
 /*
+ * A-posteriori comparison of two window models on the same atoms (section 5:
+ * different window functions are compared through their Bayes factors).
+ * Computes both maps like tfstat_fmap (no map is materialised) and writes,
+ * per bin, the log odds of window model a against window model b with even
+ * prior odds: log_odds_host[bin] = logB_a - logB_b, each logB marginalised
+ * over its own grid with a flat prior.  The two windows may differ in type,
+ * grid or both.  Synchronous on the context stream.
+ * Errors: as tfstat_fmap for either window.
+ */
+int tfstat_window_odds(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win_a,
+                       const tfstat_window *win_b, int32_t precision, double *log_odds_host);
+
+/*
  * Serving: queues a map request over resident atoms and returns a ticket at
  * once.  Requests run concurrently on the device as workspace memory and
  * worker slots allow (admission by arena footprint); each result equals the
@@ -237,10 +265,11 @@ int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t);
  * Serving admission.  Whenever one of the context's stream slots is free,
  * the requests at the head of the queue are admitted together: up to
  * max_batch of them (default 16), as many as the arena holds, run as one
- * batch with one persistent fused launch over all their tiles (FP32 and FP64
- * requests of up to 2e9 window terms -- cells x slots x bins, or cells x
- * bins for rectangular windows; larger requests, and matrix-core and
- * recurrence requests, run alone with their own kernels).  max_batch = 1
+ * batch with one persistent fused launch over all their tiles, plus one
+ * matrix-core launch for BF16X3 / F16X3 requests (requests of one precision
+ * each, of up to 2e9 window terms -- cells x slots x bins, or cells x bins
+ * for rectangular windows; larger requests, matrix-core shape windows and
+ * recurrence requests run alone with their own kernels).  max_batch = 1
  * admits one request per slot.  Results never depend on the batching.
  * Errors: E_INVAL (max_batch outside 1..1024).
  */
@@ -288,11 +317,12 @@ int tfstat_tiling_config(tfstat_ctx *ctx, int32_t runs_min_spread, int32_t split
  * (tune = 0 or 1; a forced variant, tune = -1 - v, may change tile shapes).
  * No maps are materialised.
  *   n_maps     number of maps; ids[i] and wins[i] describe map i.
- *   precision  TFSTAT_PREC_FP32, TFSTAT_PREC_FP64 or TFSTAT_PREC_BF16X3
- *              (exponential sums; rectangular windows always use compensated
- *              FP64 prefixes).  In BF16X3 the matrix-core work of all maps
- *              is one more launch after the persistent one; matrix-core
- *              shape windows are refused (E_INVAL; tfstat_fmap runs them).
+ *   precision  TFSTAT_PREC_FP32, TFSTAT_PREC_FP64, TFSTAT_PREC_BF16X3 or
+ *              TFSTAT_PREC_F16X3 (exponential sums; rectangular windows
+ *              always use compensated FP64 prefixes).  In BF16X3 and F16X3
+ *              the matrix-core work of all maps is one more launch after the
+ *              persistent one; matrix-core shape windows are refused
+ *              (E_INVAL; tfstat_fmap runs them).
  *   tune       0: each map's own tile shape, default launch width;
  *              1: time every candidate that keeps each map's own tile shape
  *              (the build for the stand-alone kernel's waves per SIMD or one

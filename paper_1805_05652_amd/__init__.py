@@ -20,7 +20,7 @@ from . import _abi
 from ._abi import TfstatError  # noqa: F401
 
 PRECISIONS = {"fp64": _abi.PREC_FP64, "fp32": _abi.PREC_FP32, "bf16x3": _abi.PREC_BF16X3,
-              "recur64": _abi.PREC_RECUR64}
+              "recur64": _abi.PREC_RECUR64, "f16x3": _abi.PREC_F16X3}
 WINDOWS = {"rect": _abi.WIN_RECT, "exp": _abi.WIN_EXP, "shape": _abi.WIN_SHAPE}
 
 
@@ -172,6 +172,16 @@ class Context:
         _abi.check(self._lib.tfstat_fmap(self._ctx, ctypes.c_uint64(atoms_id), ctypes.byref(wa.struct),
                                          _prec(precision), ptr, res))
         return _results(res), twoF
+
+    def window_odds(self, atoms_id: int, win_a, win_b, precision="fp32") -> np.ndarray:
+        """Per-bin log odds of window model a against b on the same atoms:
+        logB_a - logB_b (tfstat_window_odds)."""
+        wa = _WindowArgs.from_window(win_a)
+        wb = _WindowArgs.from_window(win_b)
+        out = np.empty(self._n_bins(atoms_id), dtype=np.float64)
+        _abi.check(self._lib.tfstat_window_odds(self._ctx, ctypes.c_uint64(atoms_id), ctypes.byref(wa.struct),
+                                                ctypes.byref(wb.struct), _prec(precision), out.ctypes.data))
+        return out
 
     def logB(self, twoF) -> np.ndarray:
         """logB of each map of a float32 CUDA tensor [n_maps, n_t0, n_tau]."""

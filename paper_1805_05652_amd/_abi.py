@@ -19,7 +19,7 @@ STATUS_NAMES = {
 }
 
 WIN_RECT, WIN_EXP, WIN_SHAPE = 0, 1, 2
-PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_RECUR64 = 0, 1, 2, 3
+PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_RECUR64, PREC_F16X3 = 0, 1, 2, 3, 4
 
 K_UPLOAD, K_WEIGHTS, K_EXP, K_SCAN, K_RECT, K_MERGE, K_MFMA, K_ABC, K_RECUR = range(9)
 KERNEL_NAMES = ["upload", "weights", "exp", "scan", "rect", "merge", "mfma", "abc", "recur"]
@@ -101,6 +101,8 @@ SIGNATURES = {
     "tfstat_fmap": (ctypes.c_int, [_P, _U64, ctypes.POINTER(Window), _I32, _P,
                                    ctypes.POINTER(BinResult)]),
     "tfstat_logB": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P]),
+    "tfstat_window_odds": (ctypes.c_int, [_P, _U64, ctypes.POINTER(Window), ctypes.POINTER(Window), _I32,
+                                          _P]),
     "tfstat_submit": (ctypes.c_int, [_P, _U64, ctypes.POINTER(Window), _I32, ctypes.POINTER(_U64)]),
     "tfstat_poll": (ctypes.c_int, [_P, _U64, ctypes.POINTER(BinResult), ctypes.POINTER(ctypes.c_int)]),
     "tfstat_cancel": (ctypes.c_int, [_P, _U64]),

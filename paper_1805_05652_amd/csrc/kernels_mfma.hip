@@ -31,6 +31,7 @@ namespace tfs {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -466,14 +467,23 @@ struct RowsSmem {
     Red wred[4][16];
 };
 
-// The lane's 8 weights of one K step as bf16 hi and lo parts (round to
-// nearest even; lo = bf16(w - hi), exact before its own rounding).  The
-// exponential is the hardware base-2 one: within a window its argument is in
-// (-3 log2(e), 0], far from the range where it would flush to zero.  EDGE:
-// the step may hold slots outside the lane's window [0, L), which weigh 0.
-template <bool EDGE>
+// The lane's 8 weights of one K step as hi and lo parts (lo = part(w - hi),
+// w - hi exact before its own rounding): bf16 (round to nearest even) or,
+// for F16, IEEE half precision (round toward zero; lo then keeps 11 of the
+// 13 remaining bits) of w * 2^kF16WeightExp (the caller folds the
+// factor into cD; it keeps the lo parts of the smallest weights, e^-3 * 2^-11,
+// out of the half-precision subnormal range).  The exponential is the
+// hardware base-2 one: within a window its argument is in (-3 log2(e), 0]
+// (plus the F16 offset), far from the range where it would flush to zero.
+// EDGE: the step may hold slots outside the lane's window [0, L), which
+// weigh 0.
+template <bool EDGE, bool F16>
 __device__ __attribute__((always_inline)) inline void rows_weights(int d0, float cT, float cD, float rho, int L,
-                                                                 bf16x8 &hi, bf16x8 &lo) {
+                                                                 u32x4 &h, u32x4 &l) {
+    // hi and lo must split one rounded FP32 weight: a product fused into
+    // the lo subtraction but not into the hi conversion would leave hi + lo
+    // one hi ulp (2^-11 in half precision) away from the weight
+#pragma clang fp contract(off)
     float w[8];
     w[0] = __builtin_amdgcn_exp2f(fmaf((float)d0, cT, cD));
 #pragma unroll
@@ -483,22 +493,39 @@ __device__ __attribute__((always_inline)) inline void rows_weights(int d0, float
         for (int j = 0; j < 8; ++j)
             if ((unsigned)(d0 + j) >= (unsigned)L) w[j] = 0.f;
     }
-    u32x4 h, l;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-        const bf16x2 h2 = {(__bf16)w[2 * p], (__bf16)w[2 * p + 1]};
-        const unsigned u = __builtin_bit_cast(unsigned, h2);
-        // hi parts as floats: the low half moved up (a byte permute, so that
-        // the compiler does not convert w again) and the high half masked
-        const float h0 = __uint_as_float(__builtin_amdgcn_perm(0u, u, 0x01000c0cu));
-        const float h1 = __uint_as_float(u & 0xffff0000u);
-        const bf16x2 l2 = {(__bf16)(w[2 * p] - h0), (__bf16)(w[2 * p + 1] - h1)};
-        h[p] = u;
-        l[p] = __builtin_bit_cast(unsigned, l2);
+        if constexpr (F16) {
+            // hi by the packing conversion (round toward zero), its value
+            // back from the packed halves, lo from the same rounded weights
+            const auto h2 = __builtin_amdgcn_cvt_pkrtz(w[2 * p], w[2 * p + 1]);
+            const float h0 = (float)h2[0], h1 = (float)h2[1];
+            const auto l2 = __builtin_amdgcn_cvt_pkrtz(w[2 * p] - h0, w[2 * p + 1] - h1);
+            h[p] = __builtin_bit_cast(unsigned, h2);
+            l[p] = __builtin_bit_cast(unsigned, l2);
+        } else {
+            typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+            const bf16x2 h2 = {(__bf16)w[2 * p], (__bf16)w[2 * p + 1]};
+            const unsigned u = __builtin_bit_cast(unsigned, h2);
+            // hi parts as floats: the low half moved up (a byte permute, so
+            // that the compiler does not convert w again) and the high half
+            // masked
+            const float h0 = __uint_as_float(__builtin_amdgcn_perm(0u, u, 0x01000c0cu));
+            const float h1 = __uint_as_float(u & 0xffff0000u);
+            const bf16x2 l2 = {(__bf16)(w[2 * p] - h0), (__bf16)(w[2 * p + 1] - h1)};
+            h[p] = u;
+            l[p] = __builtin_bit_cast(unsigned, l2);
+        }
     }
-    hi = bitcast4<bf16x8>(h);
-    lo = bitcast4<bf16x8>(l);
+}
+
+// One 16x16x32 product of the part type (bf16 or half), FP32 accumulate.
+template <bool F16>
+__device__ __attribute__((always_inline)) inline f32x4 mfma_part(u32x4 a, u32x4 b, f32x4 c) {
+    if constexpr (F16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(bitcast4<f16x8>(a), bitcast4<f16x8>(b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(bitcast4<bf16x8>(a), bitcast4<bf16x8>(b), c, 0, 0, 0);
 }
 
 // Buffer resource of `bytes` bytes at `base` (raw buffer: stride 0, offsets
@@ -507,7 +534,7 @@ __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-template <typename PP>
+template <bool F16, typename PP>
 __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, RowsSmem &sm, int q, int row_tile,
                                                                    int col_tile) {
     const int tid = threadIdx.x;
@@ -576,7 +603,7 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
             const int64_t tau = p.tau[n];
             const double inv = 1.4426950408889634 / (double)tau;
             cT[t] = (float)(-(double)T * inv);
-            cD[t] = (float)(-(double)ra.delta * inv);
+            cD[t] = (float)(-(double)ra.delta * inv) + (F16 ? (float)kF16WeightExp : 0.f);
             rho[t] = exp2f(cT[t]);
             const int64_t span = 3 * tau;
             L[t] = span > ra.delta ? (int)min((span - ra.delta + T - 1) / T, (int64_t)1 << 30) : 0;
@@ -615,17 +642,14 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
             const int d0 = kb + 8 * kg - ra.k0;
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
-                bf16x8 ah, al;
-                rows_weights<decltype(edge)::value>(d0, cT[t], cD[t], rho[t], L[t], ah, al);
+                u32x4 ah, al;
+                rows_weights<decltype(edge)::value, F16>(d0, cT[t], cD[t], rho[t], L[t], ah, al);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bitcast4<bf16x8>(ch[c]), acc[t][c], 0, 0, 0);
+                for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(ah, ch[c], acc[t][c]);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bitcast4<bf16x8>(cl[c]), acc[t][c], 0, 0, 0);
+                for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(ah, cl[c], acc[t][c]);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bitcast4<bf16x8>(ch[c]), acc[t][c], 0, 0, 0);
+                for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(al, ch[c], acc[t][c]);
             }
         };
         if (kb_begin < kb_end) {
@@ -649,7 +673,15 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
         // the folded A, B, C written by other lanes of this wave
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         __builtin_amdgcn_wave_barrier();
-        // finalize: lane holds rows 4 kg + r (r < 4) of the wave for `bin`
+        // finalize: lane holds rows 4 kg + r (r < 4) of the wave for `bin`;
+        // half-precision sums carry the powers of two of the weights and of
+        // their data column, removed exactly here
+        double sc[4] = {1.0, 1.0, 1.0, 1.0};
+        if constexpr (F16) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                sc[c] = ldexp(1.0, -(kF16WeightExp + p.colexp[c * p.bins16 + col_tile * 16 + lrow]));
+        }
         double v2[kNT][4];
         double fmx = -INFINITY;
         long long imx = 0x7fffffffffffffffLL;
@@ -662,8 +694,9 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
                 const int m = m_w + 4 * kg + r;
                 v2[t][r] = -INFINITY;
                 if (!n_ok || m >= n_t0 || !bin_ok) continue;
-                const double v = twoF_folded(sm.abc[wave][4 * kg + r][t0 + t], (double)acc[t][0][r],
-                                             (double)acc[t][1][r], (double)acc[t][2][r], (double)acc[t][3][r]);
+                const double v = twoF_folded(sm.abc[wave][4 * kg + r][t0 + t], sc[0] * (double)acc[t][0][r],
+                                             sc[1] * (double)acc[t][1][r], sc[2] * (double)acc[t][2][r],
+                                             sc[3] * (double)acc[t][3][r]);
                 if (p.twoF) p.twoF[((size_t)bin * n_t0 + m) * p.n_tau + n] = (float)v;
                 v2[t][r] = v;
                 const long long idx = (long long)m * p.n_tau + n;
@@ -708,6 +741,7 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
 
 // XCD-aware task order as in exp_mfma_kernel: column tiles dealt to the XCDs
 // when there are at least 8 of them, otherwise the tau blocks.
+template <bool F16>
 __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpMfmaRowsParams p) {
     __shared__ RowsSmem sm;
     const int bid = blockIdx.x;
@@ -730,10 +764,11 @@ __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpM
         row_tile = rem / p.n_col_tiles;
         col_tile = rem % p.n_col_tiles;
     }
-    mfma_rows_tile(p, sm, q, row_tile, col_tile);
+    mfma_rows_tile<F16>(p, sm, q, row_tile, col_tile);
 }
 
 // Matrix-core work items of many maps (one entry per workgroup).
+template <bool F16>
 __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void mfma_batch_kernel(MfmaBatchParams b) {
     __shared__ RowsSmem sm;
     const int e = blockIdx.x;
@@ -741,16 +776,40 @@ __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void mfma_batch_kernel(MfmaBat
     const int q = b.entries[4 * e + 1];
     const int row_tile = b.entries[4 * e + 2];
     const int col_tile = b.entries[4 * e + 3];
-    mfma_rows_tile(*reinterpret_cast<const __attribute__((address_space(4))) ExpMfmaRowsParams *>(
+    mfma_rows_tile<F16>(*reinterpret_cast<const __attribute__((address_space(4))) ExpMfmaRowsParams *>(
                        reinterpret_cast<uintptr_t>(b.jobs + job)),
                    sm, q, row_tile, col_tile);
 }
 
-// bf16 hi / lo planes from the FP32 atoms x32 [K+1][bins][4], laid out
+// Per data column (component c, bin) of the FP32 atoms x32 [K+1][bins][4],
+// the power of two e with max_k |x| * 2^e in [2^13, 2^14) (0 for an
+// all-zero column), so that the half-precision hi parts stay below the
+// format's largest value and the lo parts of all but tiny entries stay
+// normal; colexp is [4][bins16].
+__global__ __launch_bounds__(256) void col_exp_kernel(const float *x32, int32_t K, int32_t n_bins,
+                                                      int32_t bins16, int32_t *colexp) {
+    const int col = blockIdx.x * 256 + threadIdx.x;   // bin * 4 + c
+    if (col >= 4 * bins16) return;
+    const int bin = col >> 2, c = col & 3;
+    float mx = 0.f;
+    if (bin < n_bins)
+        for (int32_t k = 0; k < K; ++k) mx = fmaxf(mx, fabsf(x32[(size_t)k * n_bins * 4 + col]));
+    int e = 0;
+    if (mx > 0.f) {
+        int ex;
+        (void)frexpf(mx, &ex);   // mx in [2^(ex-1), 2^ex)
+        e = 14 - ex;
+    }
+    colexp[c * bins16 + bin] = e;
+}
+
+// hi / lo planes from the FP32 atoms x32 [K+1][bins][4], laid out
 // [4 components][kp / 32 steps][bins16][32 slots]: the B operand of one K
-// step for 16 bins is one contiguous kilobyte.
+// step for 16 bins is one contiguous kilobyte.  bf16 (round to nearest
+// even), or half precision of x * 2^colexp (exact scaling).
+template <bool F16>
 __global__ __launch_bounds__(256) void build_planes_kernel(const float *x32, int32_t K, int32_t n_bins,
-                                                           int32_t bins16, int32_t kp,
+                                                           int32_t bins16, int32_t kp, const int32_t *colexp,
                                                            unsigned short *xhi, unsigned short *xlo) {
     const int64_t total = (int64_t)4 * bins16 * kp;
     const int64_t per_c = (int64_t)bins16 * kp;
@@ -763,9 +822,18 @@ __global__ __launch_bounds__(256) void build_planes_kernel(const float *x32, int
         const int64_t k = step * 32 + (r2 % 32);
         float x = 0.f;
         if (k < K && bin < n_bins) x = x32[((size_t)k * n_bins + bin) * 4 + c];
-        const unsigned int pk = split_pack(x);
-        xhi[i] = (unsigned short)(pk & 0xffffu);
-        xlo[i] = (unsigned short)(pk >> 16);
+        if constexpr (F16) {
+#pragma clang fp contract(off)
+            x = ldexpf(x, colexp[c * bins16 + bin]);
+            const _Float16 h = (_Float16)x;
+            const _Float16 l = (_Float16)(x - (float)h);
+            xhi[i] = __builtin_bit_cast(unsigned short, h);
+            xlo[i] = __builtin_bit_cast(unsigned short, l);
+        } else {
+            const unsigned int pk = split_pack(x);
+            xhi[i] = (unsigned short)(pk & 0xffffu);
+            xlo[i] = (unsigned short)(pk >> 16);
+        }
     }
 }
 
@@ -797,13 +865,19 @@ hipError_t launch_exp_mfma_rows(const ExpMfmaRowsParams &p, hipStream_t s) {
         const int groups = (p.n_blocks + 7) / 8;
         grid = (unsigned)(8 * groups * p.n_row_tiles * p.n_col_tiles);
     }
-    hipLaunchKernelGGL(exp_mfma_rows_kernel, dim3(grid), dim3(256), 0, s, p);
+    if (p.f16)
+        hipLaunchKernelGGL(exp_mfma_rows_kernel<true>, dim3(grid), dim3(256), 0, s, p);
+    else
+        hipLaunchKernelGGL(exp_mfma_rows_kernel<false>, dim3(grid), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_batch(const MfmaBatchParams &p, hipStream_t s) {
     if (p.n_entries <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mfma_batch_kernel, dim3((unsigned)p.n_entries), dim3(256), 0, s, p);
+    if (p.f16)
+        hipLaunchKernelGGL(mfma_batch_kernel<true>, dim3((unsigned)p.n_entries), dim3(256), 0, s, p);
+    else
+        hipLaunchKernelGGL(mfma_batch_kernel<false>, dim3((unsigned)p.n_entries), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
@@ -817,13 +891,22 @@ hipError_t launch_shift_tables(const ShiftTableParams &p, int64_t max_entries, h
 }
 
 hipError_t launch_build_planes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16, int32_t kp,
-                               unsigned short *xhi, unsigned short *xlo, hipStream_t s) {
+                               int32_t *colexp, unsigned short *xhi, unsigned short *xlo, hipStream_t s) {
     const int64_t total = (int64_t)4 * bins16 * kp;
     int64_t g = (total + 255) / 256;
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(build_planes_kernel, dim3((unsigned)g), dim3(256), 0, s, x32, K, n_bins, bins16,
-                       kp, xhi, xlo);
+    if (colexp) {
+        hipLaunchKernelGGL(col_exp_kernel, dim3((unsigned)((4 * bins16 + 255) / 256)), dim3(256), 0, s, x32, K,
+                           n_bins, bins16, colexp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(build_planes_kernel<true>, dim3((unsigned)g), dim3(256), 0, s, x32, K, n_bins, bins16,
+                           kp, (const int32_t *)colexp, xhi, xlo);
+    } else {
+        hipLaunchKernelGGL(build_planes_kernel<false>, dim3((unsigned)g), dim3(256), 0, s, x32, K, n_bins,
+                           bins16, kp, (const int32_t *)nullptr, xhi, xlo);
+    }
     return hipGetLastError();
 }
 

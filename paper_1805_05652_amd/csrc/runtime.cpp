@@ -171,6 +171,11 @@ struct AtomsSet {
     // bf16 hi / lo planes for the matrix-core path, built on first use
     void *planes = nullptr;
     unsigned short *xhi = nullptr, *xlo = nullptr;
+    // half-precision hi / lo planes of the scaled columns and the columns'
+    // scale exponents (F16X3), built on first use
+    void *planes16 = nullptr;
+    unsigned short *xhi16 = nullptr, *xlo16 = nullptr;
+    int32_t *colexp = nullptr;
     int32_t bins16 = 0, kp = 0;
     int busy = 0;
     tfs::AtomsView view() const {
@@ -194,6 +199,9 @@ struct WindowOwned {
 
 // Banded windows run the exponential window's kernels.
 inline bool banded(int32_t type) { return type == TFSTAT_WIN_EXP || type == TFSTAT_WIN_SHAPE; }
+
+// Precisions whose long-band exponential sums run on the matrix cores.
+inline bool matrix_prec(int32_t prec) { return prec == TFSTAT_PREC_BF16X3 || prec == TFSTAT_PREC_F16X3; }
 
 WindowOwned copy_window(const tfstat_window *w) {
     if (!w) raise(TFSTAT_E_INVAL, "window is null");
@@ -375,10 +383,11 @@ void plan_job(Job &j) {
     // band grows with tau, so block b's shortest is that of its first tau).
     j.use_mfma = false;
     j.mfma_rows = false;
-    if (is_exp && j.prec == TFSTAT_PREC_BF16X3) {
+    if (is_exp && matrix_prec(j.prec)) {
         bool ok;
         if (is_shape) {
-            ok = j.rows[0].k0 >= 0;
+            // the shifted bf16 tables; F16X3 shape windows run the FP32 sums
+            ok = j.prec == TFSTAT_PREC_BF16X3 && j.rows[0].k0 >= 0;
             for (int m = 1; m < n_t0 && ok; ++m)
                 ok = j.rows[m].k0 == j.rows[0].k0 + m && j.rows[m].delta == j.rows[0].delta;
         } else {
@@ -760,8 +769,10 @@ tfs::ExpMfmaRowsParams mfma_rows_params(Job &j, const int32_t *blk_list) {
     q.rows = ws_ptr<tfs::RowPlan>(j, j.off_rows);
     q.tau = ws_ptr<int64_t>(j, j.off_tau);
     q.blk_list = blk_list;
-    q.xhi = at.xhi;
-    q.xlo = at.xlo;
+    q.f16 = j.prec == TFSTAT_PREC_F16X3;
+    q.xhi = q.f16 ? at.xhi16 : at.xhi;
+    q.xlo = q.f16 ? at.xlo16 : at.xlo;
+    q.colexp = q.f16 ? at.colexp : nullptr;
     q.abc_cell = ws_ptr<double>(j, j.off_abc);
     q.abc_pitch = abc_pitch(q.n_tau);
     q.twoF = j.twoF;
@@ -989,33 +1000,44 @@ void finish_job(tfstat_ctx *ctx, Job &j, tfstat_bin_result *out) {
     convert_results(j, static_cast<const tfs::BinResultDev *>(j.pin), out);
 }
 
-// bf16 hi / lo planes of the data atoms for the matrix-core path; built
-// once per atoms set on the context stream.  Caller holds ctx->mu.
-void ensure_planes(tfstat_ctx *ctx, AtomsSet *at) {
-    if (at->planes) return;
+// hi / lo planes of the data atoms for the matrix-core path (bf16, or for
+// F16X3 half precision with per-column scale exponents); built once per
+// atoms set and part type on the context stream.  Caller holds ctx->mu.
+void ensure_planes(tfstat_ctx *ctx, AtomsSet *at, int32_t prec) {
+    const bool f16 = prec == TFSTAT_PREC_F16X3;
+    if (f16 ? at->planes16 != nullptr : at->planes != nullptr) return;
     const int32_t bins16 = (at->n_bins + 15) / 16 * 16;
     const int32_t kp = (at->K + 31) / 32 * 32 + 32;
     const size_t plane = sizeof(unsigned short) * 4 * (size_t)bins16 * kp;
     const size_t plane_b = round_up(plane, 256);
-    void *mem = ctx->arena.alloc(2 * plane_b);
-    if (!mem) raise(TFSTAT_E_NOMEM, "arena cannot hold the bf16 planes");
+    const size_t exp_b = f16 ? round_up(sizeof(int32_t) * 4 * (size_t)bins16, 256) : 0;
+    void *mem = ctx->arena.alloc(2 * plane_b + exp_b);
+    if (!mem) raise(TFSTAT_E_NOMEM, "arena cannot hold the matrix-core planes");
     try {
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
         auto *xhi = static_cast<unsigned short *>(mem);
         auto *xlo = reinterpret_cast<unsigned short *>(static_cast<char *>(mem) + plane_b);
-        hip_check(tfs::launch_build_planes(at->x32, at->K, at->n_bins, bins16, kp, xhi, xlo, ctx->stream),
+        auto *colexp = f16 ? reinterpret_cast<int32_t *>(static_cast<char *>(mem) + 2 * plane_b) : nullptr;
+        hip_check(tfs::launch_build_planes(at->x32, at->K, at->n_bins, bins16, kp, colexp, xhi, xlo,
+                                           ctx->stream),
                   "planes kernel");
         hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-        at->xhi = xhi;
-        at->xlo = xlo;
+        if (f16) {
+            at->xhi16 = xhi;
+            at->xlo16 = xlo;
+            at->colexp = colexp;
+        } else {
+            at->xhi = xhi;
+            at->xlo = xlo;
+        }
     } catch (...) {
         ctx->arena.release(mem);
         throw;
     }
-    at->planes = mem;
+    (f16 ? at->planes16 : at->planes) = mem;
     at->bins16 = bins16;
     at->kp = kp;
-    at->bytes += 2 * plane_b;
+    at->bytes += 2 * plane_b + exp_b;
 }
 
 AtomsSet *find_atoms(tfstat_ctx *ctx, tfstat_atoms_id id) {
@@ -1353,6 +1375,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     b->mfp.jobs = reinterpret_cast<const tfs::ExpMfmaRowsParams *>(dptr(off_mfp));
     b->mfp.entries = reinterpret_cast<const int32_t *>(dptr(off_ment));
     b->mfp.n_entries = (int32_t)mfe;
+    b->mfp.f16 = b->prec == TFSTAT_PREC_F16X3;
     b->mbp.jobs = reinterpret_cast<const tfs::MergeParams *>(dptr(off_mp));
     b->mbp.job = reinterpret_cast<const int32_t *>(dptr(off_mjob));
     b->mbp.map = reinterpret_cast<const int32_t *>(dptr(off_mmap));
@@ -1388,8 +1411,8 @@ void batch_build(tfstat_ctx *ctx, tfstat_batch *b, int32_t n, const tfstat_atoms
             b->jobs.push_back(j.get());
         }
         b->holds_atoms = true;
-        if (prec == TFSTAT_PREC_BF16X3)
-            for (auto &j : b->owned) ensure_planes(ctx, j->at);
+        if (matrix_prec(prec))
+            for (auto &j : b->owned) ensure_planes(ctx, j->at, prec);
     }
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
@@ -1528,7 +1551,7 @@ double est_work(const Job &j) {
 }
 
 bool fusable(const Job &j) {
-    return (j.prec == TFSTAT_PREC_FP32 || j.prec == TFSTAT_PREC_FP64 || j.prec == TFSTAT_PREC_BF16X3) &&
+    return (j.prec == TFSTAT_PREC_FP32 || j.prec == TFSTAT_PREC_FP64 || matrix_prec(j.prec)) &&
            !(j.use_mfma && !j.mfma_rows) && !j.use_recur && est_work(j) <= kServeFuseMaxWork;
 }
 
@@ -1871,6 +1894,7 @@ int tfstat_atoms_free(tfstat_ctx *ctx, tfstat_atoms_id id) {
         if (s->busy > 0) raise(TFSTAT_E_BUSY, "atoms are in use by submitted requests");
         ctx->arena.release(s->mem);
         if (s->planes) ctx->arena.release(s->planes);
+        if (s->planes16) ctx->arena.release(s->planes16);
         ctx->atoms.erase(id);
         return (int)TFSTAT_OK;
     });
@@ -1891,13 +1915,13 @@ int tfstat_fmap(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win, i
                 float *twoF_dev, tfstat_bin_result *res_host) {
     return guarded([&] {
         if (!ctx || !res_host) raise(TFSTAT_E_INVAL, "null argument");
-        if (precision < TFSTAT_PREC_FP64 || precision > TFSTAT_PREC_RECUR64)
+        if (precision < TFSTAT_PREC_FP64 || precision > TFSTAT_PREC_F16X3)
             raise(TFSTAT_E_INVAL, "unknown precision");
         Job j;
         {
             std::lock_guard<std::mutex> g(ctx->mu);
             j.at = find_atoms(ctx, id);
-            if (precision == TFSTAT_PREC_BF16X3) ensure_planes(ctx, j.at);
+            if (matrix_prec(precision)) ensure_planes(ctx, j.at, precision);
         }
         j.win = copy_window(win);
         j.prec = precision;
@@ -1981,18 +2005,37 @@ int tfstat_logB(tfstat_ctx *ctx, const float *twoF_dev, int32_t n_maps, int32_t 
     });
 }
 
+int tfstat_window_odds(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win_a,
+                       const tfstat_window *win_b, int32_t precision, double *log_odds_host) {
+    return guarded([&] {
+        if (!ctx || !win_a || !win_b || !log_odds_host) raise(TFSTAT_E_INVAL, "null argument");
+        int32_t n_bins = 0;
+        {
+            std::lock_guard<std::mutex> g(ctx->mu);
+            n_bins = find_atoms(ctx, id)->n_bins;
+        }
+        std::vector<tfstat_bin_result> ra(n_bins), rb(n_bins);
+        int rc = tfstat_fmap(ctx, id, win_a, precision, nullptr, ra.data());
+        if (rc != TFSTAT_OK) return rc;
+        rc = tfstat_fmap(ctx, id, win_b, precision, nullptr, rb.data());
+        if (rc != TFSTAT_OK) return rc;
+        for (int32_t b = 0; b < n_bins; ++b) log_odds_host[b] = ra[b].logB - rb[b].logB;
+        return (int)TFSTAT_OK;
+    });
+}
+
 int tfstat_submit(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window *win, int32_t precision,
                   tfstat_ticket *out) {
     return guarded([&] {
         if (!ctx || !out) raise(TFSTAT_E_INVAL, "null argument");
-        if (precision < TFSTAT_PREC_FP64 || precision > TFSTAT_PREC_RECUR64)
+        if (precision < TFSTAT_PREC_FP64 || precision > TFSTAT_PREC_F16X3)
             raise(TFSTAT_E_INVAL, "unknown precision");
         auto job = std::make_unique<Job>();
         job->win = copy_window(win);
         job->prec = precision;
         std::lock_guard<std::mutex> g(ctx->mu);
         job->at = find_atoms(ctx, id);
-        if (precision == TFSTAT_PREC_BF16X3) ensure_planes(ctx, job->at);
+        if (matrix_prec(precision)) ensure_planes(ctx, job->at, precision);
         job->runs_min_spread = ctx->runs_min_spread.load();
         job->split_min_bins = ctx->split_min_bins.load();
         plan_job(*job);
@@ -2067,8 +2110,8 @@ int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *
     return guarded([&] {
         if (!ctx || !ids || !wins || !out) raise(TFSTAT_E_INVAL, "null argument");
         if (n_maps < 1) raise(TFSTAT_E_INVAL, "n_maps must be >= 1");
-        if (precision != TFSTAT_PREC_FP32 && precision != TFSTAT_PREC_FP64 && precision != TFSTAT_PREC_BF16X3)
-            raise(TFSTAT_E_INVAL, "a batch runs in FP32, FP64 or BF16X3");
+        if (precision != TFSTAT_PREC_FP32 && precision != TFSTAT_PREC_FP64 && !matrix_prec(precision))
+            raise(TFSTAT_E_INVAL, "a batch runs in FP32, FP64, BF16X3 or F16X3");
         if (tune > 1 || tune < -2 * (tfs::kShapeMixed + 1))
             raise(TFSTAT_E_INVAL, "tune must be 0, 1 or -1 - variant");
         ensure_batch_stream(ctx);

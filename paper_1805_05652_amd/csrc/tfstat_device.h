@@ -123,13 +123,17 @@ struct ExpMfmaRowsParams {
     const RowPlan *rows;      // [n_t0]
     const int64_t *tau;       // [n_tau]
     const int32_t *blk_list;  // [n_blocks] blocks of 8 taus
-    const unsigned short *xhi, *xlo;  // bf16 planes [4][kp / 32][bins16][32]
+    const unsigned short *xhi, *xlo;  // bf16 or half planes [4][kp / 32][bins16][32]
+    const int32_t *colexp;    // half planes: column scale exponents [4][bins16]
     const double *abc_cell;   // [n_t0][abc_pitch][3] (scaled, exact band)
     int32_t abc_pitch;        // n_tau rounded up to 8
-    int32_t pad;
+    int32_t f16;              // 1: half-precision parts (F16X3), 0: bf16
     float *twoF;
     Partial *part;
 };
+
+// Half-precision matrix-core weights are taken as w * 2^kF16WeightExp.
+constexpr int kF16WeightExp = 4;
 
 // Matrix-core work of many maps in one launch: entry e is {map, position in
 // the map's blk_list, 64-row tile, 16-bin column tile}.
@@ -137,7 +141,7 @@ struct MfmaBatchParams {
     const ExpMfmaRowsParams *jobs;
     const int32_t *entries;   // [n_entries][4]
     int32_t n_entries;
-    int32_t pad;
+    int32_t f16;              // every job's parts: 1 half, 0 bf16
 };
 
 struct ShiftTableParams {
@@ -358,7 +362,7 @@ static_assert(TFS_MFMA_SHIFTS == 4 || TFS_MFMA_SHIFTS == 8, "shifted copies");
 // every staged window [d_lo + kPad, d_lo + kPad + kTW) with d_lo <= lblk - 1.
 inline int32_t shift_table_len(int32_t lblk) { return (kMfmaPad + lblk + kMfmaTW + 8 + 7) / 8 * 8; }
 hipError_t launch_build_planes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16,
-                               int32_t kp, unsigned short *xhi, unsigned short *xlo,
+                               int32_t kp, int32_t *colexp, unsigned short *xhi, unsigned short *xlo,
                                hipStream_t s);
 hipError_t launch_scan(const double *in, int64_t in_row_stride, double *out,
                        int32_t K, int32_t C, hipStream_t s);

@@ -110,6 +110,14 @@ def fit_with_offset(runs, short_max_sums: float = 100.0):
             "c_sums_exp": (float(c_es), float(e_es))}
 
 
+def predict(fit, run) -> float:
+    """Modelled time of one run (keys as in fit_paper) from a fit: eq.
+    cost-rect-Nsums or eq. cost-exp-Nsums, plus c_0 when the fit has one."""
+    c_sums = fit["c_sums_rect"][0] if run["kind"] == "rect" else fit["c_sums_exp"][0]
+    return (fit.get("c_0", (0.0, 0.0))[0] + fit["c_SFTs"][0] * run["n_sft"] + c_sums * run["n_sums"]
+            + fit["c_F"][0] * run["n_cells"])
+
+
 def pgm_constants(fit, n_sft, n_t0, n_tau, tau_min, tau_max, dtau, t_sft=T_SFT):
     """PGM's per-step constants in the embedded case (eq. cost-rect-convert,
     eq. cost-exp-convert), with the fitted constants' central values."""
@@ -138,7 +146,11 @@ def setups(quick: bool = False):
     return out
 
 
-def time_runs(reps: int = 5, quick: bool = False, precision: str = "fp32", seed: int = 9000):
+def time_runs(reps: int = 5, quick: bool = False, precision: str = "fp32", seed: int = 9000,
+              on_result=None):
+    """Times tfstat_fmap over `setups(quick)`: one untimed call, then the
+    median of `reps` timed calls per setup.  on_result(atoms, win, results),
+    when given, receives each setup's per-bin results."""
     import torch
     import paper_1805_05652_amd as tf
     import tfsynth
@@ -149,7 +161,9 @@ def time_runs(reps: int = 5, quick: bool = False, precision: str = "fp32", seed:
             atoms = tfsynth.make_atoms(seed + i, k, 0.0, n_bins=1)
             win = tfsynth.linspace_grid(atoms, kind, n_t0, n_tau)
             aid = ctx.upload_atoms(atoms)
-            ctx.fmap(aid, win, precision)
+            res, _ = ctx.fmap(aid, win, precision)
+            if on_result is not None:
+                on_result(atoms, win, res)
             ts = []
             for _ in range(reps):
                 torch.cuda.synchronize()

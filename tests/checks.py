@@ -3,11 +3,17 @@ CPU oracle).
 
 Tolerances (floating point):
   * 2F: |2F_gpu - 2F_oracle| <= tol * max(2F_oracle, 1), tol = 1e-4 for FP32
-    and bf16x3 sums, 1e-9 for FP64 sums; stored maps are float32, so map
-    comparisons also allow their rounding (2^-23 relative);
+    and f16x3 sums (half-precision hi + lo parts, 22 significant bits per
+    operand), 1e-9 for FP64 sums; stored maps are float32, so map
+    comparisons also allow their rounding (2^-23 relative).  bf16x3 parts
+    keep 16 significant bits per operand (residual up to 2^-17 relative on
+    each of the weight and the datum, plus the dropped lo*lo product, 2^-16):
+    up to ~3e-5 per term before the conditioning of F amplifies it, so the
+    1e-4 bound holds for f16x3, not for bf16x3 (measured up to 1.5e-4 on the
+    256-bin workload's full map); bf16x3 is checked at 4e-4;
   * logB: absolute 1e-3;
   * argmax: exact, or a near-tie: 2F_oracle at the GPU's argmax is at least
-    (1 - 1e-4) * max 2F_oracle;
+    (1 - 1e-4) * max 2F_oracle (1 - 2 tol for bf16x3);
   * degenerate cells (2F = 0 in the oracle) are exactly 0 on the GPU.
 """
 import numpy as np
@@ -15,7 +21,7 @@ import numpy as np
 import oracle
 
 F32_MAP = 2.0 ** -23
-TOL = {"fp32": 1e-4, "fp64": 1e-9, "bf16x3": 1e-4, "recur64": 1e-8}
+TOL = {"fp32": 1e-4, "fp64": 1e-9, "f16x3": 1e-4, "bf16x3": 4e-4, "recur64": 1e-8}
 LOGB_TOL = 1e-3
 NEAR_TIE = 1e-4
 
@@ -44,7 +50,9 @@ def check_results(res, ref_map, win, tol):
         assert abs(r["max2F"] - mx[b]) <= tol * max(mx[b], 1.0), (b, r["max2F"], mx[b])
         flat = ref_map[b].ravel()
         idx = r["m"] * win.n_tau + r["n"]
-        assert idx == am[b] or flat[idx] >= (1 - NEAR_TIE) * mx[b], (b, idx, am[b])
+        # a near-tie: within the 2F tolerance of both cells (1e-4 at most)
+        near = NEAR_TIE if tol <= NEAR_TIE else 2.0 * tol
+        assert idx == am[b] or flat[idx] >= (1 - near) * mx[b], (b, idx, am[b])
         assert r["t0"] == win.t0[r["m"]] and r["tau"] == win.tau[r["n"]]
 
 

@@ -18,7 +18,7 @@ import tfsynth
 pytestmark = pytest.mark.gpu
 
 T = tfsynth.T_SFT
-TOL = {"fp32": 1e-4, "fp64": 1e-9, "bf16x3": 1e-4}
+from checks import TOL, check_results  # noqa: E402
 
 
 def _case(msg):
@@ -40,15 +40,7 @@ def small_candidates(n=8, seed_base=7100):
 
 
 def check_against_oracle(res, atoms, win, tol):
-    ref = oracle.fmap_atoms(atoms, win)
-    mx, am, lb = oracle.reduce(ref)
-    assert len(res) == atoms.n_bins
-    for b, r in enumerate(res):
-        assert abs(r["logB"] - lb[b]) <= 1e-3, (b, r["logB"], lb[b])
-        assert abs(r["max2F"] - mx[b]) <= tol * max(mx[b], 1.0), (b, r["max2F"], mx[b])
-        idx = r["m"] * win.n_tau + r["n"]
-        assert idx == am[b] or ref[b].ravel()[idx] >= (1 - 1e-4) * mx[b], (b, idx, am[b])
-        assert r["t0"] == win.t0[r["m"]] and r["tau"] == win.tau[r["n"]]
+    check_results(res, oracle.fmap_atoms(atoms, win), win, tol)
 
 
 def same_results(a, b):
@@ -210,7 +202,7 @@ def test_batch_holds_atoms_and_rejects_bad_input(ctx):
     assert e.value.code == tf._abi.E_BUSY
     b.close()
     with pytest.raises(tf.TfstatError) as e:
-        ctx.batch(items, "bf16x3")
+        ctx.batch(items, "recur64")
     assert e.value.code == tf._abi.E_INVAL
     with pytest.raises(tf.TfstatError) as e:
         ctx.batch([(987654, cands[0][1])], "fp32")
@@ -341,26 +333,28 @@ def test_timed_run_matches_graph_run(ctx):
             ctx.free(aid)
 
 
-def test_bf16x3_batch_against_oracle_and_fmap(ctx):
-    """A BF16X3 batch of uneven candidates (1-24 bins: maps of 4 or more bins
-    on the matrix cores, the others on FP32 tiles; rect maps; linspace
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
+def test_matrix_batch_against_oracle_and_fmap(ctx, prec):
+    """A matrix-core batch of uneven candidates (1-24 bins: maps of 4 or more
+    bins on the matrix cores, the others on FP32 tiles; rect maps; linspace
     grids): every map against the oracle and bit-identical to tfstat_fmap of
-    the same map in BF16X3, autotuned and forced to the default build."""
-    _case("bf16x3 batch")
+    the same map in the same precision, autotuned and forced to the default
+    build."""
+    _case(prec + " batch")
     cands = [tfsynth.candidate(i, seed_base=7700, max_slots=1500, max_grid=170, max_bins=24)
              for i in range(10)]
     assert any(a.n_bins >= 4 and w.kind == "exp" for a, w in cands)
     ids = upload_all(ctx, cands)
     try:
         for tune in (True, False):
-            with ctx.batch(list(zip(ids, [w for _, w in cands])), "bf16x3", tune=tune) as b:
+            with ctx.batch(list(zip(ids, [w for _, w in cands])), prec, tune=tune) as b:
                 assert b.stats()["variant"] in ("mixed", "mixed_lowocc")
                 got = b.run()
                 again = b.run()
             for (atoms, win), aid, res, res2 in zip(cands, ids, got, again):
                 same_results(res, res2)
-                check_against_oracle(res, atoms, win, TOL["bf16x3"])
-                single, _ = ctx.fmap(aid, win, "bf16x3")
+                check_against_oracle(res, atoms, win, TOL[prec])
+                single, _ = ctx.fmap(aid, win, prec)
                 same_results(res, single)
     finally:
         for aid in ids:

@@ -4,7 +4,8 @@ against the FP64 CPU oracle (tolerances in checks.py).
   * Uneven batch: the 64 follow-up candidates (slots log-uniform in
     [500, 8000], gaps U[0, 0.3], grids U{100..1500}^2, 1-16 bins, rect and
     exp alternating) in the benchmark's autotuned launch configuration.
-    Batches in FP32 and in BF16X3 (matrix cores for maps of 4 or more bins).
+    Batches in FP32, F16X3 and BF16X3 (matrix cores for maps of 4 or more
+    bins).
     Every map's per-bin results (max 2F, argmax, logB) are compared with the
     oracle's full map, and every cell of the single-map path's 2F map
     (bit-identical results, see test_gpu_batch) with the oracle's cells.
@@ -12,7 +13,7 @@ against the FP64 CPU oracle (tolerances in checks.py).
   * Served stream: 106 requests of the serving workload's distribution
     (Poisson 200/s for 0.6 s; slots log-uniform [200, 10000], grids up to
     2000^2, 1-64 bins, window type random), submitted at their arrival
-    times, even ones in FP32 and odd ones in BF16X3.  Each served result
+    times in FP32, F16X3 and BF16X3 in turn.  Each served result
     equals tfstat_fmap alone (bitwise); the 40
     requests of least oracle work are compared with the oracle's full map;
     the other 66 (the 10 largest among them) on sampled cells plus every
@@ -40,7 +41,7 @@ def _same(a, b):
         assert (x["max2F"], x["logB"], x["m"], x["n"]) == (y["max2F"], y["logB"], y["m"], y["n"]), (x, y)
 
 
-PRECS = ("fp32", "bf16x3")
+PRECS = ("fp32", "f16x3", "bf16x3")
 
 
 @pytest.fixture(scope="module")
@@ -107,8 +108,8 @@ def test_served_stream_against_alone_and_oracle():
             ids.append(c.upload_atoms(atoms))
             wins.append(win)
             nbs.append(atoms.n_bins)
-        # even requests in FP32, odd ones in BF16X3 (each fused with its kind)
-        precs = ["fp32" if k % 2 == 0 else "bf16x3" for k in range(len(reqs))]
+        # requests in FP32, F16X3 and BF16X3 in turn (each fused with its kind)
+        precs = [("fp32", "f16x3", "bf16x3")[k % 3] for k in range(len(reqs))]
         c.serve_config(16)
         served = {}
         pending = {}

@@ -10,6 +10,8 @@ Tolerances (floating point):
     (1 - 1e-4) * max 2F_oracle.
   * degenerate cells (2F = 0 in the oracle) are exactly 0 on the GPU.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -352,7 +354,7 @@ def exp256_oracle():
     return atoms, win, ref
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "f16x3", "bf16x3"])
 def test_full_exp_256_bins_every_cell(ctx, exp256_oracle, prec):
     """256 bins sharing antenna atoms, 2000 slots, 500 x 500 grid: every cell
     of every bin against the oracle's full map at the 2F tolerance, and the
@@ -369,12 +371,13 @@ def test_full_exp_256_bins_every_cell(ctx, exp256_oracle, prec):
     print("full exp 256 bins %s: max rel err %.3e over %d cells" % (prec, err, ref.size), flush=True)
 
 
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 @pytest.mark.parametrize("case", ["offset", "tail", "sparse_rows"])
-def test_bf16x3_ragged(ctx, case):
+def test_matrix_ragged(ctx, case, prec):
     """Matrix-core path: 21 bins (ragged bin tile), rows off the slot grid by
-    a common offset, a partial row tile, bands past the data end; sparse rows
-    fall back to the FP32 path."""
-    _case("bf16x3 " + case)
+    a common offset, a partial row tile, bands past the data end, rows three
+    slots apart."""
+    _case("%s %s" % (prec, case))
     atoms = tfsynth.make_atoms(3, 777, 0.1, n_bins=21,
                                injections=[tfsynth.Injection(4, "exp", 90 * T, 50 * T, 0.8)])
     if case == "offset":
@@ -383,8 +386,8 @@ def test_bf16x3_ragged(ctx, case):
         win = tfsynth.regular_window("exp", 700 * T, T, 77, 2 * T, 40 * T, 9)
     else:
         win = tfsynth.regular_window("exp", 0, 3 * T, 90, 2 * T, 5 * T, 30)
-    _, _, err = run_and_check(ctx, atoms, win, "bf16x3")
-    print("bf16x3 %s: max rel err %.3e" % (case, err), flush=True)
+    _, _, err = run_and_check(ctx, atoms, win, prec)
+    print("%s %s: max rel err %.3e" % (prec, case, err), flush=True)
 
 
 def _kernel_launches(ctx, fn):
@@ -397,20 +400,32 @@ def _kernel_launches(ctx, fn):
     return out, ctx.profile_read()
 
 
+@pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 @pytest.mark.parametrize("case", ["linspace", "stride7", "before_after", "bins5", "bins37", "bins3_valu",
-                                  "one_row_tile", "long_and_short"])
-def test_bf16x3_any_grid(ctx, case):
+                                  "one_row_tile", "long_and_short", "scaled"])
+def test_matrix_any_grid(ctx, case, prec):
     """Matrix cores for exponential windows on any t0 grid (weights computed
     per row): linspace rows with their own offsets, rows 7 slots apart, rows
     before and after the data, ragged bin counts (partial 16-bin column
     tiles), a map of fewer than 4 bins (FP32 path), a single partial row
-    tile, and tau blocks with short bands (FP32 F-only tiles) beside long
-    ones.  Every cell and the per-bin results against the oracle."""
-    _case("bf16x3 any grid " + case)
+    tile, tau blocks with short bands (FP32 F-only tiles) beside long ones,
+    and data far outside the half-precision range with one all-zero bin
+    (the half-precision path's column scaling).
+    Every cell and the per-bin results against the oracle."""
+    _case("%s any grid %s" % (prec, case))
     n_bins = {"bins5": 5, "bins37": 37, "bins3_valu": 3}.get(case, 24)
     atoms = tfsynth.make_atoms(811, 1400, 0.12, n_bins=n_bins,
                                injections=[tfsynth.Injection(min(4, n_bins - 1), "exp", 300 * T, 60 * T, 1.0)])
-    if case in ("linspace", "bins5", "bins37", "bins3_valu"):
+    if case == "scaled":
+        # F is unchanged when F_a, F_b scale by s and a^2, b^2, ab by s^2:
+        # s = 2^20 puts the data far beyond the half-precision range; bin 7
+        # holds no data at all (2F = 0 everywhere)
+        fa, fb = atoms.fa * 2.0 ** 20, atoms.fb * 2.0 ** 20
+        fa[7] = 0.0
+        fb[7] = 0.0
+        atoms = dataclasses.replace(atoms, fa=fa, fb=fb, a2=atoms.a2 * 2.0 ** 40, b2=atoms.b2 * 2.0 ** 40,
+                                    ab=atoms.ab * 2.0 ** 40)
+    if case in ("linspace", "bins5", "bins37", "bins3_valu", "scaled"):
         win = tfsynth.linspace_grid(atoms, "exp", 260, 110)
     elif case == "stride7":
         win = tfsynth.regular_window("exp", 333, 7 * T, 150, 2 * T, 5 * T + 17, 70)
@@ -423,17 +438,54 @@ def test_bf16x3_any_grid(ctx, case):
         win = tfsynth.list_window("exp", 5 + np.arange(0, 1300, 9) * T, tau)
     aid = ctx.upload_atoms(atoms)
     try:
-        (res, twoF), prof = _kernel_launches(ctx, lambda: ctx.fmap(aid, win, "bf16x3", want_map=True))
+        (res, twoF), prof = _kernel_launches(ctx, lambda: ctx.fmap(aid, win, prec, want_map=True))
         ref = oracle.fmap_atoms(atoms, win)
-        err = check_map(twoF.cpu().numpy(), ref, TOL["bf16x3"])
-        check_results(res, ref, win, TOL["bf16x3"])
+        err = check_map(twoF.cpu().numpy(), ref, TOL[prec])
+        check_results(res, ref, win, TOL[prec])
         assert (prof["mfma"][0] > 0) == (case != "bins3_valu"), prof["mfma"]
         # the same map again: bitwise repeatable
-        res2, _ = ctx.fmap(aid, win, "bf16x3")
+        res2, _ = ctx.fmap(aid, win, prec)
         assert res2 == res
     finally:
         ctx.free(aid)
-    print("bf16x3 %s: max rel err %.3e" % (case, err), flush=True)
+    print("%s %s: max rel err %.3e" % (prec, case, err), flush=True)
+
+
+def test_f16x3_bin_scales(ctx):
+    """Half-precision parts with each bin's data scaled by its own power of
+    two (2^-40 .. 2^40, beyond both ends of the half-precision range) and a
+    non-power-of-two scale on one bin: every cell's 2F against the oracle of
+    the scaled atoms (2F grows with the square of the scale, so the logB of
+    such bins is compared through max 2F and argmax only)."""
+    _case("f16x3 bin scales")
+    n_bins = 18
+    atoms = tfsynth.make_atoms(813, 900, 0.1, n_bins=n_bins)
+    k = np.linspace(-40, 40, n_bins).round().astype(int)
+    scale = np.ldexp(1.0, k)
+    scale[5] = 3.0e-3
+    fa = (atoms.fa * scale[:, None, None]).astype(np.float32).astype(np.float64)
+    fb = (atoms.fb * scale[:, None, None]).astype(np.float32).astype(np.float64)
+    atoms = dataclasses.replace(atoms, fa=fa, fb=fb)
+    win = tfsynth.linspace_grid(atoms, "exp", 130, 70)
+    aid = ctx.upload_atoms(atoms)
+    try:
+        res, twoF = ctx.fmap(aid, win, "f16x3", want_map=True)
+    finally:
+        ctx.free(aid)
+    ref = oracle.fmap_atoms(atoms, win)
+    got = twoF.cpu().numpy().astype(np.float64)
+    mx, am, _ = oracle.reduce(ref)
+    worst = 0.0
+    for b in range(n_bins):
+        # relative to the bin's own largest 2F (the floor of 1 would hide
+        # the tiny bins)
+        e = np.abs(got[b] - ref[b]).max() / mx[b]
+        worst = max(worst, e)
+        assert e <= TOL["f16x3"], (b, e)
+        assert abs(res[b]["max2F"] - mx[b]) <= TOL["f16x3"] * mx[b], (b, res[b]["max2F"], mx[b])
+        idx = res[b]["m"] * win.n_tau + res[b]["n"]
+        assert idx == am[b] or ref[b].ravel()[idx] >= (1 - 1e-4) * mx[b], (b, idx, am[b])
+    print("f16x3 bin scales: max err relative to each bin's max 2F %.3e" % worst, flush=True)
 
 
 @pytest.mark.parametrize("case", ["stride1", "stride3_delta", "past_end", "before_data", "bins5",
@@ -530,7 +582,8 @@ def test_deterministic_repeat(ctx):
 # Serving: results alone and in a concurrent mix are identical
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("max_batch,precs", [(16, ("fp32",)), (1, ("fp32",)), (5, ("fp32", "fp64", "bf16x3"))])
+@pytest.mark.parametrize("max_batch,precs", [(16, ("fp32",)), (1, ("fp32",)),
+                                             (5, ("fp32", "fp64", "bf16x3", "f16x3"))])
 def test_submit_poll_mix_invariance(ctx, max_batch, precs):
     """Twelve uneven requests in flight at once give exactly the results of
     each alone: batched admission (up to 16 or 5 fused), one request per
@@ -633,12 +686,12 @@ def _bump_window(base):
     return tfsynth.shape_window(base, x * np.exp(1.0 - x), (4, 1))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16x3", "f16x3"])
 def test_shape_window_against_oracle(ctx, prec):
     """t0 100 s after each SFT start (one common offset), ragged taus, bins
     spanning a partial 16-bin column tile for the matrix-core path."""
     _case("shape window " + prec)
-    n_bins = 19 if prec == "bf16x3" else 3
+    n_bins = 19 if prec in ("bf16x3", "f16x3") else 3
     atoms = tfsynth.make_atoms(501, 420, 0.1, n_bins=n_bins,
                                injections=[tfsynth.Injection(1, "exp", 60 * T, 20 * T, 1.0)])
     rng = np.random.default_rng(7)
@@ -681,5 +734,32 @@ def test_shape_window_errors(ctx):
         with pytest.raises(tf.TfstatError) as e:
             ctx.fmap(aid, bad, "fp32")
         assert e.value.code == tf._abi.E_INVAL
+    finally:
+        ctx.free(aid)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_window_odds_against_oracle(ctx, prec):
+    """Rect against exp on the same atoms (section 5: window models compared
+    through their Bayes factors): per-bin log odds logB_exp - logB_rect
+    against the oracle's two logB values, within the sum of the two logB
+    tolerances; different grids for the two models; bin 1 holds a loud
+    exponential transient, which the exponential model must favour."""
+    from checks import LOGB_TOL
+    _case("window odds " + prec)
+    atoms = tfsynth.make_atoms(511, 600, 0.1, n_bins=3,
+                               injections=[tfsynth.Injection(1, "exp", 100 * T, 40 * T, 3.0)])
+    w_exp = tfsynth.regular_window("exp", 0, 2 * T, 250, 2 * T, 3 * T, 120)
+    w_rect = tfsynth.regular_window("rect", 0, T, 480, 2 * T, 5 * T, 110)
+    aid = ctx.upload_atoms(atoms)
+    try:
+        got = ctx.window_odds(aid, w_exp, w_rect, prec)
+        _, _, lb_e = oracle.reduce(oracle.fmap_atoms(atoms, w_exp))
+        _, _, lb_r = oracle.reduce(oracle.fmap_atoms(atoms, w_rect))
+        ref = lb_e - lb_r
+        assert np.all(np.abs(got - ref) <= 2 * LOGB_TOL), (got, ref)
+        assert ref[1] > 0.0 and got[1] > 0.0, (got, ref)
+        back = ctx.window_odds(aid, w_rect, w_exp, prec)
+        assert np.array_equal(back, -got)
     finally:
         ctx.free(aid)
