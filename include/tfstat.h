@@ -226,6 +226,29 @@ int tfstat_logB(tfstat_ctx *ctx, const float *twoF_dev, int32_t n_maps,
                 int32_t n_t0, int32_t n_tau, double *logB_host);
 
 /*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid device or pinned-host
+ * allocation): tfstat_logB without any allocation.  Same kernels and the
+ * same results, bit for bit, as tfstat_logB on the same maps.
+ *   twoF_dev  device, float [n_maps][n_t0][n_tau] (read only);
+ *   logB_dev  device, double [n_maps] (written).
+ * The per-tile partials and per-map results live in one static device
+ * array per GPU of TFSTAT_NOALLOC_SCRATCH_BYTES bytes, held until the
+ * process ends; a call needs 24 * n_maps * ceil(n_t0 n_tau / 16384) bytes
+ * (rounded up to 256) plus 24 * n_maps, and larger calls fail with E_INVAL.
+ * The call is asynchronous on the context's stream (no host
+ * synchronisation; the result is ready when the stream reaches it).  Every
+ * call on one GPU shares that GPU's array: calls that may overlap on one
+ * GPU (other streams, other contexts, other threads) race and must be
+ * ordered by the caller.
+ * Errors: E_INVAL (null pointer, sizes < 1, workspace above the limit),
+ * E_DEVICE.
+ */
+#define TFSTAT_NOALLOC_SCRATCH_BYTES (4u << 20)
+int tfstat_logB_noalloc(tfstat_ctx *ctx, const float *twoF_dev, int32_t n_maps,
+                        int32_t n_t0, int32_t n_tau, double *logB_dev);
+
+/*
  * A-posteriori comparison of two window models on the same atoms (section 5:
  * different window functions are compared through their Bayes factors).
  * Computes both maps like tfstat_fmap (no map is materialised) and writes,

@@ -193,6 +193,20 @@ class Context:
                                          int(t.shape[1]), int(t.shape[2]), out.ctypes.data))
         return out
 
+    def logB_noalloc(self, twoF, out):
+        """tfstat_logB_noalloc: logB of each map of a float32 CUDA tensor
+        [n_maps, n_t0, n_tau] into `out`, a float64 CUDA tensor [n_maps],
+        asynchronously on the context's stream and without any allocation."""
+        t = twoF if twoF.dim() == 3 else twoF[None]
+        if t.dtype != self._torch.float32 or not t.is_contiguous():
+            raise ValueError("twoF must be a contiguous float32 tensor")
+        if out.dtype != self._torch.float64 or not out.is_contiguous() or out.numel() != t.shape[0]:
+            raise ValueError("out must be a contiguous float64 tensor of n_maps values")
+        _abi.check(self._lib.tfstat_logB_noalloc(self._ctx, ctypes.c_void_p(t.data_ptr()), int(t.shape[0]),
+                                                 int(t.shape[1]), int(t.shape[2]),
+                                                 ctypes.c_void_p(out.data_ptr())))
+        return out
+
     # -- serving -------------------------------------------------------------------
     def submit(self, atoms_id: int, win, precision="fp32") -> int:
         wa = _WindowArgs.from_window(win)

@@ -101,6 +101,7 @@ SIGNATURES = {
     "tfstat_fmap": (ctypes.c_int, [_P, _U64, ctypes.POINTER(Window), _I32, _P,
                                    ctypes.POINTER(BinResult)]),
     "tfstat_logB": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P]),
+    "tfstat_logB_noalloc": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P]),
     "tfstat_window_odds": (ctypes.c_int, [_P, _U64, ctypes.POINTER(Window), ctypes.POINTER(Window), _I32,
                                           _P]),
     "tfstat_submit": (ctypes.c_int, [_P, _U64, ctypes.POINTER(Window), _I32, ctypes.POINTER(_U64)]),

@@ -1268,6 +1268,7 @@ __device__ __attribute__((always_inline)) inline void merge_map(PP &p, int map,
         o.logB = t.f + log(t.s) - log((double)p.n_cells);
         o.idx = t.i;
         p.out[map] = o;
+        if (p.logB_out) p.logB_out[map] = o.logB;
     }
 }
 

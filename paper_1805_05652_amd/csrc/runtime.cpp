@@ -1764,6 +1764,7 @@ int tfstat_ctx_create(int device, void *arena_dev, size_t arena_bytes, void *hip
         auto ctx = std::make_unique<tfstat_ctx>();
         ctx->device = device;
         ctx->stream = static_cast<hipStream_t>(hip_stream);
+        hip_check(tfs::noalloc_setup(device), "allocation-free workspace address");
         ctx->arena.init(arena_dev, arena_bytes);
         *out = ctx.release();
         return (int)TFSTAT_OK;
@@ -2020,6 +2021,45 @@ int tfstat_window_odds(tfstat_ctx *ctx, tfstat_atoms_id id, const tfstat_window 
         rc = tfstat_fmap(ctx, id, win_b, precision, nullptr, rb.data());
         if (rc != TFSTAT_OK) return rc;
         for (int32_t b = 0; b < n_bins; ++b) log_odds_host[b] = ra[b].logB - rb[b].logB;
+        return (int)TFSTAT_OK;
+    });
+}
+
+int tfstat_logB_noalloc(tfstat_ctx *ctx, const float *twoF_dev, int32_t n_maps, int32_t n_t0,
+                        int32_t n_tau, double *logB_dev) {
+    return guarded([&] {
+        if (!ctx || !twoF_dev || !logB_dev) raise(TFSTAT_E_INVAL, "null argument");
+        if (n_maps < 1 || n_t0 < 1 || n_tau < 1) raise(TFSTAT_E_INVAL, "sizes must be >= 1");
+        if (n_maps > 65535) raise(TFSTAT_E_INVAL, "n_maps must be <= 65535");
+        const int64_t cells = (int64_t)n_t0 * n_tau;
+        const int64_t cpt = 16384;
+        if ((cells + cpt - 1) / cpt > 65535) raise(TFSTAT_E_INVAL, "maps of more than 2^30 cells");
+        const int32_t n_tiles = (int32_t)((cells + cpt - 1) / cpt);
+        const size_t part_b = round_up(sizeof(tfs::Partial) * (size_t)n_tiles * n_maps, 256);
+        const size_t res_b = sizeof(tfs::BinResultDev) * n_maps;
+        if (part_b + res_b > (size_t)TFSTAT_NOALLOC_SCRATCH_BYTES)
+            raise(TFSTAT_E_INVAL, "tfstat_logB_noalloc needs " + std::to_string(part_b + res_b) +
+                                      " bytes of workspace; its static workspace holds " +
+                                      std::to_string((size_t)TFSTAT_NOALLOC_SCRATCH_BYTES));
+        hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+        char *ws = static_cast<char *>(tfs::noalloc_scratch(ctx->device));
+        if (!ws) raise(TFSTAT_E_DEVICE, "allocation-free workspace not set up on this device");
+        tfs::MapReduceParams rp{};
+        rp.twoF = twoF_dev;
+        rp.n_cells = cells;
+        rp.n_maps = n_maps;
+        rp.n_tiles = n_tiles;
+        rp.cells_per_tile = cpt;
+        rp.part = reinterpret_cast<tfs::Partial *>(ws);
+        hip_check(tfs::launch_map_reduce(rp, ctx->stream), "map reduce kernel");
+        tfs::MergeParams mp{};
+        mp.n_tiles = n_tiles;
+        mp.n_maps = n_maps;
+        mp.n_cells = cells;
+        mp.part = rp.part;
+        mp.out = reinterpret_cast<tfs::BinResultDev *>(ws + part_b);
+        mp.logB_out = logB_dev;
+        hip_check(tfs::launch_merge(mp, ctx->stream), "merge kernel");
         return (int)TFSTAT_OK;
     });
 }

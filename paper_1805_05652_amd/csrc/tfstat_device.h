@@ -215,6 +215,7 @@ struct MergeParams {
     int64_t n_cells;
     const Partial *part;      // [n_maps][n_tiles]
     BinResultDev *out;        // [n_maps]
+    double *logB_out;         // optional [n_maps]: logB again, as a plain array
 };
 
 // ---------------------------------------------------------------------------
@@ -369,6 +370,10 @@ hipError_t launch_scan(const double *in, int64_t in_row_stride, double *out,
 hipError_t launch_rect(const RectParams &p, hipStream_t s);
 hipError_t launch_merge(const MergeParams &p, hipStream_t s);
 hipError_t launch_map_reduce(const MapReduceParams &p, hipStream_t s);
+// Device address of this GPU's allocation-free workspace (noalloc.hip):
+// looked up once per device with that device current, null before.
+hipError_t noalloc_setup(int device);
+void *noalloc_scratch(int device);
 hipError_t launch_weights_batch(const WeightBatchParams &p, hipStream_t s);
 hipError_t launch_abc_batch(const AbcBatchParams &p, hipStream_t s);
 hipError_t launch_scan_batch(const ScanJob *jobs, int32_t n_jobs, hipStream_t s);
