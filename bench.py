@@ -211,7 +211,7 @@ def _percentiles(lat_ms):
 
 
 def serving(ctx, seed: int = 4000, rate_hz: float = 200.0, duration_s: float = 15.0,
-            precision: str = "fp32", pool: int = 400, ramp=(250.0, 300.0, 350.0, 400.0),
+            precision: str = "f16x3", pool: int = 400, ramp=(300.0, 500.0, 700.0, 900.0, 1100.0, 1300.0),
             ramp_s: float = 4.0):
     """Served maps: a Poisson stream of map requests over resident atoms.
 
@@ -378,7 +378,8 @@ def roofline_for(atoms, win, prec, prof, workload):
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = traffic_from_profile(workload, {"exp": "exp_valu", "rect": "rect",
-                                                      "mfma": "exp_mfma", "recur": "exp_recur"}[dom])
+                                                      "mfma": "exp_mfma", "recur": "exp_recur"}[dom],
+                                           prec if mfma else None)
     roof["kernel"] = dom
     roof["kernel_avg_ms"] = avg_ms
     return roof
@@ -512,7 +513,7 @@ def bench_batch(args, tf, torch, prec):
     flops = 8.0 * valu_present + 6.0 * abc_cells_sfts + 30.0 * rect_cells
     roof_f = {"bound": "alu", "achieved": flops / (fused_ms * 1e-3) / 1e12, "peak": PEAK_ALU_TFLOPS,
               "unit": "TFLOP/s", "kernel": "fused", "kernel_avg_ms": fused_ms,
-              "traffic": traffic_from_profile("batch", "fused", st["variant"]) if prec == "fp32" else None}
+              "traffic": traffic_from_profile("batch_" + prec, "fused", st["variant"])}
     roof_f["frac"] = roof_f["achieved"] / roof_f["peak"]
     roof = roof_f
     out = {
@@ -532,7 +533,8 @@ def bench_batch(args, tf, torch, prec):
         # the matrix-core launch: 24 matrix-core flops per cell*SFT*bin it sums
         roof_m = {"bound": "mfma", "achieved": 24.0 * mfma_present / (mfma_ms * 1e-3) / 1e12,
                   "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "kernel": "mfma_batch",
-                  "kernel_avg_ms": mfma_ms, "cells_sfts_bins": mfma_present, "traffic": None}
+                  "kernel_avg_ms": mfma_ms, "cells_sfts_bins": mfma_present,
+                  "traffic": traffic_from_profile("batch_" + prec, "mfma_batch", prec)}
         roof_m["frac"] = roof_m["achieved"] / roof_m["peak"]
         out["roofline_fused"] = roof_f
         out["roofline_mfma"] = roof_m
