@@ -10,7 +10,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _CSRC = os.path.join(_HERE, "csrc")
 LIB_NAME = "libtfstat.so"
 
-SOURCES = ["kernels.hip", "kernels_mfma.hip", "kernels_recur.hip", "noalloc.hip", "runtime.cpp"]
+SOURCES = ["kernels.hip", "kernels_mfma.hip", "kernels_recur.hip", "kernels_abc.hip", "noalloc.hip", "runtime.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

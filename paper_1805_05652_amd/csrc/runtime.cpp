@@ -780,6 +780,37 @@ tfs::ExpMfmaRowsParams mfma_rows_params(Job &j, const int32_t *blk_list) {
     return q;
 }
 
+// Rows per lane segment of the A/B/C recurrence.  Each segment starts with
+// one direct window sum and then takes one short dependent step per row, so
+// a lane's time is its chain of round trips to the caches: more segments
+// mean shorter chains and more lanes (and repeated direct sums).  A map
+// takes about 16 K lanes (taus x segments), which leaves the chip room
+// for several maps at once, with at least 8 rows per segment.
+int32_t abc_seg_rows(const Job &j) {
+    const int64_t n_t0 = (int64_t)j.win.t0.size();
+    const int64_t n_tau = std::max<int64_t>(1, (int64_t)j.win.tau.size());
+    const int64_t n_seg = std::max<int64_t>(1, std::min<int64_t>(16384 / n_tau, (n_t0 + 7) / 8));
+    return (int32_t)((n_t0 + n_seg - 1) / n_seg);
+}
+
+// A/B/C of every cell of an exponential-window map by the recurrence over
+// t0 rows, into the map's abc_cell buffer (shape windows take the VALU
+// A/B/C pass: their weights are not exponential).
+tfs::AbcRecurParams abc_recur_params(Job &j) {
+    tfs::AbcRecurParams q{};
+    q.rows = ws_ptr<tfs::RowPlan>(j, j.off_rows);
+    q.tau = ws_ptr<int64_t>(j, j.off_tau);
+    q.abc = j.at->abc;
+    q.abc_out = ws_ptr<double>(j, j.off_abc);
+    q.abc_pitch = abc_pitch((int32_t)j.win.tau.size());
+    q.n_t0 = (int32_t)j.win.t0.size();
+    q.n_tau = (int32_t)j.win.tau.size();
+    q.K = j.at->K;
+    q.t_sft = j.at->t_sft;
+    q.seg_rows = abc_seg_rows(j);
+    return q;
+}
+
 tfs::RectParams rect_params(Job &j) {
     tfs::RectParams p{};
     p.K = j.at->K;
@@ -912,7 +943,10 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
             tfs::ExpValuParams pa = p;
             pa.twoF = nullptr;
             record_kernel(ctx, j, TFSTAT_K_ABC, s, true);
-            hip_check(tfs::launch_exp_abc(pa, s), "exp abc kernel");
+            if (j.win.type == TFSTAT_WIN_EXP)
+                hip_check(tfs::launch_abc_recur(abc_recur_params(j), s), "abc recurrence kernel");
+            else
+                hip_check(tfs::launch_exp_abc(pa, s), "exp abc kernel");
             record_kernel(ctx, j, TFSTAT_K_ABC, s, false);
             record_kernel(ctx, j, TFSTAT_K_EXP, s, true);
             hip_check(tfs::launch_exp_fonly(p, j.n_groups, s), "exp F kernel");
@@ -938,7 +972,10 @@ void enqueue_job(tfstat_ctx *ctx, Job &j, hipStream_t s) {
             pa.abc_out = ws_ptr<double>(j, j.off_abc);
             pa.abc_pitch = abc_pitch(n_tau);
             record_kernel(ctx, j, TFSTAT_K_ABC, s, true);
-            hip_check(tfs::launch_exp_abc(pa, s), "exp abc kernel");
+            if (j.win.type == TFSTAT_WIN_EXP)
+                hip_check(tfs::launch_abc_recur(abc_recur_params(j), s), "abc recurrence kernel");
+            else
+                hip_check(tfs::launch_exp_abc(pa, s), "exp abc kernel");
             record_kernel(ctx, j, TFSTAT_K_ABC, s, false);
             pa.blk_list = p.blk_list + j.n_valu;   // the matrix-core blocks
             pa.n_list = j.n_mfma;
@@ -1083,7 +1120,8 @@ struct tfstat_batch {
     int n_scan = 0;
     tfs::MergeBatchParams mbp{};
     tfs::AbcBatchParams abp{};       // A/B/C pre-pass of the split-form and matrix-core maps
-    tfs::MfmaBatchParams mfp{};      // matrix-core work of the BF16X3 maps
+    tfs::MfmaBatchParams mfp{};      // matrix-core work of the BF16X3 / F16X3 maps
+    tfs::AbcRecurBatchParams rap{};  // recurrence A/B/C of exponential split and matrix-core maps
     tfs::BinResultDev *res_dev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1143,7 +1181,9 @@ int job_shape(const Job &j) {
 bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bool have_lock) {
     const int32_t n = (int32_t)b->jobs.size();
     std::vector<int> shape(n, -1), eidx(n, -1), ridx(n, -1), midx(n, -1);
-    int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0, n_abc = 0, n_mfma_maps = 0;
+    int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0, n_abc = 0, n_mfma_maps = 0, n_rabc_maps = 0;
+    size_t n_rabc = 0;   // recurrence A/B/C entries (exponential windows)
+    std::vector<int> aidx(n, -1);
     size_t n_mfma_entries = 0;
     int32_t max_chunks = 1;
     b->res_off.assign(n, 0);
@@ -1156,10 +1196,23 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             shape[i] = job_shape(j);
             eidx[i] = n_exp++;
             n_went += j.NB;
-            if (j.split) n_abc += j.n_valu * j.n_row_tiles;
+            // A/B/C of every cell of split and matrix-core maps: the
+            // recurrence for exponential windows, the VALU pass (every
+            // block) for shape windows
+            if (j.split || j.use_mfma) {
+                if (j.win.type == TFSTAT_WIN_EXP) {
+                    aidx[i] = n_rabc_maps++;
+                    tfs::AbcRecurParams q{};
+                    q.n_t0 = (int32_t)j.win.t0.size();
+                    q.n_tau = (int32_t)j.win.tau.size();
+                    q.seg_rows = abc_seg_rows(j);
+                    n_rabc += (size_t)tfs::abc_recur_blocks(q);
+                } else {
+                    n_abc += (j.n_valu + j.n_mfma) * j.n_row_tiles;
+                }
+            }
             if (j.use_mfma) {
-                // A/B/C of every block; matrix-core work of the long-band blocks
-                n_abc += (j.n_valu + j.n_mfma) * j.n_row_tiles;
+                // matrix-core work of the long-band blocks
                 midx[i] = n_mfma_maps++;
                 n_mfma_entries += (size_t)j.n_mfma * j.n_row_tiles * (j.at->bins16 / 16);
             }
@@ -1201,7 +1254,8 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             n_tiles_total += (size_t)ny * j.n_tiles_n * ((j.at->n_bins + tfs::kRectBins - 1) / tfs::kRectBins);
         }
     }
-    if (n_tiles_total > (size_t)INT32_MAX / 2 || n_mfma_entries > (size_t)INT32_MAX / 2)
+    if (n_tiles_total > (size_t)INT32_MAX / 2 || n_mfma_entries > (size_t)INT32_MAX / 2 ||
+        n_rabc > (size_t)INT32_MAX / 2)
         raise(TFSTAT_E_INVAL, "batch has too many tiles");
     std::stable_sort(groups_e.begin(), groups_e.end(),
                      [](const Group &a, const Group &c) { return a.cost > c.cost; });
@@ -1260,6 +1314,8 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     const size_t off_ay = take(sizeof(int32_t) * n_abc);
     const size_t off_mfp = take(sizeof(tfs::ExpMfmaRowsParams) * n_mfma_maps);
     const size_t off_ment = take(sizeof(int32_t) * 4 * n_mfma_entries);
+    const size_t off_rap = take(sizeof(tfs::AbcRecurParams) * n_rabc_maps);
+    const size_t off_rent = take(sizeof(int32_t) * 2 * n_rabc);
     const size_t desc_end = o;
     const size_t off_counter = take(sizeof(int32_t));
     const size_t off_res = take(sizeof(tfs::BinResultDev) * b->n_results);
@@ -1299,6 +1355,9 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     auto *ay = reinterpret_cast<int32_t *>(hptr(off_ay));
     auto *mfp = reinterpret_cast<tfs::ExpMfmaRowsParams *>(hptr(off_mfp));
     auto *ment = reinterpret_cast<int32_t *>(hptr(off_ment));
+    auto *rap = reinterpret_cast<tfs::AbcRecurParams *>(hptr(off_rap));
+    auto *rent = reinterpret_cast<int32_t *>(hptr(off_rent));
+    size_t re = 0;
     int we = 0, se = 0, me = 0, ae = 0;
     size_t mfe = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -1311,7 +1370,15 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
                 wblk[we] = nb;
                 ++we;
             }
-            if (j.split || j.use_mfma) {
+            if (aidx[i] >= 0) {
+                rap[aidx[i]] = abc_recur_params(j);
+                const int64_t nb = tfs::abc_recur_blocks(rap[aidx[i]]);
+                for (int64_t bk = 0; bk < nb; ++bk) {
+                    rent[2 * re + 0] = aidx[i];
+                    rent[2 * re + 1] = (int32_t)bk;
+                    ++re;
+                }
+            } else if (j.split || j.use_mfma) {
                 // longest bands first, as in the tile list (matrix-core maps:
                 // every block, the matrix-core ones included)
                 for (int q = 0; q < j.n_valu + j.n_mfma; ++q)
@@ -1372,6 +1439,9 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     b->abp.x = reinterpret_cast<const int32_t *>(dptr(off_ax));
     b->abp.y = reinterpret_cast<const int32_t *>(dptr(off_ay));
     b->abp.n_entries = n_abc;
+    b->rap.jobs = reinterpret_cast<const tfs::AbcRecurParams *>(dptr(off_rap));
+    b->rap.entries = reinterpret_cast<const int32_t *>(dptr(off_rent));
+    b->rap.n_entries = (int32_t)n_rabc;
     b->mfp.jobs = reinterpret_cast<const tfs::ExpMfmaRowsParams *>(dptr(off_mfp));
     b->mfp.entries = reinterpret_cast<const int32_t *>(dptr(off_ment));
     b->mfp.n_entries = (int32_t)mfe;
@@ -1444,6 +1514,7 @@ hipError_t batch_enqueue(tfstat_batch *b, hipStream_t s, bool timed) {
     if (e == hipSuccess) e = tfs::launch_weights_batch(b->wbp, s);
     if (e == hipSuccess) e = tfs::launch_scan_batch(b->scan_jobs, b->n_scan, s);
     if (e == hipSuccess) e = tfs::launch_abc_batch(b->abp, s);
+    if (e == hipSuccess) e = tfs::launch_abc_recur_batch(b->rap, s);
     if (e == hipSuccess && timed) e = hipEventRecord(b->evf0, s);
     if (e == hipSuccess) e = tfs::launch_fused(b->fp, b->variant, b->groups, s);
     if (e == hipSuccess && timed) e = hipEventRecord(b->evf1, s);

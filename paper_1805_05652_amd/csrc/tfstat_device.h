@@ -276,6 +276,35 @@ struct AbcBatchParams {
     int32_t pad;
 };
 
+// A, B, C of every cell of an exponential-window map by the recurrence
+// over t0 rows (kernels_abc.hip): lanes (tau, segment of seg_rows rows).
+struct AbcRecurParams {
+    const RowPlan *rows;      // [n_t0], ascending t0
+    const int64_t *tau;       // [n_tau]
+    const double *abc;        // resident antenna atoms [K+1][4] (a^2, b^2, ab, 0)
+    double *abc_out;          // [n_t0][abc_pitch][3] (scaled, exact band)
+    int32_t abc_pitch;
+    int32_t n_t0, n_tau;
+    int32_t K;
+    int64_t t_sft;
+    int32_t seg_rows;
+    int32_t pad;
+};
+
+// Many maps: entry e = {map, block of 256 lanes of that map}.
+struct AbcRecurBatchParams {
+    const AbcRecurParams *jobs;
+    const int32_t *entries;   // [n_entries][2]
+    int32_t n_entries;
+    int32_t pad;
+};
+
+// Workgroups of 256 lanes that cover a map's (tau, segment) lanes.
+inline int64_t abc_recur_blocks(const AbcRecurParams &p) {
+    const int64_t n_seg = (p.n_t0 + p.seg_rows - 1) / p.seg_rows;
+    return ((int64_t)(p.n_tau + 63) / 64 * 64 * n_seg + 255) / 256;
+}
+
 // Weight tables of many maps: entry i is block blk[i] of job job[i].
 struct WeightBatchParams {
     const WeightParams *jobs;
@@ -370,6 +399,8 @@ hipError_t launch_scan(const double *in, int64_t in_row_stride, double *out,
 hipError_t launch_rect(const RectParams &p, hipStream_t s);
 hipError_t launch_merge(const MergeParams &p, hipStream_t s);
 hipError_t launch_map_reduce(const MapReduceParams &p, hipStream_t s);
+hipError_t launch_abc_recur(const AbcRecurParams &p, hipStream_t s);
+hipError_t launch_abc_recur_batch(const AbcRecurBatchParams &p, hipStream_t s);
 // Device address of this GPU's allocation-free workspace (noalloc.hip):
 // looked up once per device with that device current, null before.
 hipError_t noalloc_setup(int device);
