@@ -1160,14 +1160,31 @@ __global__ __launch_bounds__(kScanWaves * 64) void scan_batch_kernel(const ScanJ
 }
 
 // ---------------------------------------------------------------------------
-// Rectangular-window cells: window sums as prefix differences, finalize,
+// Rectangular windows: window sums from compensated prefixes, D, 2F, the
 // optional map, per-tile reduction.  Tile = kRectRows rows x 64 taus x
 // kRectBins bins: lane = tau, the waves take every fourth row; A, B, C and
 // 2 / D of a cell are formed once for its bins, and each lane keeps a
 // running (max, sum, first argmax) per bin, so the tile reduces once.
+//
+// Window ends hi = ceil((t0 - T0 + tau) / T_sft) grow with t0 and tau, so a
+// tile's ends lie between those of its first cell and its last.  When that
+// range fits kRectStage slots (tiles of a grid at about one slot per step),
+// STAGE copies the range's prefixes of the tile's bins and of the antenna
+// sums into LDS once, laid out [channel][slot] as (hi, lo) pairs so that the
+// 64 lanes' reads of consecutive slots are conflict-free 16-byte accesses;
+// the cells then read their end prefixes from LDS instead of addressing 80
+// bytes per cell and bin through the texture path.  Window starts are one
+// per row, wave-uniform, read through the scalar path either way.
 // ---------------------------------------------------------------------------
-template <typename PP>
-__device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wred)[kRectBins],
+constexpr int kRectStage = 128;                 // staged window-end slots
+constexpr int kRectStageCh = 4 * kRectBins + 3;  // data (4 per bin) and antenna channels
+
+struct RectStage {
+    double2 v[kRectStageCh][kRectStage];
+};
+
+template <bool STAGE, typename PP>
+__device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wred)[kRectBins], RectStage *st,
                                                                  int bx, int by, int bg) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1181,6 +1198,41 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wr
     const int nbg = min(kRectBins, p.n_bins - bin0);
     const size_t bin_stride = ((size_t)K + 1) * 8;   // prefixes of one bin: [K+1][8]
     const double *pxb = p.px + (size_t)bin0 * bin_stride;
+    auto window = [&](const RowPlan &rp, int64_t tau_c, int64_t &lo, int64_t &hi) {
+        const int64_t L = tau_c > rp.delta ? (tau_c - rp.delta + T - 1) / T : 0;
+        lo = min(max((int64_t)rp.k0, (int64_t)0), K);
+        hi = min(max((int64_t)rp.k0 + L, (int64_t)0), K);
+    };
+    bool staged = false;
+    int64_t s0 = 0;
+    if constexpr (STAGE) {
+        const int m_last = min(by * kRectRows + kRectRows - 1, p.n_t0 - 1);
+        const int n_last = min(bx * 64 + 63, p.n_tau - 1);
+        int64_t lo_a, hi_a, lo_b, hi_b;
+        window(p.rows[by * kRectRows], p.tau[bx * 64], lo_a, hi_a);
+        window(p.rows[m_last], p.tau[n_last], lo_b, hi_b);
+        s0 = hi_a;
+        staged = hi_b - hi_a < kRectStage;
+        if (staged) {
+            const int ns = (int)(hi_b - hi_a + 1);
+            for (int e = threadIdx.x; e < kRectStageCh * ns; e += 256) {
+                const int ch = e / ns, sl = e - ch * ns;
+                const int64_t k = s0 + sl;
+                const double *src;
+                int c;
+                if (ch < 4 * kRectBins) {
+                    const int b = ch >> 2;
+                    c = ch & 3;
+                    src = pxb + min(b, nbg - 1) * bin_stride + k * 8;
+                } else {
+                    c = ch - 4 * kRectBins;
+                    src = p.pabc + k * 8;
+                }
+                st->v[ch][sl] = double2{src[c], src[4 + c]};
+            }
+            __syncthreads();
+        }
+    }
     Red r[kRectBins];
 #pragma unroll
     for (int b = 0; b < kRectBins; ++b) r[b] = red_empty();
@@ -1189,15 +1241,24 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wr
         const int m = by * kRectRows + i * kWaves + wave;
         if (m >= p.n_t0) break;
         const RowPlan rp = p.rows[m];
-        const int64_t L = tau > rp.delta ? (tau - rp.delta + T - 1) / T : 0;
-        const int64_t lo = min(max((int64_t)rp.k0, (int64_t)0), K);
-        const int64_t hi = min(max((int64_t)rp.k0 + L, (int64_t)0), K);
+        int64_t lo, hi;
+        window(rp, tau, lo, hi);
         // window sums from compensated prefixes: (hi_h - lo_h) + (hi_l - lo_l)
-        const double *a_hi = p.pabc + hi * 8;
         const double *a_lo = p.pabc + lo * 8;
-        const double A = (a_hi[0] - a_lo[0]) + (a_hi[4] - a_lo[4]);
-        const double B = (a_hi[1] - a_lo[1]) + (a_hi[5] - a_lo[5]);
-        const double C = (a_hi[2] - a_lo[2]) + (a_hi[6] - a_lo[6]);
+        double A, B, C;
+        if (STAGE && staged) {
+            const int sl = (int)(hi - s0);
+            const double2 ha = st->v[4 * kRectBins + 0][sl], hb = st->v[4 * kRectBins + 1][sl],
+                          hc = st->v[4 * kRectBins + 2][sl];
+            A = (ha.x - a_lo[0]) + (ha.y - a_lo[4]);
+            B = (hb.x - a_lo[1]) + (hb.y - a_lo[5]);
+            C = (hc.x - a_lo[2]) + (hc.y - a_lo[6]);
+        } else {
+            const double *a_hi = p.pabc + hi * 8;
+            A = (a_hi[0] - a_lo[0]) + (a_hi[4] - a_lo[4]);
+            B = (a_hi[1] - a_lo[1]) + (a_hi[5] - a_lo[5]);
+            C = (a_hi[2] - a_lo[2]) + (a_hi[6] - a_lo[6]);
+        }
         // 2F = (2 / D) (B |F_a|^2 + A |F_b|^2 - 2 C Re(F_a F_b*)) (eq. F_FaFb);
         // a degenerate window (D <= rtol A B) gets 2F = 0
         const double D = A * B - C * C;
@@ -1207,11 +1268,20 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wr
 #pragma unroll
         for (int b = 0; b < kRectBins; ++b) {
             if (b >= nbg) break;
-            const double *x_hi = pxb + b * bin_stride + hi * 8;
             const double *x_lo = pxb + b * bin_stride + lo * 8;
             double f[4];
+            if (STAGE && staged) {
+                const int sl = (int)(hi - s0);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) f[c] = (x_hi[c] - x_lo[c]) + (x_hi[4 + c] - x_lo[4 + c]);
+                for (int c = 0; c < 4; ++c) {
+                    const double2 h = st->v[4 * b + c][sl];
+                    f[c] = (h.x - x_lo[c]) + (h.y - x_lo[4 + c]);
+                }
+            } else {
+                const double *x_hi = pxb + b * bin_stride + hi * 8;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[c] = (x_hi[c] - x_lo[c]) + (x_hi[4 + c] - x_lo[4 + c]);
+            }
             const double v = kB * (f[0] * f[0] + f[1] * f[1]) + kA * (f[2] * f[2] + f[3] * f[3])
                              - kC * (f[0] * f[2] + f[1] * f[3]);
             if (n_ok) {
@@ -1240,7 +1310,8 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wr
 
 __global__ __launch_bounds__(256) void rect_kernel(RectParams p) {
     __shared__ Red wred[kWaves][kRectBins];
-    rect_block(p, wred, blockIdx.x, blockIdx.y, blockIdx.z);
+    __shared__ RectStage st;
+    rect_block<true>(p, wred, &st, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -1393,7 +1464,7 @@ __global__ __launch_bounds__(kThreads, (fused_waves<V, M>())) void fused_kernel(
         const BatchTile t = load_uniform(p.tiles + ti);   // one tile, held in scalar registers
         if (t.kind == 1) {
             auto &rp = const_params(p.rect_jobs + t.job);
-            rect_block(rp, reinterpret_cast<Red (*)[kRectBins]>(smem), t.x, t.y, t.z);
+            rect_block<false>(rp, reinterpret_cast<Red (*)[kRectBins]>(smem), nullptr, t.x, t.y, t.z);
             continue;
         }
         auto &ep = const_params(p.exp_jobs + t.job);
