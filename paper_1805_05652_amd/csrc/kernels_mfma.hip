@@ -465,6 +465,9 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
 struct RowsSmem {
     double abc[4][16][kBlk][3];   // per wave: its rows' folded A, B, C of the block
     Red wred[4][16];
+    // per wave: 2F of its 16 rows x 16 bins x 8 taus, written to the map
+    // once both passes are done (one padding float per row and bin)
+    float out[4][16][16][kBlk + 1];
 };
 
 // The lane's 8 weights of one K step as hi and lo parts (lo = part(w - hi),
@@ -697,7 +700,7 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
                 const double v = twoF_folded(sm.abc[wave][4 * kg + r][t0 + t], sc[0] * (double)acc[t][0][r],
                                              sc[1] * (double)acc[t][1][r], sc[2] * (double)acc[t][2][r],
                                              sc[3] * (double)acc[t][3][r]);
-                if (p.twoF) p.twoF[((size_t)bin * n_t0 + m) * p.n_tau + n] = (float)v;
+                if (p.twoF) sm.out[wave][4 * kg + r][lrow][t0 + t] = (float)v;
                 v2[t][r] = v;
                 const long long idx = (long long)m * p.n_tau + n;
                 if (v > fmx || (v == fmx && idx < imx)) {
@@ -714,6 +717,32 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
                 for (int r = 0; r < 4; ++r)
                     if (v2[t][r] != -INFINITY) sum += (double)__expf((float)(0.5 * (v2[t][r] - fmx)));
             red = red_combine(red, Red{0.5 * fmx, sum, imx});
+        }
+    }
+
+    // the wave's map cells, 8 taus of one (bin, row) at a time: the 32
+    // bytes of a map row that this block owns arrive together, instead of
+    // as two 16-byte pieces, one from each pass
+    if (p.twoF) {
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __builtin_amdgcn_wave_barrier();
+        const int n0 = nb * kBlk;
+        const int nt = min(kBlk, p.n_tau - n0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pr = lane + 64 * j;
+            const int r = pr >> 4, bl = pr & 15;
+            const int m = m_w + r, b = col_tile * 16 + bl;
+            if (m < n_t0 && b < p.n_bins) {
+                float *dst = p.twoF + ((size_t)b * n_t0 + m) * p.n_tau + n0;
+                const float *src = sm.out[wave][r][bl];
+                if (nt == kBlk) {
+#pragma unroll
+                    for (int t = 0; t < kBlk; ++t) dst[t] = src[t];
+                } else {
+                    for (int t = 0; t < nt; ++t) dst[t] = src[t];
+                }
+            }
         }
     }
 
