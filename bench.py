@@ -472,8 +472,11 @@ def bench_batch(args, tf, torch, prec):
         batch.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         res = batch.run()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     t1 = time.perf_counter()
     st = batch.stats()
     ms = (t1 - t0) * 1e3 / args.steps
@@ -524,6 +527,7 @@ def bench_batch(args, tf, torch, prec):
         "rect_cells_bins": rect_cells, "maps": len(cands), "bin_maps": st["n_results"],
         "variant": st["variant"], "groups": st["groups"], "tiles": st["n_tiles"],
         "tune_ms": st["tune_ms"], "plan_s": plan_s, "graph_ms": st["last_ms"],
+        "step_ms": [round(x, 3) for x in step_ms],
         "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / ms,
         "results_equal_sequential": bool(same),
         "max_rel_err_2F_vs_oracle": err,
