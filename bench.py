@@ -35,6 +35,8 @@ Prints ONE JSON line.  Options:
 from __future__ import annotations
 
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -385,6 +387,18 @@ def roofline_for(atoms, win, prec, prof, workload):
     return roof
 
 
+@contextlib.contextmanager
+def no_gc():
+    """Python's cyclic collector paused over a timed region (collected
+    first), so that a collection pass does not land inside one step."""
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        gc.enable()
+
+
 def time_map(ctx, aid, atoms, win, prec, twoF, steps, warmup, workload):
     """Times `steps` calls of tfstat_fmap (map written to twoF when given)
     after `warmup` untimed ones; per-kernel device times from HIP events."""
@@ -395,12 +409,13 @@ def time_map(ctx, aid, atoms, win, prec, twoF, steps, warmup, workload):
     ctx.profile_reset()
     ctx.profile(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     res = None
-    for _ in range(steps):
-        res, _ = ctx.fmap(aid, win, prec, out=twoF)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with no_gc():
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res, _ = ctx.fmap(aid, win, prec, out=twoF)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     ctx.profile(False)
     prof = ctx.profile_read()
     ms = (t1 - t0) * 1e3 / steps
@@ -471,13 +486,15 @@ def bench_batch(args, tf, torch, prec):
     for _ in range(args.warmup):
         batch.run()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    step_ms = []
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        res = batch.run()
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-    t1 = time.perf_counter()
+    step_ms, step_graph_ms = [], []
+    with no_gc():
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            res = batch.run()
+            step_ms.append((time.perf_counter() - ts) * 1e3)
+            step_graph_ms.append(batch.stats()["last_ms"])
+        t1 = time.perf_counter()
     st = batch.stats()
     ms = (t1 - t0) * 1e3 / args.steps
     # the fused kernel and the matrix-core launch alone, timed with HIP
@@ -528,6 +545,7 @@ def bench_batch(args, tf, torch, prec):
         "variant": st["variant"], "groups": st["groups"], "tiles": st["n_tiles"],
         "tune_ms": st["tune_ms"], "plan_s": plan_s, "graph_ms": st["last_ms"],
         "step_ms": [round(x, 3) for x in step_ms],
+        "step_graph_ms": [round(x, 3) for x in step_graph_ms],
         "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / ms,
         "results_equal_sequential": bool(same),
         "max_rel_err_2F_vs_oracle": err,
