@@ -764,50 +764,351 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
     }
 }
 
+// ---------------------------------------------------------------------------
+// Maps of kSwMinColTiles or more 16-bin column tiles: one work item is 64 t0
+// rows x 4 column tiles (64 bins) x 8 taus.  The four waves take the rows 16
+// at a time, all four on the same rows, and split the bins (wave w: column
+// tile 4 g + w); the 8 taus are one pass, so that each B load of a wave
+// feeds 8 taus' products.  In every K step each wave makes the weights of two
+// taus (w and w + 4) for the shared rows, exactly as mfma_rows_tile makes
+// them, and puts their hi and lo parts in LDS; every wave reads the eight
+// taus' parts from there.  A weight is thus made once per 64 bins instead of
+// once per 16, which leaves the matrix cores most of each wave's issue
+// cycles.  The K steps of the four waves are the same (same rows, same
+// taus), so they run in step, two LDS buffers of weights and one barrier per
+// step.
+// ---------------------------------------------------------------------------
+#ifndef TFS_SW_NT
+#define TFS_SW_NT 8            // taus per pass of the shared-weight work item
+#endif
+constexpr int kSwNT = TFS_SW_NT;
+constexpr int kSwTW = kSwNT / 4;   // taus whose weights each wave makes
+static_assert(kSwNT % 4 == 0 && kBlk % kSwNT == 0, "taus of a pass split over the four waves");
+
+struct SwSmem {
+    u32x4 a[2][kSwNT][2][64];        // weights of one K step: [buffer][tau][hi, lo][lane]
+    double abc[16][kBlk][3];         // the 16 rows' folded A, B, C of the block
+    float out[4][16][16][kBlk + 1];  // per wave: 2F of the rows x its 16 bins x 8 taus
+};
+
+template <bool F16, typename PP>
+__device__ __attribute__((always_inline)) inline void mfma_rows_tile_sw(PP &p, SwSmem &sm, int q, int row_tile,
+                                                                      int col_group) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nb = p.blk_list[q];
+    const int tile = nb * p.n_row_tiles + row_tile;
+    const int n_t0 = p.n_t0;
+    const int lrow = lane & 15;   // A row / C column within the 16 tile
+    const int kg = lane >> 4;     // K group of 8
+    const int col_tile = col_group * 4 + wave;
+    const bool col_ok = col_tile < p.n_col_tiles;   // wave-uniform
+    const int bin = col_tile * 16 + lrow;
+    const bool bin_ok = bin < p.n_bins;
+    const int64_t T = p.t_sft;
+
+    // B operand as in mfma_rows_tile (waves past the last column tile load
+    // nothing; they still make weights and keep the barriers)
+    const uint32_t comp_bytes = (uint32_t)p.bins16 * (uint32_t)p.kp * 2u;
+    const uint32_t step_bytes = (uint32_t)p.bins16 * 64u;
+    const uint32_t lane_off = (uint32_t)(((col_ok ? col_tile : 0) * 16 + lrow) * 32 + 8 * kg) * 2u;
+    __amdgpu_buffer_rsrc_t rh[4], rl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        rh[c] = plane_rsrc(p.xhi + (size_t)c * p.bins16 * p.kp, comp_bytes);
+        rl[c] = plane_rsrc(p.xlo + (size_t)c * p.bins16 * p.kp, comp_bytes);
+    }
+    auto load_b = [&](int kb, u32x4 *h, u32x4 *l) {
+        const int so = (int)((uint32_t)(kb >> 5) * step_bytes);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            h[c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh[c], (int)lane_off, so, 0));
+            l[c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl[c], (int)lane_off, so, 0));
+        }
+    };
+    double sc[4] = {1.0, 1.0, 1.0, 1.0};
+    if constexpr (F16) {
+        if (col_ok) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                sc[c] = ldexp(1.0, -(kF16WeightExp + p.colexp[c * p.bins16 + col_tile * 16 + lrow]));
+        }
+    }
+
+    Red red = red_empty();
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        const int m_g = row_tile * 64 + 16 * g;   // first row of the group
+        if (m_g >= n_t0) break;
+        // A, B, C of the group's 16 rows x 8 taus with 2 / D folded in (the
+        // previous group's readers are done first)
+        __syncthreads();
+        if (tid < 16 * kBlk) {
+            const int r = tid / kBlk, t = tid % kBlk;
+            const int m = min(m_g + r, n_t0 - 1);
+            const double *src = p.abc_cell + ((size_t)m * p.abc_pitch + (size_t)nb * kBlk + t) * 3;
+            double abc[3] = {src[0], src[1], src[2]};
+            fold_abc(abc, 1.0);
+            sm.abc[r][t][0] = abc[0];
+            sm.abc[r][t][1] = abc[1];
+            sm.abc[r][t][2] = abc[2];
+        }
+        __syncthreads();
+        // the lane's A row (rows past the grid repeat the last one; never written)
+        const RowPlan ra = p.rows[min(m_g + lrow, n_t0 - 1)];
+        const int k_first = __builtin_amdgcn_readfirstlane(p.rows[m_g].k0);
+#pragma unroll 1
+        for (int half = 0; half < kBlk / kSwNT; ++half) {
+            const int t0 = half * kSwNT;
+            // this wave's taus (t0 + w + 4 i): their weight constants for the
+            // lane's row; the pass's last tau: the K range
+            float cT[kSwTW], cD[kSwTW], rho[kSwTW];
+            int Lw[kSwTW], Llast;
+#pragma unroll
+            for (int i = 0; i < kSwTW; ++i) {
+                const int n = min(nb * kBlk + t0 + wave + 4 * i, p.n_tau - 1);
+                const int64_t tau = p.tau[n];
+                const double inv = 1.4426950408889634 / (double)tau;
+                cT[i] = (float)(-(double)T * inv);
+                cD[i] = (float)(-(double)ra.delta * inv) + (F16 ? (float)kF16WeightExp : 0.f);
+                rho[i] = exp2f(cT[i]);
+                const int64_t span = 3 * tau;
+                Lw[i] = span > ra.delta ? (int)min((span - ra.delta + T - 1) / T, (int64_t)1 << 30) : 0;
+            }
+            {
+                const int64_t span_l = 3 * p.tau[min(nb * kBlk + t0 + kSwNT - 1, p.n_tau - 1)];
+                Llast = span_l > ra.delta ? (int)min((span_l - ra.delta + T - 1) / T, (int64_t)1 << 30) : 0;
+            }
+            // K range: the first row's slot to the furthest band end of the
+            // rows (the pass's last tau is its longest), an even number of
+            // 32-slot steps
+            int kend = (int)min((int64_t)ra.k0 + Llast, (int64_t)p.kp_data);
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) kend = max(kend, __shfl_xor(kend, o, 64));
+            kend = __builtin_amdgcn_readfirstlane(kend);
+            const int kb_begin = max(k_first, 0) & ~31;
+            const int kb_data_end = min((kend + 31) & ~31, p.kp_data);
+            const int kb_end = kb_data_end > kb_begin ? kb_begin + ((kb_data_end - kb_begin + 63) & ~63) : kb_begin;
+
+            f32x4 acc[kSwNT][4];
+#pragma unroll
+            for (int t = 0; t < kSwNT; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+            // this wave's weights of step kb into LDS buffer buf (the window
+            // mask applied in every step: no branch between the weights and
+            // the products, which the compiler may then interleave)
+            auto make_w = [&](int kb, int buf) {
+#pragma unroll
+                for (int i = 0; i < kSwTW; ++i) {
+                    u32x4 ah, al;
+                    rows_weights<true, F16>(kb + 8 * kg - ra.k0, cT[i], cD[i], rho[i], Lw[i], ah, al);
+                    sm.a[buf][wave + 4 * i][0][lane] = ah;
+                    sm.a[buf][wave + 4 * i][1][lane] = al;
+                }
+            };
+            // the products of one step (12 per tau), each tau's weights read
+            // from LDS buffer buf one tau ahead of its products
+            auto mma = [&](int buf, const u32x4 *ch, const u32x4 *cl) {
+                u32x4 ah = sm.a[buf][0][0][lane], al = sm.a[buf][0][1][lane];
+#pragma unroll
+                for (int t = 0; t < kSwNT; ++t) {
+                    u32x4 nah = ah, nal = al;
+                    if (t + 1 < kSwNT) {
+                        nah = sm.a[buf][t + 1][0][lane];
+                        nal = sm.a[buf][t + 1][1][lane];
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(ah, ch[c], acc[t][c]);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(ah, cl[c], acc[t][c]);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(al, ch[c], acc[t][c]);
+                    ah = nah;
+                    al = nal;
+                }
+            };
+            if (kb_begin < kb_end) {
+                make_w(kb_begin, 0);
+                if (col_ok) {
+                    u32x4 bh[4], bl[4], nh[4], nl[4];
+                    load_b(kb_begin, bh, bl);
+                    __syncthreads();
+#pragma unroll 1
+                    for (int kb = kb_begin; kb < kb_end; kb += 64) {
+                        // step kb from buffer 0 while step kb + 32's weights
+                        // go to buffer 1 (kb + 32 < kb_end: the count is even)
+                        load_b(kb + 32, nh, nl);
+                        make_w(kb + 32, 1);
+                        mma(0, bh, bl);
+                        __syncthreads();
+                        load_b(min(kb + 64, kb_end - 32), bh, bl);
+                        // (the last round writes one step again: no branch)
+                        make_w(min(kb + 64, kb_end - 32), 0);
+                        mma(1, nh, nl);
+                        __syncthreads();
+                    }
+                } else {
+                    // no column tile: this wave's weights only
+                    __syncthreads();
+#pragma unroll 1
+                    for (int kb = kb_begin; kb < kb_end; kb += 64) {
+                        make_w(kb + 32, 1);
+                        __syncthreads();
+                        make_w(min(kb + 64, kb_end - 32), 0);
+                        __syncthreads();
+                    }
+                }
+            }
+
+            // finalize: lane holds rows 4 kg + r (r < 4) of the group for
+            // `bin`; half-precision sums carry the powers of two of the
+            // weights and of their data column, removed exactly here
+            if (col_ok) {
+                double v2[kSwNT][4];
+                double fmx = -INFINITY;
+                long long imx = 0x7fffffffffffffffLL;
+#pragma unroll
+                for (int t = 0; t < kSwNT; ++t) {
+                    const int n = nb * kBlk + t0 + t;
+                    const bool n_ok = n < p.n_tau;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = m_g + 4 * kg + r;
+                        v2[t][r] = -INFINITY;
+                        if (!n_ok || m >= n_t0 || !bin_ok) continue;
+                        const double v = twoF_folded(sm.abc[4 * kg + r][t0 + t], sc[0] * (double)acc[t][0][r],
+                                                     sc[1] * (double)acc[t][1][r], sc[2] * (double)acc[t][2][r],
+                                                     sc[3] * (double)acc[t][3][r]);
+                        if (p.twoF) sm.out[wave][4 * kg + r][lrow][t0 + t] = (float)v;
+                        v2[t][r] = v;
+                        const long long idx = (long long)m * p.n_tau + n;
+                        if (v > fmx || (v == fmx && idx < imx)) {
+                            fmx = v;
+                            imx = idx;
+                        }
+                    }
+                }
+                if (fmx != -INFINITY) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int t = 0; t < kSwNT; ++t)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (v2[t][r] != -INFINITY) sum += (double)__expf((float)(0.5 * (v2[t][r] - fmx)));
+                    red = red_combine(red, Red{0.5 * fmx, sum, imx});
+                }
+            }
+        }
+
+        // the group's map cells of this wave's bins, 8 taus of one (bin,
+        // row) at a time
+        if (p.twoF && col_ok) {
+            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+            __builtin_amdgcn_wave_barrier();
+            const int n0 = nb * kBlk;
+            const int nt = min(kBlk, p.n_tau - n0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int pr = lane + 64 * j;
+                const int r = pr >> 4, bl = pr & 15;
+                const int m = m_g + r, b = col_tile * 16 + bl;
+                if (m < n_t0 && b < p.n_bins) {
+                    float *dst = p.twoF + ((size_t)b * n_t0 + m) * p.n_tau + n0;
+                    const float *src = sm.out[wave][r][bl];
+                    if (nt == kBlk) {
+#pragma unroll
+                        for (int t = 0; t < kBlk; ++t) dst[t] = src[t];
+                    } else {
+                        for (int t = 0; t < nt; ++t) dst[t] = src[t];
+                    }
+                }
+            }
+        }
+    }
+
+    // lanes sharing a bin: xor 16, 32; each wave owns its bins' partials
+    red = red_combine(red, red_shfl_xor(red, 16));
+    red = red_combine(red, red_shfl_xor(red, 32));
+    if (col_ok && lane < 16 && bin_ok) {
+        Partial &o = p.part[(size_t)bin * p.n_tiles + tile];
+        o.fmax = red.f;
+        o.s = red.s;
+        o.idx = red.i;
+    }
+}
+
+union MfmaRowsSmem {
+    RowsSmem rows;
+    SwSmem sw;
+};
+
 #ifndef TFS_ROWS_WAVES
 #define TFS_ROWS_WAVES 2       // waves per SIMD the register budget targets
 #endif
 
 // XCD-aware task order as in exp_mfma_kernel: column tiles dealt to the XCDs
 // when there are at least 8 of them, otherwise the tau blocks.
+// Work items of a map: 16-bin column tiles, or groups of four of them
+// (mfma_rows_tile_sw) when the map has kSwMinColTiles or more.
+template <bool F16, typename PP>
+__device__ __attribute__((always_inline)) inline void mfma_rows_item(PP &p, MfmaRowsSmem &sm, int q, int row_tile,
+                                                                   int col_item) {
+    if (p.n_col_tiles >= kSwMinColTiles)
+        mfma_rows_tile_sw<F16>(p, sm.sw, q, row_tile, col_item);
+    else
+        mfma_rows_tile<F16>(p, sm.rows, q, row_tile, col_item);
+}
+
 template <bool F16>
 __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpMfmaRowsParams p) {
-    __shared__ RowsSmem sm;
+    __shared__ MfmaRowsSmem sm;
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
     const int slot = bid >> 3;
-    int q, row_tile, col_tile;
-    if (p.n_col_tiles >= 8) {
-        const int cpx = (p.n_col_tiles + 7) / 8;
+    const int n_col = mfma_col_items(p.n_col_tiles);
+    int q, row_tile, col_item;
+    if (n_col >= 8) {
+        const int cpx = (n_col + 7) / 8;
         const int per_block = p.n_row_tiles * cpx;
         q = slot / per_block;
         const int rem = slot % per_block;
         row_tile = rem / cpx;
-        col_tile = (rem % cpx) * 8 + xcd;
-        if (q >= p.n_blocks || col_tile >= p.n_col_tiles) return;
+        col_item = (rem % cpx) * 8 + xcd;
+        if (q >= p.n_blocks || col_item >= n_col) return;
+    } else if (n_col == 2 || n_col == 4) {
+        // each XCD one column item (its share of the B planes stays in the
+        // XCD's L2) and every (8 / n_col)-th tau block
+        const int r = 8 / n_col;
+        col_item = xcd % n_col;
+        q = (slot / p.n_row_tiles) * r + xcd / n_col;
+        row_tile = slot % p.n_row_tiles;
+        if (q >= p.n_blocks) return;
     } else {
-        const int per_block = p.n_row_tiles * p.n_col_tiles;
+        const int per_block = p.n_row_tiles * n_col;
         q = (slot / per_block) * 8 + xcd;
         if (q >= p.n_blocks) return;
         const int rem = slot % per_block;
-        row_tile = rem / p.n_col_tiles;
-        col_tile = rem % p.n_col_tiles;
+        row_tile = rem / n_col;
+        col_item = rem % n_col;
     }
-    mfma_rows_tile<F16>(p, sm, q, row_tile, col_tile);
+    mfma_rows_item<F16>(p, sm, q, row_tile, col_item);
 }
 
 // Matrix-core work items of many maps (one entry per workgroup).
 template <bool F16>
 __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void mfma_batch_kernel(MfmaBatchParams b) {
-    __shared__ RowsSmem sm;
+    __shared__ MfmaRowsSmem sm;
     const int e = blockIdx.x;
     const int job = b.entries[4 * e + 0];
     const int q = b.entries[4 * e + 1];
     const int row_tile = b.entries[4 * e + 2];
-    const int col_tile = b.entries[4 * e + 3];
-    mfma_rows_tile<F16>(*reinterpret_cast<const __attribute__((address_space(4))) ExpMfmaRowsParams *>(
-                       reinterpret_cast<uintptr_t>(b.jobs + job)),
-                   sm, q, row_tile, col_tile);
+    const int col_item = b.entries[4 * e + 3];
+    mfma_rows_item<F16>(*reinterpret_cast<const __attribute__((address_space(4))) ExpMfmaRowsParams *>(
+                            reinterpret_cast<uintptr_t>(b.jobs + job)),
+                        sm, q, row_tile, col_item);
 }
 
 // Per data column (component c, bin) of the FP32 atoms x32 [K+1][bins][4],
@@ -887,12 +1188,16 @@ hipError_t launch_exp_mfma_rows(const ExpMfmaRowsParams &p, hipStream_t s) {
     if (p.n_blocks <= 0) return hipSuccess;
     if (p.kp < p.kp_data + 32) return hipErrorInvalidValue;   // even-step padding reads up to kp_data + 32
     unsigned grid;
-    if (p.n_col_tiles >= 8) {
-        const int cpx = (p.n_col_tiles + 7) / 8;
+    const int n_col = mfma_col_items(p.n_col_tiles);
+    if (n_col >= 8) {
+        const int cpx = (n_col + 7) / 8;
         grid = (unsigned)(8 * p.n_blocks * p.n_row_tiles * cpx);
+    } else if (n_col == 2 || n_col == 4) {
+        const int r = 8 / n_col;
+        grid = (unsigned)(8 * ((p.n_blocks + r - 1) / r) * p.n_row_tiles);
     } else {
         const int groups = (p.n_blocks + 7) / 8;
-        grid = (unsigned)(8 * groups * p.n_row_tiles * p.n_col_tiles);
+        grid = (unsigned)(8 * groups * p.n_row_tiles * n_col);
     }
     if (p.f16)
         hipLaunchKernelGGL(exp_mfma_rows_kernel<true>, dim3(grid), dim3(256), 0, s, p);

@@ -1214,7 +1214,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             if (j.use_mfma) {
                 // matrix-core work of the long-band blocks
                 midx[i] = n_mfma_maps++;
-                n_mfma_entries += (size_t)j.n_mfma * j.n_row_tiles * (j.at->bins16 / 16);
+                n_mfma_entries += (size_t)j.n_mfma * j.n_row_tiles * tfs::mfma_col_items(j.at->bins16 / 16);
             }
             max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
         } else {
@@ -1392,7 +1392,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             if (j.use_mfma) {
                 const int32_t *blk = reinterpret_cast<const int32_t *>(ws_ptr<char>(j, j.off_order)) + j.n_valu;
                 mfp[midx[i]] = mfma_rows_params(j, blk);
-                const int n_ct = j.at->bins16 / 16;
+                const int n_ct = tfs::mfma_col_items(j.at->bins16 / 16);
                 for (int q = 0; q < j.n_mfma; ++q)
                     for (int rt = 0; rt < j.n_row_tiles; ++rt)
                         for (int ct = 0; ct < n_ct; ++ct) {

@@ -132,6 +132,14 @@ struct ExpMfmaRowsParams {
     Partial *part;
 };
 
+// Maps of at least this many 16-bin column tiles take their matrix-core
+// work items four column tiles at a time (one wave each, weights shared).
+constexpr int kSwMinColTiles = 4;
+// Column work items of a map with n_col_tiles 16-bin column tiles.
+__host__ __device__ inline int mfma_col_items(int n_col_tiles) {
+    return n_col_tiles >= kSwMinColTiles ? (n_col_tiles + 3) / 4 : n_col_tiles;
+}
+
 // Half-precision matrix-core weights are taken as w * 2^kF16WeightExp.
 constexpr int kF16WeightExp = 4;
 

@@ -402,7 +402,7 @@ def _kernel_launches(ctx, fn):
 
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 @pytest.mark.parametrize("case", ["linspace", "stride7", "before_after", "bins5", "bins37", "bins3_valu",
-                                  "one_row_tile", "long_and_short", "scaled"])
+                                  "one_row_tile", "long_and_short", "scaled", "bins70", "bins64_stride3"])
 def test_matrix_any_grid(ctx, case, prec):
     """Matrix cores for exponential windows on any t0 grid (weights computed
     per row): linspace rows with their own offsets, rows 7 slots apart, rows
@@ -410,10 +410,12 @@ def test_matrix_any_grid(ctx, case, prec):
     tiles), a map of fewer than 4 bins (FP32 path), a single partial row
     tile, tau blocks with short bands (FP32 F-only tiles) beside long ones,
     and data far outside the half-precision range with one all-zero bin
-    (the half-precision path's column scaling).
+    (the half-precision path's column scaling).  Maps of 64 and 70 bins take
+    the work items of four column tiles with shared weights (70 bins: a
+    last group of one column tile and three waves without one).
     Every cell and the per-bin results against the oracle."""
     _case("%s any grid %s" % (prec, case))
-    n_bins = {"bins5": 5, "bins37": 37, "bins3_valu": 3}.get(case, 24)
+    n_bins = {"bins5": 5, "bins37": 37, "bins3_valu": 3, "bins70": 70, "bins64_stride3": 64}.get(case, 24)
     atoms = tfsynth.make_atoms(811, 1400, 0.12, n_bins=n_bins,
                                injections=[tfsynth.Injection(min(4, n_bins - 1), "exp", 300 * T, 60 * T, 1.0)])
     if case == "scaled":
@@ -425,8 +427,10 @@ def test_matrix_any_grid(ctx, case, prec):
         fb[7] = 0.0
         atoms = dataclasses.replace(atoms, fa=fa, fb=fb, a2=atoms.a2 * 2.0 ** 40, b2=atoms.b2 * 2.0 ** 40,
                                     ab=atoms.ab * 2.0 ** 40)
-    if case in ("linspace", "bins5", "bins37", "bins3_valu", "scaled"):
+    if case in ("linspace", "bins5", "bins37", "bins3_valu", "scaled", "bins70"):
         win = tfsynth.linspace_grid(atoms, "exp", 260, 110)
+    elif case == "bins64_stride3":
+        win = tfsynth.regular_window("exp", 50 * T + 3, 3 * T, 150, 2 * T, 4 * T + 9, 75)
     elif case == "stride7":
         win = tfsynth.regular_window("exp", 333, 7 * T, 150, 2 * T, 5 * T + 17, 70)
     elif case == "before_after":
