@@ -1049,8 +1049,6 @@ union MfmaRowsSmem {
 #define TFS_ROWS_WAVES 2       // waves per SIMD the register budget targets
 #endif
 
-// XCD-aware task order as in exp_mfma_kernel: column tiles dealt to the XCDs
-// when there are at least 8 of them, otherwise the tau blocks.
 // Work items of a map: 16-bin column tiles, or groups of four of them
 // (mfma_rows_tile_sw) when the map has kSwMinColTiles or more.
 template <bool F16, typename PP>
@@ -1062,6 +1060,9 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_item(PP &p, Mfma
         mfma_rows_tile<F16>(p, sm.rows, q, row_tile, col_item);
 }
 
+// XCD-aware task order: column items dealt to the XCDs when there are at
+// least 8 of them, one per XCD when there are 2 or 4, otherwise the tau
+// blocks.
 template <bool F16>
 __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpMfmaRowsParams p) {
     __shared__ MfmaRowsSmem sm;
