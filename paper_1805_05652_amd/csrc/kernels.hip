@@ -1198,11 +1198,19 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wr
     const int nbg = min(kRectBins, p.n_bins - bin0);
     const size_t bin_stride = ((size_t)K + 1) * 8;   // prefixes of one bin: [K+1][8]
     const double *pxb = p.px + (size_t)bin0 * bin_stride;
-    auto window = [&](const RowPlan &rp, int64_t tau_c, int64_t &lo, int64_t &hi) {
-        const int64_t L = tau_c > rp.delta ? (tau_c - rp.delta + T - 1) / T : 0;
+    // Window of a row for tau = q T + r (0 <= r < T): the SFT starts in
+    // [t0, t0 + tau) are slots k0 .. k0 + L - 1 with L = ceil((tau - delta) / T)
+    // (0 when tau <= delta); as the row offset delta lies in [0, T), that is
+    // L = q + (r > delta), so the division is made once per tau, not per cell.
+    auto window_qr = [&](const RowPlan &rp, int64_t q_t, int64_t r_t, int64_t &lo, int64_t &hi) {
+        const int64_t L = q_t + (r_t > rp.delta ? 1 : 0);
         lo = min(max((int64_t)rp.k0, (int64_t)0), K);
         hi = min(max((int64_t)rp.k0 + L, (int64_t)0), K);
     };
+    auto window = [&](const RowPlan &rp, int64_t tau_c, int64_t &lo, int64_t &hi) {
+        window_qr(rp, tau_c / T, tau_c % T, lo, hi);
+    };
+    const int64_t tau_q = tau / T, tau_r = tau % T;
     bool staged = false;
     int64_t s0 = 0;
     if constexpr (STAGE) {
@@ -1242,7 +1250,7 @@ __device__ __attribute__((always_inline)) inline void rect_block(PP &p, Red (*wr
         if (m >= p.n_t0) break;
         const RowPlan rp = p.rows[m];
         int64_t lo, hi;
-        window(rp, tau, lo, hi);
+        window_qr(rp, tau_q, tau_r, lo, hi);
         // window sums from compensated prefixes: (hi_h - lo_h) + (hi_l - lo_l)
         const double *a_lo = p.pabc + lo * 8;
         double A, B, C;
