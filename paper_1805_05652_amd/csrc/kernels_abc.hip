@@ -31,18 +31,25 @@ namespace tfs {
 
 namespace {
 
-// Adds sum_{k in [lo, hi)} f u^(k - lo) y_k to g, k clipped to [0, K) (f is
-// the weight of slot lo, sign included; c2 = ln u).  Eight slots' atoms are
+// Running sums of the three antenna channels.
+struct Sum3 {
+    double a, b, c;
+};
+
+// g + sum_{k in [lo, hi)} f u^(k - lo) y_k, k clipped to [0, K) (f is the
+// weight of slot lo, sign included; c2 = ln u).  Eight slots' atoms are
 // loaded before they are summed, so that the loads of a group are in flight
-// together.
-__device__ __attribute__((noinline)) void add_run(double g[3], const double *abc, int32_t K, int64_t lo,
-                                                  int64_t hi, double f, double u, double c2) {
+// together.  Out of line (it is the rare path) and by value, so that the
+// caller's sums stay in registers.
+__device__ __attribute__((noinline)) Sum3 add_run(Sum3 acc, const double *abc, int32_t K, int64_t lo, int64_t hi,
+                                                  double f, double u, double c2) {
+    double g[3] = {acc.a, acc.b, acc.c};
     if (lo < 0) {
         f *= exp(c2 * (double)(-lo));
         lo = 0;
     }
     hi = hi > K ? K : hi;
-    if (lo >= hi) return;
+    if (lo >= hi) return acc;
     int64_t k = lo;
     for (; k + 8 <= hi; k += 8) {
         double2 ab[8];
@@ -67,6 +74,7 @@ __device__ __attribute__((noinline)) void add_run(double g[3], const double *abc
         g[2] = fma(f, y[2], g[2]);
         f *= u;
     }
+    return Sum3{g[0], g[1], g[2]};
 }
 
 // Atoms (a^2, b^2, ab) of slot k, zero outside [0, K).
@@ -170,8 +178,10 @@ __device__ __attribute__((always_inline)) inline void abc_recur_lane(PP &p, int 
                     g[2] = fma(f, ty[i][2], g[2]);
                 }
             } else if (m == m_hi - 1 || kn >= e) {
-                g[0] = g[1] = g[2] = 0.0;
-                add_run(g, p.abc, K, k0, e, 1.0, u, c2);
+                const Sum3 r = add_run(Sum3{0.0, 0.0, 0.0}, p.abc, K, k0, e, 1.0, u, c2);
+                g[0] = r.a;
+                g[1] = r.b;
+                g[2] = r.c;
             } else {
                 // u^D by products for short steps, the exponential otherwise
                 const int64_t D = kn - k0;
@@ -181,15 +191,15 @@ __device__ __attribute__((always_inline)) inline void abc_recur_lane(PP &p, int 
                 } else {
                     uD = exp(c2 * (double)D);
                 }
-                g[0] *= uD;
-                g[1] *= uD;
-                g[2] *= uD;
-                add_run(g, p.abc, K, k0, kn, 1.0, u, c2);
+                Sum3 r = add_run(Sum3{g[0] * uD, g[1] * uD, g[2] * uD}, p.abc, K, k0, kn, 1.0, u, c2);
                 if (e != en) {
                     const int64_t lo = e > en ? en : e;
                     const double sign = e > en ? 1.0 : -1.0;
-                    add_run(g, p.abc, K, lo, e > en ? e : en, sign * exp(c2 * (double)(lo - k0)), u, c2);
+                    r = add_run(r, p.abc, K, lo, e > en ? e : en, sign * exp(c2 * (double)(lo - k0)), u, c2);
                 }
+                g[0] = r.a;
+                g[1] = r.b;
+                g[2] = r.c;
             }
             kn = k0;
             en = e;
