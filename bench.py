@@ -59,12 +59,13 @@ DTYPES = {"fp32": "f32+f64", "fp64": "f64", "bf16x3": "bf16x3(f32 acc)+f64", "f1
           "recur64": "f64"}
 
 
-def mfma_taus(atoms, win, taus_per_block: int = 8, min_band: int = 64, min_bins: int = 4):
+def mfma_taus(atoms, win, prec="bf16x3", taus_per_block: int = 8, min_band: int = 64, min_bins: int = 4):
     """Boolean mask of the taus whose sums run on the matrix cores in
-    F16X3 or BF16X3 -- the library's planning rule restated: exponential windows of at
-    least 4 bins; blocks of 8 consecutive taus whose shortest band (the
-    slots of [t0, t0 + 3 tau) over the row with the largest offset from the
-    slot grid, capped at the data end) is at least 64 slots."""
+    F16X3 or BF16X3 -- the library's planning rule restated: exponential
+    windows of at least 4 bins with a block of 8 consecutive taus whose
+    shortest band (the slots of [t0, t0 + 3 tau) over the row with the
+    largest offset from the slot grid, capped at the data end) is at least
+    64 slots; in BF16X3 only such blocks, in F16X3 then every block."""
     keep = np.zeros(win.n_tau, dtype=bool)
     if win.kind != "exp" or atoms.n_bins < min_bins:
         return keep
@@ -80,13 +81,15 @@ def mfma_taus(atoms, win, taus_per_block: int = 8, min_band: int = 64, min_bins:
     for b0 in range(0, win.n_tau, taus_per_block):
         if lcol[b0:b0 + taus_per_block].min() >= min_band:
             keep[b0:b0 + taus_per_block] = True
+    if prec == "f16x3" and keep.any():
+        keep[:] = True
     return keep
 
 
-def mfma_cells(atoms, win):
+def mfma_cells(atoms, win, prec="bf16x3"):
     """cells*present SFTs*bins of the tau blocks that run on the matrix
     cores (the others run on the VALU)."""
-    keep = mfma_taus(atoms, win)
+    keep = mfma_taus(atoms, win, prec)
     if not keep.any():
         return 0
     sub = tfsynth.Window(win.kind, win.t0, win.tau[keep])
@@ -359,7 +362,7 @@ def roofline_for(atoms, win, prec, prof, workload):
         # half-precision or bf16 products (hi*hi + hi*lo + lo*hi): 24
         # matrix-core flops, counted over the tau blocks the matrix-core
         # kernel runs
-        long_cells = mfma_cells(atoms, win)
+        long_cells = mfma_cells(atoms, win, prec)
         flops = 24.0 * long_cells
         roof = {"bound": "mfma", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "cells_sfts_bins": long_cells}
@@ -470,7 +473,7 @@ def bench_batch(args, tf, torch, prec):
             p, sl = work_counts(a, w)
             exp_present += p
             exp_slots += sl
-            mc = mfma_cells(a, w) if prec in MATRIX_PRECS else 0
+            mc = mfma_cells(a, w, prec) if prec in MATRIX_PRECS else 0
             mfma_present += mc
             valu_present += p - mc
             if not split_form(a, w, "fp32" if prec in MATRIX_PRECS else prec) and mc == 0:

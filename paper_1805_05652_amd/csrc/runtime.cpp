@@ -474,15 +474,18 @@ void plan_job(Job &j) {
             }
         }
         if (j.use_mfma) {
-            // a block with any short band stays on the FP32 VALU path: short
-            // windows carry little work and the worst conditioning, which
-            // would amplify the ~2^-16 error of the split operands
+            // BF16X3: a block with any short band stays on the FP32 VALU
+            // path: short windows carry little work and the worst
+            // conditioning, which would amplify the ~2^-16 error of the bf16
+            // split operands.  F16X3 (~2^-22, between FP32 and that) takes
+            // every block of the map onto the matrix cores.
+            const int32_t min_band = j.prec == TFSTAT_PREC_F16X3 ? 0 : kMfmaMinBand;
             std::vector<int32_t> lv, lm;
             for (int32_t b : j.order) {
                 int32_t shortest = INT32_MAX;
                 for (int r = 0; r < j.R && b * j.R + r < n_tau; ++r)
                     shortest = std::min(shortest, j.lcol[b * j.R + r]);
-                (shortest >= kMfmaMinBand ? lm : lv).push_back(b);
+                (shortest >= min_band ? lm : lv).push_back(b);
             }
             j.n_valu = (int)lv.size();
             j.n_mfma = (int)lm.size();

@@ -103,6 +103,10 @@ def test_mfma_cells_blocks():
     assert 0 < want < bench.work_counts(atoms, win)[0]
     assert bench.mfma_cells(_gapless(600, n_bins=3), win) == 0
     assert bench.mfma_cells(atoms, tfsynth.list_window("rect", win.t0, tau)) == 0
+    # F16X3: every block of a map that has a long one; none without one
+    assert bench.mfma_cells(atoms, win, "f16x3") == bench.work_counts(atoms, win)[0]
+    short = tfsynth.list_window("exp", win.t0, tau[8:24])
+    assert bench.mfma_cells(atoms, short, "f16x3") == 0
 
 
 def test_mfma_taus_offsets_and_data_end():

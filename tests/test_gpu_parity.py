@@ -408,7 +408,8 @@ def test_matrix_any_grid(ctx, case, prec):
     per row): linspace rows with their own offsets, rows 7 slots apart, rows
     before and after the data, ragged bin counts (partial 16-bin column
     tiles), a map of fewer than 4 bins (FP32 path), a single partial row
-    tile, tau blocks with short bands (FP32 F-only tiles) beside long ones,
+    tile, tau blocks with short bands beside long ones (BF16X3: FP32 F-only
+    tiles; F16X3: matrix cores too),
     and data far outside the half-precision range with one all-zero bin
     (the half-precision path's column scaling).  Maps of 64 and 70 bins take
     the work items of four column tiles with shared weights (70 bins: a
