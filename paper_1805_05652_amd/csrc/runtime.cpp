@@ -783,17 +783,17 @@ tfs::ExpMfmaRowsParams mfma_rows_params(Job &j, const int32_t *blk_list) {
     return q;
 }
 
-// Rows per lane segment of the A/B/C recurrence.  Each segment starts with
-// one direct window sum and then takes one short dependent step per row, so
-// a lane's time is its chain of round trips to the caches: more segments
-// mean shorter chains and more lanes (and repeated direct sums).  A map
-// takes about 16 K lanes (taus x segments), which leaves the chip room
-// for several maps at once, with at least 8 rows per segment.
+// Rows per segment of the A/B/C scan: one wave per (tau, segment), which
+// sums the segment's last window directly and scans its rows 64 at a time,
+// one dependent chunk after another.  More segments mean shorter chains
+// and more waves (and repeated direct sums); a map takes about 2048 waves,
+// in segments of whole 64-row chunks.
 int32_t abc_seg_rows(const Job &j) {
     const int64_t n_t0 = (int64_t)j.win.t0.size();
     const int64_t n_tau = std::max<int64_t>(1, (int64_t)j.win.tau.size());
-    const int64_t n_seg = std::max<int64_t>(1, std::min<int64_t>(16384 / n_tau, (n_t0 + 7) / 8));
-    return (int32_t)((n_t0 + n_seg - 1) / n_seg);
+    const int64_t chunks = std::max<int64_t>(1, (n_t0 + 63) / 64);
+    const int64_t n_seg = std::max<int64_t>(1, std::min<int64_t>((2048 + n_tau - 1) / n_tau, chunks));
+    return (int32_t)((chunks + n_seg - 1) / n_seg * 64);
 }
 
 // A/B/C of every cell of an exponential-window map by the recurrence over

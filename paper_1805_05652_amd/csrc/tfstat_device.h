@@ -299,7 +299,7 @@ struct AbcRecurParams {
     int32_t pad;
 };
 
-// Many maps: entry e = {map, block of 256 lanes of that map}.
+// Many maps: entry e = {map, block of 4 waves of that map}.
 struct AbcRecurBatchParams {
     const AbcRecurParams *jobs;
     const int32_t *entries;   // [n_entries][2]
@@ -307,10 +307,10 @@ struct AbcRecurBatchParams {
     int32_t pad;
 };
 
-// Workgroups of 256 lanes that cover a map's (tau, segment) lanes.
+// Workgroups of 4 waves that cover a map's (tau, segment) waves.
 inline int64_t abc_recur_blocks(const AbcRecurParams &p) {
     const int64_t n_seg = (p.n_t0 + p.seg_rows - 1) / p.seg_rows;
-    return ((int64_t)(p.n_tau + 63) / 64 * 64 * n_seg + 255) / 256;
+    return ((int64_t)p.n_tau * n_seg + 3) / 4;
 }
 
 // Weight tables of many maps: entry i is block blk[i] of job job[i].
