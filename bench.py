@@ -59,10 +59,10 @@ DTYPES = {"fp32": "f32+f64", "fp64": "f64", "bf16x3": "bf16x3(f32 acc)+f64", "f1
           "recur64": "f64"}
 
 
-def mfma_taus(atoms, win, prec="bf16x3", taus_per_block: int = 8, min_band: int = 64, min_bins: int = 4):
+def mfma_taus(atoms, win, prec="bf16x3", taus_per_block: int = 8, min_band: int = 64, min_bins: int = 2):
     """Boolean mask of the taus whose sums run on the matrix cores in
     F16X3 or BF16X3 -- the library's planning rule restated: exponential
-    windows of at least 4 bins with a block of 8 consecutive taus whose
+    windows of at least 2 bins with a block of 8 consecutive taus whose
     shortest band (the slots of [t0, t0 + 3 tau) over the row with the
     largest offset from the slot grid, capped at the data end) is at least
     64 slots; in BF16X3 only such blocks, in F16X3 then every block."""
@@ -461,7 +461,7 @@ def bench_batch(args, tf, torch, prec):
     [500, 8000], gaps U[0, 0.3], grids U{100..1500}^2, 1..16 bins, rect and
     exp alternating) as one planned batch -- one captured graph with one
     persistent fused launch per step (and, in F16X3 / BF16X3, one matrix-core
-    launch for the long-band blocks of maps of 4 or more bins) -- against the same
+    launch for the exponential maps of 2 or more bins) -- against the same
     maps computed one map per call.  Returns the record of the step."""
     cands = [tfsynth.candidate(i) for i in range(64)]
     exp_present = exp_slots = rect_cells = 0

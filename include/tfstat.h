@@ -80,11 +80,11 @@ typedef enum {
  *            (three products: hi*hi + hi*lo + lo*hi) and FP32 accumulation
  *            (section 3, exponential case: every cell is one banded
  *            contraction over the SFTs, shared by all bins), for
- *            exponential-window maps of 4 or more bins on any t0 grid, and
+ *            exponential-window maps of 2 or more bins on any t0 grid, and
  *            for shape windows whose t0 rows fall on consecutive slots with
  *            one common offset.  Blocks of 8 taus whose shortest band is
- *            under 64 slots, maps of fewer bins and other shape-window
- *            grids run the FP32 sums.  bf16 hi + lo keeps 16 significant
+ *            under 64 slots, one-bin exponential maps and other
+ *            shape-window grids run the FP32 sums.  bf16 hi + lo keeps 16 significant
  *            bits per operand (relative residual up to 2^-17), so 2F can
  *            miss a 1e-4 relative bound on a few cells of badly conditioned
  *            windows; F16X3 meets it.  The first call on an atoms set builds

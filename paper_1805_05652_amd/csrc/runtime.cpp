@@ -253,9 +253,12 @@ enum { NK = TFSTAT_K_COUNT };
 constexpr int kMfmaTaus = 8;       // taus per matrix-core work item
 inline int32_t abc_pitch(int32_t n_tau) { return (n_tau + kMfmaTaus - 1) / kMfmaTaus * kMfmaTaus; }
 constexpr int kMfmaMinBand = 64;   // shorter bands stay on the VALU path
-// Exponential BF16X3 maps with fewer bins run the FP32 path: a matrix-core
-// column tile holds 16 bins, and with few bins the VALU sums cost less.
-constexpr int kMfmaMinBins = 4;
+// Exponential one-bin maps run the FP32 path: there each wave-uniform weight
+// serves 64 rows' sums (about 0.35 ns per cell*SFT on the 1-bin workload),
+// while the matrix-core form makes a weight per row, tau and slot (about
+// 0.44 ns per cell*SFT for any bin count up to 16 on the uneven batch); from
+// two bins on the matrix cores are faster.
+constexpr int kMfmaMinBins = 2;
 // Tiling threshold of the exponential VALU sums (tfstat_tiling_config):
 // kRunsAuto sends a map to the runs form when its median 64-row tile spans
 // more slots than one LDS stage can stage in rounds of kExpMinStageRound.

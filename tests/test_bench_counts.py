@@ -91,7 +91,7 @@ def test_work_counts_brute_force():
 def test_mfma_cells_blocks():
     """The matrix-core share counts exactly the tau blocks of 8 whose
     shortest band (ceil(3 tau / T_sft) slots for rows on slot starts) is at
-    least 64, for maps of at least 4 bins; fewer bins run on the VALU."""
+    least 64, for maps of at least 2 bins; one-bin maps run on the VALU."""
     atoms = _gapless(600, n_bins=5)
     tau = np.concatenate([np.full(8, 30 * T), np.full(8, 21 * T), [21 * T + 1] * 7 + [10 * T],
                           np.full(3, 40 * T)]).astype(np.int64)
@@ -101,7 +101,7 @@ def test_mfma_cells_blocks():
     want = bench.work_counts(atoms, tfsynth.list_window("exp", win.t0, tau[keep]))[0]
     assert bench.mfma_cells(atoms, win) == want
     assert 0 < want < bench.work_counts(atoms, win)[0]
-    assert bench.mfma_cells(_gapless(600, n_bins=3), win) == 0
+    assert bench.mfma_cells(_gapless(600, n_bins=1), win) == 0
     assert bench.mfma_cells(atoms, tfsynth.list_window("rect", win.t0, tau)) == 0
     # F16X3: every block of a map that has a long one; none without one
     assert bench.mfma_cells(atoms, win, "f16x3") == bench.work_counts(atoms, win)[0]

@@ -335,8 +335,8 @@ def test_timed_run_matches_graph_run(ctx):
 
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 def test_matrix_batch_against_oracle_and_fmap(ctx, prec):
-    """A matrix-core batch of uneven candidates (1-24 bins: maps of 4 or more
-    bins on the matrix cores, the others on FP32 tiles; rect maps; linspace
+    """A matrix-core batch of uneven candidates (1-24 bins: exponential maps
+    of 2 or more bins on the matrix cores, one-bin maps on FP32 tiles; rect maps; linspace
     grids): every map against the oracle and bit-identical to tfstat_fmap of
     the same map in the same precision, autotuned and forced to the default
     build."""

@@ -401,13 +401,13 @@ def _kernel_launches(ctx, fn):
 
 
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
-@pytest.mark.parametrize("case", ["linspace", "stride7", "before_after", "bins5", "bins37", "bins3_valu",
+@pytest.mark.parametrize("case", ["linspace", "stride7", "before_after", "bins5", "bins37", "bins1_valu", "bins3",
                                   "one_row_tile", "long_and_short", "scaled", "bins70", "bins64_stride3"])
 def test_matrix_any_grid(ctx, case, prec):
     """Matrix cores for exponential windows on any t0 grid (weights computed
     per row): linspace rows with their own offsets, rows 7 slots apart, rows
     before and after the data, ragged bin counts (partial 16-bin column
-    tiles), a map of fewer than 4 bins (FP32 path), a single partial row
+    tiles), a one-bin map (FP32 path) and a three-bin one, a single partial row
     tile, tau blocks with short bands beside long ones (BF16X3: FP32 F-only
     tiles; F16X3: matrix cores too),
     and data far outside the half-precision range with one all-zero bin
@@ -416,7 +416,7 @@ def test_matrix_any_grid(ctx, case, prec):
     last group of one column tile and three waves without one).
     Every cell and the per-bin results against the oracle."""
     _case("%s any grid %s" % (prec, case))
-    n_bins = {"bins5": 5, "bins37": 37, "bins3_valu": 3, "bins70": 70, "bins64_stride3": 64}.get(case, 24)
+    n_bins = {"bins5": 5, "bins37": 37, "bins1_valu": 1, "bins3": 3, "bins70": 70, "bins64_stride3": 64}.get(case, 24)
     atoms = tfsynth.make_atoms(811, 1400, 0.12, n_bins=n_bins,
                                injections=[tfsynth.Injection(min(4, n_bins - 1), "exp", 300 * T, 60 * T, 1.0)])
     if case == "scaled":
@@ -428,7 +428,7 @@ def test_matrix_any_grid(ctx, case, prec):
         fb[7] = 0.0
         atoms = dataclasses.replace(atoms, fa=fa, fb=fb, a2=atoms.a2 * 2.0 ** 40, b2=atoms.b2 * 2.0 ** 40,
                                     ab=atoms.ab * 2.0 ** 40)
-    if case in ("linspace", "bins5", "bins37", "bins3_valu", "scaled", "bins70"):
+    if case in ("linspace", "bins5", "bins37", "bins1_valu", "bins3", "scaled", "bins70"):
         win = tfsynth.linspace_grid(atoms, "exp", 260, 110)
     elif case == "bins64_stride3":
         win = tfsynth.regular_window("exp", 50 * T + 3, 3 * T, 150, 2 * T, 4 * T + 9, 75)
@@ -447,7 +447,7 @@ def test_matrix_any_grid(ctx, case, prec):
         ref = oracle.fmap_atoms(atoms, win)
         err = check_map(twoF.cpu().numpy(), ref, TOL[prec])
         check_results(res, ref, win, TOL[prec])
-        assert (prof["mfma"][0] > 0) == (case != "bins3_valu"), prof["mfma"]
+        assert (prof["mfma"][0] > 0) == (case != "bins1_valu"), prof["mfma"]
         # the same map again: bitwise repeatable
         res2, _ = ctx.fmap(aid, win, prec)
         assert res2 == res
