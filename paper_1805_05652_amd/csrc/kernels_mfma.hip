@@ -480,6 +480,19 @@ struct RowsSmem {
 // (plus the F16 offset), far from the range where it would flush to zero.
 // EDGE: the step may hold slots outside the lane's window [0, L), which
 // weigh 0.
+// w - h with h the low (sub_half_lo) or high (sub_half_hi) IEEE half of the
+// packed pair hb: one v_fma_mix_f32 (h * -1 + w, the half widened exactly).
+__device__ inline float sub_half_lo(float w, unsigned hb) {
+    float r;
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hb), "v"(w));
+    return r;
+}
+__device__ inline float sub_half_hi(float w, unsigned hb) {
+    float r;
+    asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hb), "v"(w));
+    return r;
+}
+
 template <bool EDGE, bool F16>
 __device__ __attribute__((always_inline)) inline void rows_weights(int d0, float cT, float cD, float rho, int L,
                                                                  u32x4 &h, u32x4 &l) {
@@ -499,12 +512,13 @@ __device__ __attribute__((always_inline)) inline void rows_weights(int d0, float
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         if constexpr (F16) {
-            // hi by the packing conversion (round toward zero), its value
-            // back from the packed halves, lo from the same rounded weights
+            // hi by the packing conversion (round toward zero); w - hi, exact
+            // in FP32, from the packed half and the same rounded weight in
+            // one mixed-precision FMA each; lo its packing conversion
             const auto h2 = __builtin_amdgcn_cvt_pkrtz(w[2 * p], w[2 * p + 1]);
-            const float h0 = (float)h2[0], h1 = (float)h2[1];
-            const auto l2 = __builtin_amdgcn_cvt_pkrtz(w[2 * p] - h0, w[2 * p + 1] - h1);
-            h[p] = __builtin_bit_cast(unsigned, h2);
+            const unsigned hb = __builtin_bit_cast(unsigned, h2);
+            const auto l2 = __builtin_amdgcn_cvt_pkrtz(sub_half_lo(w[2 * p], hb), sub_half_hi(w[2 * p + 1], hb));
+            h[p] = hb;
             l[p] = __builtin_bit_cast(unsigned, l2);
         } else {
             typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
