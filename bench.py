@@ -65,7 +65,8 @@ def mfma_taus(atoms, win, prec="bf16x3", taus_per_block: int = 8, min_band: int 
     windows of at least 2 bins with a block of 8 consecutive taus whose
     shortest band (the slots of [t0, t0 + 3 tau) over the row with the
     largest offset from the slot grid, capped at the data end) is at least
-    64 slots; in BF16X3 only such blocks, in F16X3 then every block."""
+    64 slots; the matrix cores take the blocks whose shortest band is at
+    least 64 slots (BF16X3) or 24 slots (F16X3)."""
     keep = np.zeros(win.n_tau, dtype=bool)
     if win.kind != "exp" or atoms.n_bins < min_bins:
         return keep
@@ -78,11 +79,16 @@ def mfma_taus(atoms, win, prec="bf16x3", taus_per_block: int = 8, min_band: int 
     dmax = int(delta.max())
     lcol = np.where(span > dmax, -(-(span - dmax) // T_), 0)
     lcol = np.minimum(lcol, cap)
+    long_block = False
     for b0 in range(0, win.n_tau, taus_per_block):
         if lcol[b0:b0 + taus_per_block].min() >= min_band:
+            long_block = True
+    if not long_block:
+        return keep
+    band = 24 if prec == "f16x3" else min_band
+    for b0 in range(0, win.n_tau, taus_per_block):
+        if lcol[b0:b0 + taus_per_block].min() >= band:
             keep[b0:b0 + taus_per_block] = True
-    if prec == "f16x3" and keep.any():
-        keep[:] = True
     return keep
 
 

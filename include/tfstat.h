@@ -94,9 +94,10 @@ typedef enum {
  *            the data columns scaled by powers of two (one per bin and
  *            component, undone exactly in FP64) and the weights by 2^4, so
  *            that no part leaves the half-precision range.  Exponential
- *            windows only: shape windows run the FP32 sums.  A map that
- *            has a block of 8 taus with every band at least 64 slots long
- *            runs all its blocks on the matrix cores, short ones included.
+ *            windows only: shape windows run the FP32 sums.  In a map that
+ *            has a block of 8 taus with every band at least 64 slots long,
+ *            the blocks whose shortest band is at least 24 slots run on the
+ *            matrix cores (shorter windows amplify the parts' rounding).
  *            Builds its own planes on first use (16 bytes per slot and bin).
  *   RECUR64: exponential windows on a regular t0 grid whose step is a whole
  *            number of SFT slots (at most 64): every sum in FP64 by the exact

@@ -252,7 +252,8 @@ enum { NK = TFSTAT_K_COUNT };
 
 constexpr int kMfmaTaus = 8;       // taus per matrix-core work item
 inline int32_t abc_pitch(int32_t n_tau) { return (n_tau + kMfmaTaus - 1) / kMfmaTaus * kMfmaTaus; }
-constexpr int kMfmaMinBand = 64;   // shorter bands stay on the VALU path
+constexpr int kMfmaMinBand = 64;      // BF16X3: shorter bands stay on the VALU path
+constexpr int kMfmaMinBandF16 = 24;   // F16X3: the same for its finer parts
 // Exponential one-bin maps run the FP32 path: there each wave-uniform weight
 // serves 64 rows' sums (about 0.35 ns per cell*SFT on the 1-bin workload),
 // while the matrix-core form makes a weight per row, tau and slot (about
@@ -477,12 +478,13 @@ void plan_job(Job &j) {
             }
         }
         if (j.use_mfma) {
-            // BF16X3: a block with any short band stays on the FP32 VALU
-            // path: short windows carry little work and the worst
-            // conditioning, which would amplify the ~2^-16 error of the bf16
-            // split operands.  F16X3 (~2^-22, between FP32 and that) takes
-            // every block of the map onto the matrix cores.
-            const int32_t min_band = j.prec == TFSTAT_PREC_F16X3 ? 0 : kMfmaMinBand;
+            // a block with any short band stays on the FP32 VALU path: short
+            // windows carry little work and the worst conditioning, which
+            // amplifies the error of the split operands (~2^-16 for bf16,
+            // ~2^-22 for half precision: on windows of 3-7 SFTs F16X3 2F
+            // errors reach 5e-5 against FP32's 7e-6, and from 24 slots on
+            // they are at FP32's level)
+            const int32_t min_band = j.prec == TFSTAT_PREC_F16X3 ? kMfmaMinBandF16 : kMfmaMinBand;
             std::vector<int32_t> lv, lm;
             for (int32_t b : j.order) {
                 int32_t shortest = INT32_MAX;

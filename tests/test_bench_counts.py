@@ -103,10 +103,16 @@ def test_mfma_cells_blocks():
     assert 0 < want < bench.work_counts(atoms, win)[0]
     assert bench.mfma_cells(_gapless(600, n_bins=1), win) == 0
     assert bench.mfma_cells(atoms, tfsynth.list_window("rect", win.t0, tau)) == 0
-    # F16X3: every block of a map that has a long one; none without one
+    # F16X3: blocks whose bands are all at least 24 slots, in a map that has
+    # a block of 64 (here every block: its shortest band is 30)
     assert bench.mfma_cells(atoms, win, "f16x3") == bench.work_counts(atoms, win)[0]
     short = tfsynth.list_window("exp", win.t0, tau[8:24])
     assert bench.mfma_cells(atoms, short, "f16x3") == 0
+    # a block whose shortest band is 23 slots (3 tau = 22.67 T) stays off
+    tau23 = np.concatenate([np.full(8, 30 * T), np.full(8, 7 * T + 1000)]).astype(np.int64)
+    w23 = tfsynth.list_window("exp", win.t0, tau23)
+    assert bench.mfma_cells(atoms, w23, "f16x3") == \
+        bench.work_counts(atoms, tfsynth.list_window("exp", win.t0, tau23[:8]))[0]
 
 
 def test_mfma_taus_offsets_and_data_end():

@@ -371,6 +371,36 @@ def test_full_exp_256_bins_every_cell(ctx, exp256_oracle, prec):
     print("full exp 256 bins %s: max rel err %.3e over %d cells" % (prec, err, ref.size), flush=True)
 
 
+@pytest.mark.parametrize("case", ["mixed_spacing", "few_taus", "many_segments"])
+def test_abc_scan_rows(ctx, case):
+    """The A/B/C of matrix-core maps come from a scan of the row recurrence
+    (64 rows per chunk, several segments per tau).  Rows that share a first
+    slot, rows one slot and far apart (windows that end before the next row
+    starts), rows before the data and past its end, taus shorter than one
+    SFT, grids of 64 k +- 1 rows over several chunks and segments: every
+    cell's 2F and the per-bin results against the oracle (F16X3)."""
+    _case("abc scan " + case)
+    rng = np.random.default_rng({"mixed_spacing": 91, "few_taus": 92, "many_segments": 93}[case])
+    atoms = tfsynth.make_atoms(9100 + len(case), 900, 0.15, n_bins=5,
+                               injections=[tfsynth.Injection(2, "exp", 200 * T, 40 * T, 1.0)])
+    T0 = int(atoms.timestamps[0])
+    if case == "mixed_spacing":
+        # steps of 0 (same slot), a few seconds, one slot, and far apart
+        steps = rng.choice([7, 300, T, T + 11, 3 * T, 40 * T], size=192)
+        t0 = T0 - 30 * T + np.cumsum(steps)
+        tau = np.concatenate([[T // 3, T - 1], np.arange(2, 60, 3) * T + 17, [300 * T, 2000 * T]])
+    elif case == "few_taus":
+        t0 = T0 - 5 * T + np.arange(129) * (T // 2)
+        tau = np.array([5 * T, 70 * T + 3, 400 * T], dtype=np.int64)
+    else:
+        # 700 rows x 600 taus: segments of three 64-row chunks
+        t0 = T0 + 20 * T + np.arange(700) * T + 13
+        tau = np.arange(1, 601) * (T // 2)
+    win = tfsynth.list_window("exp", np.unique(t0.astype(np.int64)), tau.astype(np.int64))
+    _, _, err = run_and_check(ctx, atoms, win, "f16x3")
+    print("abc scan %s: %d rows, %d taus, max rel err %.3e" % (case, win.n_t0, win.n_tau, err), flush=True)
+
+
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 @pytest.mark.parametrize("case", ["offset", "tail", "sparse_rows"])
 def test_matrix_ragged(ctx, case, prec):
