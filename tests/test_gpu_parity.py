@@ -432,21 +432,24 @@ def _kernel_launches(ctx, fn):
 
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 @pytest.mark.parametrize("case", ["linspace", "stride7", "before_after", "bins5", "bins37", "bins1_valu", "bins3",
-                                  "one_row_tile", "long_and_short", "scaled", "bins70", "bins64_stride3"])
+                                  "one_row_tile", "long_and_short", "scaled", "bins70", "bins64_stride3",
+                                  "bins150", "bins520"])
 def test_matrix_any_grid(ctx, case, prec):
     """Matrix cores for exponential windows on any t0 grid (weights computed
     per row): linspace rows with their own offsets, rows 7 slots apart, rows
     before and after the data, ragged bin counts (partial 16-bin column
     tiles), a one-bin map (FP32 path) and a three-bin one, a single partial row
-    tile, tau blocks with short bands beside long ones (BF16X3: FP32 F-only
-    tiles; F16X3: matrix cores too),
+    tile, tau blocks with short bands beside long ones (FP32 F-only tiles),
     and data far outside the half-precision range with one all-zero bin
-    (the half-precision path's column scaling).  Maps of 64 and 70 bins take
+    (the half-precision path's column scaling).  Maps of 64 to 520 bins take
     the work items of four column tiles with shared weights (70 bins: a
-    last group of one column tile and three waves without one).
+    last group of one column tile and three waves without one; 70, 150 and
+    520 bins: 2, 3 and 9 column groups, each with its own order of work
+    items over the XCDs).
     Every cell and the per-bin results against the oracle."""
     _case("%s any grid %s" % (prec, case))
-    n_bins = {"bins5": 5, "bins37": 37, "bins1_valu": 1, "bins3": 3, "bins70": 70, "bins64_stride3": 64}.get(case, 24)
+    n_bins = {"bins5": 5, "bins37": 37, "bins1_valu": 1, "bins3": 3, "bins70": 70, "bins64_stride3": 64,
+              "bins150": 150, "bins520": 520}.get(case, 24)
     atoms = tfsynth.make_atoms(811, 1400, 0.12, n_bins=n_bins,
                                injections=[tfsynth.Injection(min(4, n_bins - 1), "exp", 300 * T, 60 * T, 1.0)])
     if case == "scaled":
@@ -462,6 +465,8 @@ def test_matrix_any_grid(ctx, case, prec):
         win = tfsynth.linspace_grid(atoms, "exp", 260, 110)
     elif case == "bins64_stride3":
         win = tfsynth.regular_window("exp", 50 * T + 3, 3 * T, 150, 2 * T, 4 * T + 9, 75)
+    elif case in ("bins150", "bins520"):
+        win = tfsynth.linspace_grid(atoms, "exp", 70, 40)
     elif case == "stride7":
         win = tfsynth.regular_window("exp", 333, 7 * T, 150, 2 * T, 5 * T + 17, 70)
     elif case == "before_after":
