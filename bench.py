@@ -27,7 +27,8 @@ The same JSON line also carries, unless --no-extras:
 Prints ONE JSON line.  Options:
   --gpus N       only 1 is supported (the path runs on one GPU)
   --steps K      timed steps (default 20)
-  --warmup W     untimed steps (default 3)
+  --warmup W     untimed steps (default 3; continued until 0.3 s of untimed
+                 work has run, so that the timed steps see settled clocks)
   --workload     exp1bin (default) | exp256 | rect | rect256 | batch
   --prec         fp32 (default) | fp64 | f16x3 | bf16x3 | recur64
   --no-extras, --no-cpu-baseline, --serve-seconds S (0 skips serving)
@@ -408,13 +409,29 @@ def no_gc():
         gc.enable()
 
 
+SETTLE_S = 0.3   # untimed work before the timed steps, so that the clocks have ramped
+
+
+def settle(step, warmup):
+    """The `warmup` untimed steps, continued until SETTLE_S seconds have
+    passed: a cold GPU runs its first milliseconds of work at lower clocks."""
+    import torch
+    t = time.perf_counter()
+    n = 0
+    while n < warmup or (time.perf_counter() - t < SETTLE_S and n < 100000):
+        step()
+        n += 1
+        if n % 16 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+
+
 def time_map(ctx, aid, atoms, win, prec, twoF, steps, warmup, workload):
     """Times `steps` calls of tfstat_fmap (map written to twoF when given)
-    after `warmup` untimed ones; per-kernel device times from HIP events."""
+    after `warmup` untimed ones (at least SETTLE_S seconds of them);
+    per-kernel device times from HIP events."""
     import torch
-    for _ in range(warmup):
-        ctx.fmap(aid, win, prec, out=twoF)
-    torch.cuda.synchronize()
+    settle(lambda: ctx.fmap(aid, win, prec, out=twoF), warmup)
     ctx.profile_reset()
     ctx.profile(True)
     torch.cuda.synchronize()
@@ -492,9 +509,7 @@ def bench_batch(args, tf, torch, prec):
     t = time.perf_counter()
     batch = ctx.batch(items, prec, tune=not args.no_tune)
     plan_s = time.perf_counter() - t
-    for _ in range(args.warmup):
-        batch.run()
-    torch.cuda.synchronize()
+    settle(batch.run, args.warmup)
     step_ms, step_graph_ms = [], []
     with no_gc():
         t0 = time.perf_counter()
@@ -633,7 +648,8 @@ def main(argv=None):
             return 2
         b = bench_batch(args, tf, torch, args.prec)
         out = {"metric": metric, "value": b.pop("value"), "unit": b.pop("unit"), "n_gpus": 1,
-               "steps": args.steps, "warmup": args.warmup, "ms_per_step": b.pop("ms_per_step"),
+               "steps": args.steps, "warmup": args.warmup, "settle_s": SETTLE_S,
+               "ms_per_step": b.pop("ms_per_step"),
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                "dtype": DTYPES[args.prec],
                "data": "synthetic",
@@ -656,6 +672,7 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_s": SETTLE_S,
         "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
