@@ -664,16 +664,13 @@ constexpr int exp_waves() {
 template <typename XT, int R, int BG, int MODE = kModeAll>
 __global__ __launch_bounds__(kThreads, (exp_waves<XT, R, BG, MODE>())) void exp_valu_kernel(ExpValuParams p) {
     __shared__ ExpSmem<XT, R, BG> sm;
-    // XCD-aware task order: workgroup b runs on XCD b % 8.  Blocks of tau
-    // (sorted largest band first) are dealt round-robin to the XCDs and all
-    // row tiles of a block stay on one XCD, so its weight table is fetched
-    // into one L2 only.
-    const int bid = blockIdx.x;
-    const int xcd = bid & 7;
-    const int slot = bid >> 3;
-    const int q = (slot / p.n_row_tiles) * 8 + xcd;
+    // XCD-aware task order (unit_decode): blocks of tau (sorted largest band
+    // first), each with its row tiles, so a block's weight table is fetched
+    // into one L2 only
+    int q, row_tile;
+    unit_decode(blockIdx.x, p.n_list, p.n_row_tiles, q, row_tile);
     if (q >= p.n_list) return;
-    exp_tile<XT, R, BG, MODE>(p, sm, q, slot % p.n_row_tiles, blockIdx.y);
+    exp_tile<XT, R, BG, MODE>(p, sm, q, row_tile, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -997,13 +994,11 @@ constexpr bool runs_sw() {
 template <typename XT, int R, int BG>
 __global__ __launch_bounds__(kThreads, (runs_waves<XT, R, BG>())) void exp_runs_kernel(ExpValuParams p) {
     __shared__ RunSmem<XT, R, BG, 8, runs_sw<XT, R, BG>()> sm;
-    // groups of four tau blocks, dealt round-robin to the XCDs
-    const int bid = blockIdx.x;
-    const int xcd = bid & 7;
-    const int slot = bid >> 3;
-    const int g = (slot / p.n_row_tiles) * 8 + xcd;
+    // groups of four tau blocks as the units of the XCD-aware order
+    int g, row_tile;
+    unit_decode(blockIdx.x, (p.n_list + kWaves - 1) / kWaves, p.n_row_tiles, g, row_tile);
     if (g * kWaves >= p.n_list) return;
-    exp_runs_tile<XT, R, BG, 8, runs_sw<XT, R, BG>()>(p, sm, g * kWaves, slot % p.n_row_tiles, blockIdx.y);
+    exp_runs_tile<XT, R, BG, 8, runs_sw<XT, R, BG>()>(p, sm, g * kWaves, row_tile, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1570,8 +1565,7 @@ void exp_valu_config(int prec, int n_bins, int *R, int *BG) {
 
 hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s) {
     if (p.n_list <= 0) return hipSuccess;
-    const int groups = (p.n_list + 7) / 8;
-    const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), 1u);
+    const dim3 grid((unsigned)unit_grid(p.n_list, p.n_row_tiles), 1u);
     hipLaunchKernelGGL((exp_valu_kernel<float, 8, 1, kModeAbc>), grid, dim3(kThreads), 0, s, p);
     return hipGetLastError();
 }
@@ -1579,8 +1573,7 @@ hipError_t launch_exp_abc(const ExpValuParams &p, hipStream_t s) {
 hipError_t launch_exp_fonly(const ExpValuParams &p, int n_groups, hipStream_t s) {
     if (p.n_list <= 0 || n_groups <= 0) return hipSuccess;
     if (p.bin_base + (n_groups - 1) * 4 >= p.at.n_bins || !p.abc_out) return hipErrorInvalidValue;
-    const int groups = (p.n_list + 7) / 8;
-    const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), (unsigned)n_groups);
+    const dim3 grid((unsigned)unit_grid(p.n_list, p.n_row_tiles), (unsigned)n_groups);
     hipLaunchKernelGGL((exp_valu_kernel<float, 8, 4, kModeF>), grid, dim3(kThreads), 0, s, p);
     return hipGetLastError();
 }
@@ -1588,8 +1581,7 @@ hipError_t launch_exp_fonly(const ExpValuParams &p, int n_groups, hipStream_t s)
 hipError_t launch_exp_valu(const ExpValuParams &p, int prec, int R, int BG, int n_groups, hipStream_t s) {
     if (p.n_list <= 0 || n_groups <= 0) return hipSuccess;
     if (p.bin_base + (n_groups - 1) * BG >= p.at.n_bins) return hipErrorInvalidValue;
-    const int groups = (p.n_list + 7) / 8;
-    const dim3 grid((unsigned)(8 * groups * p.n_row_tiles), (unsigned)n_groups);
+    const dim3 grid((unsigned)unit_grid(p.n_list, p.n_row_tiles), (unsigned)n_groups);
     if (prec == 0 && R == 4 && BG == 1)
         hipLaunchKernelGGL((exp_valu_kernel<double, 4, 1>), grid, dim3(kThreads), 0, s, p);
     else if (prec == 1 && R == 8 && BG == 1)
@@ -1609,7 +1601,7 @@ hipError_t launch_exp_runs(const ExpValuParams &p, int prec, int R, int BG, int 
     if (p.n_list <= 0 || n_groups <= 0) return hipSuccess;
     if (p.bin_base + (n_groups - 1) * BG >= p.at.n_bins) return hipErrorInvalidValue;
     const int n_q = (p.n_list + kWaves - 1) / kWaves;
-    const dim3 grid((unsigned)(8 * ((n_q + 7) / 8) * p.n_row_tiles), (unsigned)n_groups);
+    const dim3 grid((unsigned)unit_grid(n_q, p.n_row_tiles), (unsigned)n_groups);
     if (prec == 0 && R == 4 && BG == 1)
         hipLaunchKernelGGL((exp_runs_kernel<double, 4, 1>), grid, dim3(kThreads), 0, s, p);
     else if (prec == 1 && R == 8 && BG == 1)

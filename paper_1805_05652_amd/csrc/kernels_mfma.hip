@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
     // dealt round-robin to the XCDs, so an XCD streams only its own bins'
     // bf16 planes; its tasks run block by block (largest band first), row
     // tile by row tile, so one block's weight tables are reused while hot.
-    // With fewer column tiles, the blocks are dealt to the XCDs instead.
+    // With fewer column tiles, the blocks are the units of unit_decode.
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
     const int slot = bid >> 3;
@@ -190,10 +190,9 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
         col_tile = (rem % cpx) * 8 + xcd;
         if (q >= p.n_blocks || col_tile >= p.n_col_tiles) return;
     } else {
-        const int per_block = p.n_row_tiles * p.n_col_tiles;
-        q = (slot / per_block) * 8 + xcd;
+        int rem;
+        unit_decode(bid, p.n_blocks, p.n_row_tiles * p.n_col_tiles, q, rem);
         if (q >= p.n_blocks) return;
-        const int rem = slot % per_block;
         row_tile = rem / p.n_col_tiles;
         col_tile = rem % p.n_col_tiles;
     }
@@ -1076,7 +1075,7 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_item(PP &p, Mfma
 
 // XCD-aware task order: column items dealt to the XCDs when there are at
 // least 8 of them, one per XCD when there are 2 or 4, otherwise the tau
-// blocks.
+// blocks as the units of unit_decode.
 template <bool F16>
 __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpMfmaRowsParams p) {
     __shared__ MfmaRowsSmem sm;
@@ -1102,10 +1101,9 @@ __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpM
         row_tile = slot % p.n_row_tiles;
         if (q >= p.n_blocks) return;
     } else {
-        const int per_block = p.n_row_tiles * n_col;
-        q = (slot / per_block) * 8 + xcd;
+        int rem;
+        unit_decode(bid, p.n_blocks, p.n_row_tiles * n_col, q, rem);
         if (q >= p.n_blocks) return;
-        const int rem = slot % per_block;
         row_tile = rem / n_col;
         col_item = rem % n_col;
     }
@@ -1192,8 +1190,7 @@ hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s) {
         const int cpx = (p.n_col_tiles + 7) / 8;
         grid = (unsigned)(8 * p.n_blocks * p.n_row_tiles * cpx);
     } else {
-        const int groups = (p.n_blocks + 7) / 8;
-        grid = (unsigned)(8 * groups * p.n_row_tiles * p.n_col_tiles);
+        grid = (unsigned)unit_grid(p.n_blocks, p.n_row_tiles * p.n_col_tiles);
     }
     hipLaunchKernelGGL(exp_mfma_kernel, dim3(grid), dim3(256), 0, s, p);
     return hipGetLastError();
@@ -1211,8 +1208,7 @@ hipError_t launch_exp_mfma_rows(const ExpMfmaRowsParams &p, hipStream_t s) {
         const int r = 8 / n_col;
         grid = (unsigned)(8 * ((p.n_blocks + r - 1) / r) * p.n_row_tiles);
     } else {
-        const int groups = (p.n_blocks + 7) / 8;
-        grid = (unsigned)(8 * groups * p.n_row_tiles * n_col);
+        grid = (unsigned)unit_grid(p.n_blocks, p.n_row_tiles * n_col);
     }
     if (p.f16)
         hipLaunchKernelGGL(exp_mfma_rows_kernel<true>, dim3(grid), dim3(256), 0, s, p);

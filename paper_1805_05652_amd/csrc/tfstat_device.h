@@ -132,6 +132,27 @@ struct ExpMfmaRowsParams {
     Partial *part;
 };
 
+// XCD-aware task order.  Workgroup b runs on XCD b % 8, and each XCD has its
+// own L2.  With 8 or more units of work (tau blocks, or groups of them),
+// the units are dealt round-robin to the XCDs and all per_unit tasks of a
+// unit (row tiles, column tiles) stay on its XCD, so the unit's tables are
+// fetched into one L2; with fewer units that order would leave XCDs idle,
+// and the tasks run in plain order instead.
+__host__ __device__ inline int64_t unit_grid(int n_units, int per_unit) {
+    return n_units >= 8 ? (int64_t)8 * ((n_units + 7) / 8) * per_unit : (int64_t)n_units * per_unit;
+}
+// Unit and task within the unit of workgroup bid (unit >= n_units: none).
+__host__ __device__ inline void unit_decode(int bid, int n_units, int per_unit, int &unit, int &task) {
+    if (n_units >= 8) {
+        const int slot = bid >> 3;
+        unit = (slot / per_unit) * 8 + (bid & 7);
+        task = slot % per_unit;
+    } else {
+        unit = bid / per_unit;
+        task = bid % per_unit;
+    }
+}
+
 // Maps of at least this many 16-bin column tiles take their matrix-core
 // work items four column tiles at a time (one wave each, weights shared).
 constexpr int kSwMinColTiles = 4;
