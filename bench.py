@@ -431,12 +431,14 @@ def time_map(ctx, aid, atoms, win, prec, twoF, steps, warmup, workload):
     after `warmup` untimed ones (at least SETTLE_S seconds of them);
     per-kernel device times from HIP events."""
     import torch
-    settle(lambda: ctx.fmap(aid, win, prec, out=twoF), warmup)
-    ctx.profile_reset()
-    ctx.profile(True)
-    torch.cuda.synchronize()
     res = None
+    ctx.profile(True)
+    # the collector's pass happens before the warmup, so that no idle gap
+    # (clocks fall back within tens of milliseconds) separates the warmup
+    # from the timed steps
     with no_gc():
+        settle(lambda: ctx.fmap(aid, win, prec, out=twoF), warmup)
+        ctx.profile_reset()
         t0 = time.perf_counter()
         for _ in range(steps):
             res, _ = ctx.fmap(aid, win, prec, out=twoF)
@@ -509,9 +511,9 @@ def bench_batch(args, tf, torch, prec):
     t = time.perf_counter()
     batch = ctx.batch(items, prec, tune=not args.no_tune)
     plan_s = time.perf_counter() - t
-    settle(batch.run, args.warmup)
     step_ms, step_graph_ms = [], []
     with no_gc():
+        settle(batch.run, args.warmup)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             ts = time.perf_counter()
