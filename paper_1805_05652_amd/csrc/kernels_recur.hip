@@ -8,8 +8,8 @@
 // every channel obeys
 //   U_m = sum_{d<s} rho^d x[k_m + d] + rho^s U_{m+1} - sum_{d=L}^{L+s-1} rho^d x[k_m + d],
 // so a map costs O(N_t0 + L) per channel instead of the O(N_t0 L) direct
-// sums that section 3 describes ("no such simple trick" exists across tau;
-// along t0 it does).  A, B, C use rho^2, F_a, F_b use rho; the common row
+// sums that section 3 describes (the paper finds no reuse of the sums
+// across tau; along t0 there is one).  A, B, C use rho^2, F_a, F_b use rho; the common row
 // scale exp(-delta/tau) (squared for A, B, C) is applied at the end.
 //
 // One wave per (tau, group of BG bins).  Lane j owns a segment of G rows.
