@@ -449,25 +449,14 @@ __global__ __launch_bounds__(256, TFS_MFMA_WAVES) void exp_mfma_kernel(ExpMfmaPa
 // ---------------------------------------------------------------------------
 // Any t0 grid: weights computed in registers.
 //
-// Work item: 64 t0 rows x 16 bins x 8 taus, one wave per 16 rows, in two
-// passes of 4 taus.  Each wave runs its own K range, from its first row's
-// slot to the furthest band end of its rows, so rows may be any distance
-// apart.  The A operand of one K step is the lane's 8 weights
+// Eight weights of one K step of a lane are
 //   w_j = exp(-(t_{k+j} - t0_m) / tau) = 2^((d + j) c_T + c_delta),
 //   d = k - k0_m, c_T = -T log2(e) / tau, c_delta = -delta_m log2(e) / tau,
 // zero outside the row's window (0 <= d + j < L_m: the SFT start times in
 // [t0_m, t0_m + 3 tau)), generated as one exp2 and 7 products by
-// exp(-T / tau), then split into bf16 hi + lo.  The row scale and the exact
-// band end of every row are in the weights, so no correction terms remain;
-// A, B, C (FP64, the same weights squared) come from the VALU A/B/C pass.
+// exp(-T / tau), then split into hi + lo parts.  A, B, C (FP64, the same
+// weights squared) come from the A/B/C scan.
 // ---------------------------------------------------------------------------
-struct RowsSmem {
-    double abc[4][16][kBlk][3];   // per wave: its rows' folded A, B, C of the block
-    Red wred[4][16];
-    // per wave: 2F of its 16 rows x 16 bins x 8 taus, written to the map
-    // once both passes are done (one padding float per row and bin)
-    float out[4][16][16][kBlk + 1];
-};
 
 // The lane's 8 weights of one K step as hi and lo parts (lo = part(w - hi),
 // w - hi exact before its own rounding): bf16 (round to nearest even) or,
@@ -550,230 +539,249 @@ __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// ---------------------------------------------------------------------------
+// Maps of fewer than kSwMinColTiles column tiles: the transposed product.
+// For one bin, one tau and data component c,
+//   F_c[m] = s_m sum_d g[d] x_c[k0_m + d],   g[d] = exp(-d T_sft / tau),
+//   s_m = exp(-delta_m / tau),
+// with k0_m the row's first slot on the slot grid (extended before the
+// data, so that delta_m lies in [0, T_sft)).  The weights g depend on the
+// tau and the lag only, so they are the B operand (32 lags x 16 taus per
+// K step) that a wave shares among all its rows, and the A operand gathers
+// the data: row 4 i + c of a 16-row tile is component c of the tile's cell
+// i, and its 8 lags of a K step are the 8 slots from k0_m + d.  A window
+// holds the lags below L_m = ceil((3 tau - delta_m) / T_sft), which is
+// L = ceil(3 tau / T_sft) or L - 1; B holds the lags below L, and a cell
+// whose band is L - 1 has the product of lag L - 1 taken off in the
+// finalize.  Every product's columns are taus and its rows cells, so the
+// matrix cores do no work on absent bins, and a weight is made once per
+// 16 cells.
+//
+// Work item: 64 rows (16 per wave, as four 16-row tiles of 4 cells) x one
+// bin x kCellsBlocks blocks of 8 taus (kCellsNT tiles of 16 taus; the
+// blocks of one item are consecutive in the block list, which runs from
+// the longest band down, and a tile sits out the K steps past its own
+// longest band).  Data planes: [copy 2][component 4][bin][kpc], slot k of
+// copy par at element k + 8 + par, so that the 8 slots from any k are one
+// 16-byte load from a 4-byte aligned address in the copy of k's parity;
+// slots outside [0, K) read as zero (the 8 + par elements in front and the
+// pad behind K are zero, and loads that would start before that pad or at
+// or after K are sent beyond the buffer's end, which reads zero).
+// ---------------------------------------------------------------------------
+struct CellsSmem {
+    Red wred[4];
+};
+
 template <bool F16, typename PP>
-__device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, RowsSmem &sm, int q, int row_tile,
-                                                                   int col_tile) {
+__device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, CellsSmem &sm, int g, int row_tile,
+                                                                    int bin) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nb = p.blk_list[q];
-    const int tile = nb * p.n_row_tiles + row_tile;
+    const int lrow = lane & 15;   // A row / B and C column within the 16 tile
+    const int kg = lane >> 4;     // K group of 8; C rows 4 kg .. 4 kg + 3
     const int n_t0 = p.n_t0;
+    const int K = p.K;
     const int m_w = row_tile * 64 + 16 * wave;   // first row of this wave
-    const int lrow = lane & 15;                  // A row / C column within the 16 tile
-    const int kg = lane >> 4;                    // K group of 8
-    const int bin = col_tile * 16 + lrow;
-    const bool bin_ok = bin < p.n_bins;
+    const int q0 = g * kCellsBlocks;
+    const int nblk = min(kCellsBlocks, p.n_blocks - q0);
     const int64_t T = p.t_sft;
 
-    // the lane's A row (rows past the grid repeat the last one; never written)
-    const RowPlan ra = p.rows[min(m_w + lrow, n_t0 - 1)];
-    const int k_first = __builtin_amdgcn_readfirstlane(p.rows[min(m_w, n_t0 - 1)].k0);
-
-    // planes [4][kp / 32][bins16][32]: lane's 8 slots of step kb for its bin.
-    // One buffer resource per component and part (scalar registers), the
-    // step's offset in a scalar, the lane's own offset in a vector register:
-    // no vector address arithmetic per load (component planes are < 2^31
-    // bytes, which the planner checks).
-    const uint32_t comp_bytes = (uint32_t)p.bins16 * (uint32_t)p.kp * 2u;
-    const uint32_t step_bytes = (uint32_t)p.bins16 * 64u;
-    const uint32_t lane_off = (uint32_t)((col_tile * 16 + lrow) * 32 + 8 * kg) * 2u;
-    __amdgpu_buffer_rsrc_t rh[4], rl[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        rh[c] = plane_rsrc(p.xhi + (size_t)c * p.bins16 * p.kp, comp_bytes);
-        rl[c] = plane_rsrc(p.xlo + (size_t)c * p.bins16 * p.kp, comp_bytes);
-    }
-    auto load_b = [&](int kb, u32x4 *h, u32x4 *l) {
-        const int so = (int)((uint32_t)(kb >> 5) * step_bytes);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            h[c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh[c], (int)lane_off, so, 0));
-            l[c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl[c], (int)lane_off, so, 0));
+    // B side: the lane's tau (column lrow) of each 16-tau tile; a column
+    // without a tau has weights exp2(-inf) = 0
+    float cT[kCellsNT], cD[kCellsNT], rho[kCellsNT];
+    int L[kCellsNT];
+    int Lt[kCellsNT];        // the tile's longest band (wave-uniform; 0: no tau)
+    int Lmin = 1 << 30;      // shortest band of the lane's taus
+    // the lane's tau of tile t (-1: none)
+    auto tau_of = [&](int t) {
+        const int qb = 2 * t + (lrow >> 3);
+        int n = -1;
+        if (qb < nblk) {
+            n = p.blk_list[q0 + qb] * kBlk + (lrow & 7);
+            if (n >= p.n_tau) n = -1;
         }
+        return n;
     };
-
-    // A, B, C of the wave's 16 rows x 8 taus, with 2 / D folded in, into the
-    // wave's own LDS region (rows of abc_cell hold whole blocks)
-    for (int e = lane; e < 16 * kBlk; e += 64) {
-        const int r = e / kBlk, t = e % kBlk;
-        const int m = min(m_w + r, n_t0 - 1);
-        const double *src = p.abc_cell + ((size_t)m * p.abc_pitch + (size_t)nb * kBlk + t) * 3;
-        double abc[3] = {src[0], src[1], src[2]};
-        fold_abc(abc, 1.0);
-        sm.abc[wave][r][t][0] = abc[0];
-        sm.abc[wave][r][t][1] = abc[1];
-        sm.abc[wave][r][t][2] = abc[2];
-    }
-
-    Red red = red_empty();
-#pragma unroll 1
-    for (int half = 0; half < kBlk / kNT; ++half) {
-        const int t0 = half * kNT;
-        // the pass's weight constants for the lane's row
-        float cT[kNT], cD[kNT], rho[kNT];
-        int L[kNT];
 #pragma unroll
-        for (int t = 0; t < kNT; ++t) {
-            const int n = min(nb * kBlk + t0 + t, p.n_tau - 1);
+    for (int t = 0; t < kCellsNT; ++t) {
+        const int n = tau_of(t);
+        if (n >= 0) {
             const int64_t tau = p.tau[n];
             const double inv = 1.4426950408889634 / (double)tau;
             cT[t] = (float)(-(double)T * inv);
-            cD[t] = (float)(-(double)ra.delta * inv) + (F16 ? (float)kF16WeightExp : 0.f);
+            cD[t] = F16 ? (float)kF16WeightExp : 0.f;
             rho[t] = exp2f(cT[t]);
-            const int64_t span = 3 * tau;
-            L[t] = span > ra.delta ? (int)min((span - ra.delta + T - 1) / T, (int64_t)1 << 30) : 0;
+            L[t] = (int)min((3 * tau + T - 1) / T, (int64_t)1 << 30);
+            Lmin = min(Lmin, L[t]);
+        } else {
+            cT[t] = 0.f;
+            cD[t] = -INFINITY;
+            rho[t] = 0.f;
+            L[t] = 0;
         }
-        // K range of the wave: its first row's slot to the furthest band end
-        // of its rows (taus increase within a block: the pass's last is the
-        // longest), rounded to an even number of 32-slot steps (B plane
-        // columns kp_data .. kp are zero)
-        int kend = (int)min((int64_t)ra.k0 + L[kNT - 1], (int64_t)p.kp_data);
-        // steps that hold no window edge of any lane and tau: from the last
-        // row's slot to the earliest band end (the pass's first tau)
-        int kin_lo = ra.k0;
-        int kin_hi = (int)min((int64_t)ra.k0 + L[0], (int64_t)1 << 30);
+        int lt = L[t];
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            kend = max(kend, __shfl_xor(kend, o, 64));
-            kin_lo = max(kin_lo, __shfl_xor(kin_lo, o, 64));
-            kin_hi = min(kin_hi, __shfl_xor(kin_hi, o, 64));
-        }
-        kend = __builtin_amdgcn_readfirstlane(kend);
-        kin_lo = __builtin_amdgcn_readfirstlane(kin_lo);
-        kin_hi = __builtin_amdgcn_readfirstlane(kin_hi);
-        const int kb_begin = max(k_first, 0) & ~31;
-        const int kb_data_end = min((kend + 31) & ~31, p.kp_data);
-        const int kb_end = kb_data_end > kb_begin ? kb_begin + ((kb_data_end - kb_begin + 63) & ~63) : kb_begin;
+        for (int o = 1; o < 16; o <<= 1) lt = max(lt, __shfl_xor(lt, o, 64));
+        Lt[t] = __builtin_amdgcn_readfirstlane(lt);
+    }
 
-        f32x4 acc[kNT][4];
+    // A side: the lane's cell (lrow >> 2) of each 16-row tile, component
+    // lrow & 3; element of slot k0 in its copy (rows past the grid repeat
+    // the last one; never written)
+    const int comp = lrow & 3;
+    int a_k0[4], a_base[4];
+    int k0lo = 1 << 30, k0hi = -(1 << 30);
 #pragma unroll
-        for (int t = 0; t < kNT; ++t)
+    for (int mt = 0; mt < 4; ++mt) {
+        const int k0 = p.rows[min(m_w + 4 * mt + (lrow >> 2), n_t0 - 1)].k0;
+        const int par = k0 & 1;
+        a_k0[mt] = k0;
+        a_base[mt] = ((par * 4 + comp) * p.n_bins + bin) * p.kpc + 8 + par + k0;
+        k0lo = min(k0lo, k0);
+        k0hi = max(k0hi, k0);
+    }
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int o = 1; o < 64; o <<= 1) {
+        k0lo = min(k0lo, __shfl_xor(k0lo, o, 64));
+        k0hi = max(k0hi, __shfl_xor(k0hi, o, 64));
+        Lmin = min(Lmin, __shfl_xor(Lmin, o, 64));
+    }
+    k0lo = __builtin_amdgcn_readfirstlane(k0lo);
+    k0hi = __builtin_amdgcn_readfirstlane(k0hi);
+    Lmin = __builtin_amdgcn_readfirstlane(Lmin);
+    int lmax = 0;
+#pragma unroll
+    for (int t = 0; t < kCellsNT; ++t) lmax = max(lmax, Lt[t]);
+    // lags with data for some row: below K - k0lo; an even number of steps
+    const int kend = min(lmax, K - k0lo);
+    const int kb_end = kend > 0 ? (kend + 63) & ~63 : 0;
+    // steps whose loads all fall in [-8, K) (no per-lane check) and whose
+    // lags all lie below every band (no weight mask)
+    const int kd_lo = -8 - k0lo, kd_hi = K - 24 - k0hi;
 
-        // one K step: per tau, the lane's weights, then 12 products (three
-        // bf16 products of the four data components)
-        auto step = [&](auto edge, int kb, const u32x4 *ch, const u32x4 *cl) {
-            const int d0 = kb + 8 * kg - ra.k0;
+    const uint32_t bytes = (uint32_t)(2 * 4 * p.n_bins) * (uint32_t)p.kpc * 2u;
+    const __amdgpu_buffer_rsrc_t rh = plane_rsrc(p.chi, bytes);
+    const __amdgpu_buffer_rsrc_t rl = plane_rsrc(p.clo, bytes);
+    auto load_a = [&](int kb, u32x4 *h, u32x4 *l) {
+        const int d0 = kb + 8 * kg;
+        const bool edge = kb < kd_lo || kb >= kd_hi;
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) {
-                u32x4 ah, al;
-                rows_weights<decltype(edge)::value, F16>(d0, cT[t], cD[t], rho[t], L[t], ah, al);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(ah, ch[c], acc[t][c]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(ah, cl[c], acc[t][c]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[t][c] = mfma_part<F16>(al, ch[c], acc[t][c]);
+        for (int mt = 0; mt < 4; ++mt) {
+            uint32_t off = (uint32_t)(a_base[mt] + d0) * 2u;
+            if (edge) {
+                const int s = a_k0[mt] + d0;
+                if (s < -8 || s >= K) off = 0x80000000u;
             }
+            h[mt] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)off, 0, 0));
+            l[mt] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)off, 0, 0));
+        }
+    };
+
+    f32x4 acc[4][kCellsNT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int t = 0; t < kCellsNT; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // one K step: per tau tile still inside its band, the lane's weights,
+    // then 12 products (three of each 16-row tile)
+    auto step = [&](auto edge, int kb, const u32x4 *ah, const u32x4 *al) {
+        const int d0 = kb + 8 * kg;
+#pragma unroll
+        for (int t = 0; t < kCellsNT; ++t) {
+            if (kb >= Lt[t]) continue;
+            u32x4 bh, bl;
+            rows_weights<decltype(edge)::value, F16>(d0, cT[t], cD[t], rho[t], L[t], bh, bl);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[mt][t] = mfma_part<F16>(ah[mt], bh, acc[mt][t]);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[mt][t] = mfma_part<F16>(ah[mt], bl, acc[mt][t]);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[mt][t] = mfma_part<F16>(al[mt], bh, acc[mt][t]);
+        }
+    };
+    if (kb_end > 0) {
+        u32x4 ah[4], al[4], nh[4], nl[4];
+        load_a(0, ah, al);
+        auto run = [&](int kb, const u32x4 *h, const u32x4 *l) {
+            if (kb + 32 > Lmin)
+                step(std::true_type{}, kb, h, l);
+            else
+                step(std::false_type{}, kb, h, l);
         };
-        if (kb_begin < kb_end) {
-            u32x4 bh[4], bl[4], nh[4], nl[4];
-            load_b(kb_begin, bh, bl);
-            auto run = [&](int kb, const u32x4 *ch, const u32x4 *cl) {
-                if (kb < kin_lo || kb + 32 > kin_hi)
-                    step(std::true_type{}, kb, ch, cl);
-                else
-                    step(std::false_type{}, kb, ch, cl);
-            };
 #pragma unroll 1
-            for (int kb = kb_begin; kb < kb_end; kb += 64) {
-                load_b(kb + 32, nh, nl);
-                run(kb, bh, bl);
-                load_b(min(kb + 64, kb_end - 32), bh, bl);
-                run(kb + 32, nh, nl);
-            }
-        }
-
-        // the folded A, B, C written by other lanes of this wave
-        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-        __builtin_amdgcn_wave_barrier();
-        // finalize: lane holds rows 4 kg + r (r < 4) of the wave for `bin`;
-        // half-precision sums carry the powers of two of the weights and of
-        // their data column, removed exactly here
-        double sc[4] = {1.0, 1.0, 1.0, 1.0};
-        if constexpr (F16) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                sc[c] = ldexp(1.0, -(kF16WeightExp + p.colexp[c * p.bins16 + col_tile * 16 + lrow]));
-        }
-        double v2[kNT][4];
-        double fmx = -INFINITY;
-        long long imx = 0x7fffffffffffffffLL;
-#pragma unroll
-        for (int t = 0; t < kNT; ++t) {
-            const int n = nb * kBlk + t0 + t;
-            const bool n_ok = n < p.n_tau;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = m_w + 4 * kg + r;
-                v2[t][r] = -INFINITY;
-                if (!n_ok || m >= n_t0 || !bin_ok) continue;
-                const double v = twoF_folded(sm.abc[wave][4 * kg + r][t0 + t], sc[0] * (double)acc[t][0][r],
-                                             sc[1] * (double)acc[t][1][r], sc[2] * (double)acc[t][2][r],
-                                             sc[3] * (double)acc[t][3][r]);
-                if (p.twoF) sm.out[wave][4 * kg + r][lrow][t0 + t] = (float)v;
-                v2[t][r] = v;
-                const long long idx = (long long)m * p.n_tau + n;
-                if (v > fmx || (v == fmx && idx < imx)) {
-                    fmx = v;
-                    imx = idx;
-                }
-            }
-        }
-        if (fmx != -INFINITY) {
-            double sum = 0.0;
-#pragma unroll
-            for (int t = 0; t < kNT; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (v2[t][r] != -INFINITY) sum += (double)__expf((float)(0.5 * (v2[t][r] - fmx)));
-            red = red_combine(red, Red{0.5 * fmx, sum, imx});
+        for (int kb = 0; kb < kb_end; kb += 64) {
+            load_a(kb + 32, nh, nl);
+            run(kb, ah, al);
+            load_a(min(kb + 64, kb_end - 32), ah, al);
+            run(kb + 32, nh, nl);
         }
     }
 
-    // the wave's map cells, 8 taus of one (bin, row) at a time: the 32
-    // bytes of a map row that this block owns arrive together, instead of
-    // as two 16-byte pieces, one from each pass
-    if (p.twoF) {
-        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-        __builtin_amdgcn_wave_barrier();
-        const int n0 = nb * kBlk;
-        const int nt = min(kBlk, p.n_tau - n0);
+    // finalize: lane holds cell kg of each 16-row tile (row m_w + 4 mt + kg)
+    // for the tau of its column, components r = 0..3 in acc[mt][t][r].  Half
+    // precision sums carry the powers of two of the weights and of their
+    // data column, removed exactly here.
+    double sc[4] = {1.0, 1.0, 1.0, 1.0};
+    if constexpr (F16) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int pr = lane + 64 * j;
-            const int r = pr >> 4, bl = pr & 15;
-            const int m = m_w + r, b = col_tile * 16 + bl;
-            if (m < n_t0 && b < p.n_bins) {
-                float *dst = p.twoF + ((size_t)b * n_t0 + m) * p.n_tau + n0;
-                const float *src = sm.out[wave][r][bl];
-                if (nt == kBlk) {
+        for (int c = 0; c < 4; ++c) sc[c] = ldexp(1.0, -(kF16WeightExp + p.colexp[c * p.bins16 + bin]));
+    }
+    Red red = red_empty();
 #pragma unroll
-                    for (int t = 0; t < kBlk; ++t) dst[t] = src[t];
-                } else {
-                    for (int t = 0; t < nt; ++t) dst[t] = src[t];
-                }
+    for (int t = 0; t < kCellsNT; ++t) {
+        const int n = tau_of(t);
+        if (n < 0) continue;
+        const int64_t tau = p.tau[n];
+        const float cI = (float)(1.4426950408889634 / (double)tau);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int m = m_w + 4 * mt + kg;
+            if (m >= n_t0) continue;
+            const RowPlan rp = p.rows[m];
+            double f[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) f[c] = sc[c] * (double)acc[mt][t][c];
+            // the band of this row: L or L - 1; the last lag's product off
+            const int64_t span = 3 * tau - rp.delta;
+            const int64_t Lm = span > 0 ? min((span + T - 1) / T, (int64_t)1 << 30) : 0;
+            const int sf = rp.k0 + L[t] - 1;
+            if (Lm < L[t] && sf >= 0 && sf < K) {
+                // the weight of lag L - 1 as the K steps made it
+                const int dl = L[t] - 1;
+                float w = __builtin_amdgcn_exp2f(fmaf((float)(dl & ~7), cT[t], cD[t]));
+                for (int j = 0; j < (dl & 7); ++j) w *= rho[t];
+                const double wq = F16 ? ldexp((double)w, -kF16WeightExp) : (double)w;
+                const float4 x = *reinterpret_cast<const float4 *>(p.x32 + ((size_t)sf * p.n_bins + bin) * 4);
+                f[0] -= wq * (double)x.x;
+                f[1] -= wq * (double)x.y;
+                f[2] -= wq * (double)x.z;
+                f[3] -= wq * (double)x.w;
             }
+            const double *src = p.abc_cell + ((size_t)m * p.abc_pitch + n) * 3;
+            double abc[3] = {src[0], src[1], src[2]};
+            fold_abc(abc, (double)exp2f(-(float)rp.delta * cI));
+            const double v = twoF_folded(abc, f[0], f[1], f[2], f[3]);
+            if (p.twoF) p.twoF[((size_t)bin * n_t0 + m) * p.n_tau + n] = (float)v;
+            red = red_combine(red, Red{0.5 * v, 1.0, (long long)m * p.n_tau + n});
         }
     }
 
-    // lanes sharing a bin: xor 16, 32; then the four waves in order
-    red = red_combine(red, red_shfl_xor(red, 16));
-    red = red_combine(red, red_shfl_xor(red, 32));
-    if (lane < 16) sm.wred[wave][lane] = red;
+    // the wave's lanes, then the four waves in order
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) red = red_combine(red, red_shfl_xor(red, o));
+    if (lane == 0) sm.wred[wave] = red;
     __syncthreads();
-    if (tid < 16) {
-        const int b = col_tile * 16 + tid;
-        if (b < p.n_bins) {
-            Red tt = sm.wred[0][tid];
-            for (int w = 1; w < 4; ++w) tt = red_combine(tt, sm.wred[w][tid]);
-            Partial &o = p.part[(size_t)b * p.n_tiles + tile];
-            o.fmax = tt.f;
-            o.s = tt.s;
-            o.idx = tt.i;
-        }
+    if (tid < nblk) {
+        Red tt = red_empty();
+        if (tid == 0)
+            for (int w = 0; w < 4; ++w) tt = red_combine(tt, sm.wred[w]);
+        // the item's cells count in its first block's slot; the others empty
+        Partial &o = p.part[(size_t)bin * p.n_tiles + (size_t)p.blk_list[q0 + tid] * p.n_row_tiles + row_tile];
+        o.fmax = tt.f;
+        o.s = tt.s;
+        o.idx = tt.i;
     }
 }
 
@@ -783,8 +791,8 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile(PP &p, Rows
 // at a time, all four on the same rows, and split the bins (wave w: column
 // tile 4 g + w); the 8 taus are one pass, so that each B load of a wave
 // feeds 8 taus' products.  In every K step each wave makes the weights of two
-// taus (w and w + 4) for the shared rows, exactly as mfma_rows_tile makes
-// them, and puts their hi and lo parts in LDS; every wave reads the eight
+// taus (w and w + 4) for the shared rows, the row scale and each row's exact
+// band end included, and puts their hi and lo parts in LDS; every wave reads the eight
 // taus' parts from there.  A weight is thus made once per 64 bins instead of
 // once per 16, which leaves the matrix cores most of each wave's issue
 // cycles.  The K steps of the four waves are the same (same rows, same
@@ -821,8 +829,13 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile_sw(PP &p, S
     const bool bin_ok = bin < p.n_bins;
     const int64_t T = p.t_sft;
 
-    // B operand as in mfma_rows_tile (waves past the last column tile load
-    // nothing; they still make weights and keep the barriers)
+    // B operand: planes [4][kp / 32][bins16][32], the lane's 8 slots of step
+    // kb for its bin.  One buffer resource per component and part (scalar
+    // registers), the step's offset in a scalar, the lane's own offset in a
+    // vector register: no vector address arithmetic per load (component
+    // planes are < 2^31 bytes, which the planner checks).  Waves past the
+    // last column tile load nothing; they still make weights and keep the
+    // barriers.
     const uint32_t comp_bytes = (uint32_t)p.bins16 * (uint32_t)p.kp * 2u;
     const uint32_t step_bytes = (uint32_t)p.bins16 * 64u;
     const uint32_t lane_off = (uint32_t)(((col_ok ? col_tile : 0) * 16 + lrow) * 32 + 8 * kg) * 2u;
@@ -1054,7 +1067,7 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile_sw(PP &p, S
 }
 
 union MfmaRowsSmem {
-    RowsSmem rows;
+    CellsSmem cells;
     SwSmem sw;
 };
 
@@ -1062,15 +1075,17 @@ union MfmaRowsSmem {
 #define TFS_ROWS_WAVES 2       // waves per SIMD the register budget targets
 #endif
 
-// Work items of a map: 16-bin column tiles, or groups of four of them
-// (mfma_rows_tile_sw) when the map has kSwMinColTiles or more.
+// Work items of a map: one bin and kCellsBlocks blocks of the transposed
+// form, or four 16-bin column tiles and one block (mfma_rows_tile_sw) when
+// the map has kSwMinColTiles or more (q: the unit, a block or a group of
+// kCellsBlocks blocks).
 template <bool F16, typename PP>
 __device__ __attribute__((always_inline)) inline void mfma_rows_item(PP &p, MfmaRowsSmem &sm, int q, int row_tile,
                                                                    int col_item) {
-    if (p.n_col_tiles >= kSwMinColTiles)
-        mfma_rows_tile_sw<F16>(p, sm.sw, q, row_tile, col_item);
+    if (mfma_cells_form(p.n_col_tiles))
+        mfma_cells_tile<F16>(p, sm.cells, q, row_tile, col_item);
     else
-        mfma_rows_tile<F16>(p, sm.rows, q, row_tile, col_item);
+        mfma_rows_tile_sw<F16>(p, sm.sw, q, row_tile, col_item);
 }
 
 // XCD-aware task order: column items dealt to the XCDs when there are at
@@ -1082,7 +1097,8 @@ __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpM
     const int bid = blockIdx.x;
     const int xcd = bid & 7;
     const int slot = bid >> 3;
-    const int n_col = mfma_col_items(p.n_col_tiles);
+    const int n_col = mfma_col_items(p.n_col_tiles, p.n_bins);
+    const int n_units = mfma_units(p.n_blocks, p.n_col_tiles);
     int q, row_tile, col_item;
     if (n_col >= 8) {
         const int cpx = (n_col + 7) / 8;
@@ -1091,19 +1107,19 @@ __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpM
         const int rem = slot % per_block;
         row_tile = rem / cpx;
         col_item = (rem % cpx) * 8 + xcd;
-        if (q >= p.n_blocks || col_item >= n_col) return;
+        if (q >= n_units || col_item >= n_col) return;
     } else if (n_col == 2 || n_col == 4) {
-        // each XCD one column item (its share of the B planes stays in the
-        // XCD's L2) and every (8 / n_col)-th tau block
+        // each XCD one column item (its share of the data planes stays in
+        // the XCD's L2) and every (8 / n_col)-th unit
         const int r = 8 / n_col;
         col_item = xcd % n_col;
         q = (slot / p.n_row_tiles) * r + xcd / n_col;
         row_tile = slot % p.n_row_tiles;
-        if (q >= p.n_blocks) return;
+        if (q >= n_units) return;
     } else {
         int rem;
-        unit_decode(bid, p.n_blocks, p.n_row_tiles * n_col, q, rem);
-        if (q >= p.n_blocks) return;
+        unit_decode(bid, n_units, p.n_row_tiles * n_col, q, rem);
+        if (q >= n_units) return;
         row_tile = rem / n_col;
         col_item = rem % n_col;
     }
@@ -1180,7 +1196,55 @@ __global__ __launch_bounds__(256) void build_planes_kernel(const float *x32, int
     }
 }
 
+// Column planes of the transposed form: the parts build_planes_kernel
+// makes, laid out [copy 2][4 components][n_bins][kpc] with slot k of copy
+// par at element k + 8 + par (zero outside [0, K)).
+template <bool F16>
+__global__ __launch_bounds__(256) void build_cplanes_kernel(const float *x32, int32_t K, int32_t n_bins,
+                                                            int32_t bins16, int32_t kpc, const int32_t *colexp,
+                                                            unsigned short *chi, unsigned short *clo) {
+    const int64_t per_c = (int64_t)n_bins * kpc;
+    const int64_t per_copy = 4 * per_c;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 2 * per_copy; i += (int64_t)gridDim.x * 256) {
+        const int par = (int)(i / per_copy);
+        const int64_t r = i - par * per_copy;
+        const int c = (int)(r / per_c);
+        const int64_t r2 = r - c * per_c;
+        const int bin = (int)(r2 / kpc);
+        const int64_t k = r2 - (int64_t)bin * kpc - 8 - par;
+        float x = 0.f;
+        if (k >= 0 && k < K) x = x32[((size_t)k * n_bins + bin) * 4 + c];
+        if constexpr (F16) {
+#pragma clang fp contract(off)
+            x = ldexpf(x, colexp[c * bins16 + bin]);
+            const _Float16 h = (_Float16)x;
+            const _Float16 l = (_Float16)(x - (float)h);
+            chi[i] = __builtin_bit_cast(unsigned short, h);
+            clo[i] = __builtin_bit_cast(unsigned short, l);
+        } else {
+            const unsigned int pk = split_pack(x);
+            chi[i] = (unsigned short)(pk & 0xffffu);
+            clo[i] = (unsigned short)(pk >> 16);
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_build_cplanes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16, int32_t kpc,
+                                const int32_t *colexp, unsigned short *chi, unsigned short *clo, hipStream_t s) {
+    const int64_t total = (int64_t)8 * n_bins * kpc;
+    int64_t g = (total + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    if (colexp)
+        hipLaunchKernelGGL(build_cplanes_kernel<true>, dim3((unsigned)g), dim3(256), 0, s, x32, K, n_bins, bins16,
+                           kpc, colexp, chi, clo);
+    else
+        hipLaunchKernelGGL(build_cplanes_kernel<false>, dim3((unsigned)g), dim3(256), 0, s, x32, K, n_bins, bins16,
+                           kpc, colexp, chi, clo);
+    return hipGetLastError();
+}
 
 hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s) {
     if (p.n_blocks <= 0) return hipSuccess;
@@ -1199,16 +1263,19 @@ hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s) {
 hipError_t launch_exp_mfma_rows(const ExpMfmaRowsParams &p, hipStream_t s) {
     if (p.n_blocks <= 0) return hipSuccess;
     if (p.kp < p.kp_data + 32) return hipErrorInvalidValue;   // even-step padding reads up to kp_data + 32
+    if (mfma_cells_form(p.n_col_tiles) && (p.chi == nullptr || p.clo == nullptr || p.x32 == nullptr))
+        return hipErrorInvalidValue;
     unsigned grid;
-    const int n_col = mfma_col_items(p.n_col_tiles);
+    const int n_col = mfma_col_items(p.n_col_tiles, p.n_bins);
+    const int n_units = mfma_units(p.n_blocks, p.n_col_tiles);
     if (n_col >= 8) {
         const int cpx = (n_col + 7) / 8;
-        grid = (unsigned)(8 * p.n_blocks * p.n_row_tiles * cpx);
+        grid = (unsigned)(8 * n_units * p.n_row_tiles * cpx);
     } else if (n_col == 2 || n_col == 4) {
         const int r = 8 / n_col;
-        grid = (unsigned)(8 * ((p.n_blocks + r - 1) / r) * p.n_row_tiles);
+        grid = (unsigned)(8 * ((n_units + r - 1) / r) * p.n_row_tiles);
     } else {
-        grid = (unsigned)unit_grid(p.n_blocks, p.n_row_tiles * n_col);
+        grid = (unsigned)unit_grid(n_units, p.n_row_tiles * n_col);
     }
     if (p.f16)
         hipLaunchKernelGGL(exp_mfma_rows_kernel<true>, dim3(grid), dim3(256), 0, s, p);

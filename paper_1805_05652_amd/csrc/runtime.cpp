@@ -177,6 +177,10 @@ struct AtomsSet {
     unsigned short *xhi16 = nullptr, *xlo16 = nullptr;
     int32_t *colexp = nullptr;
     int32_t bins16 = 0, kp = 0;
+    // column planes of the transposed matrix-core form (maps of fewer than
+    // 64 bins): bf16 and half-precision parts, in the allocations above
+    unsigned short *chi = nullptr, *clo = nullptr, *chi16 = nullptr, *clo16 = nullptr;
+    int32_t kpc = 0;
     int busy = 0;
     tfs::AtomsView view() const {
         tfs::AtomsView v;
@@ -398,6 +402,8 @@ void plan_job(Job &j) {
             const int64_t bins16 = (at.n_bins + 15) / 16 * 16;
             const int64_t kp = ((int64_t)at.K + 31) / 32 * 32 + 32;
             ok = at.n_bins >= kMfmaMinBins && bins16 * kp * 2 < ((int64_t)1 << 31);
+            if (tfs::mfma_cells_form((int)(bins16 / 16)))
+                ok = ok && (int64_t)16 * at.n_bins * tfs::cells_plane_pitch(at.K) < ((int64_t)1 << 31);
             j.mfma_rows = ok;
         }
         bool long_block = false;
@@ -785,6 +791,11 @@ tfs::ExpMfmaRowsParams mfma_rows_params(Job &j, const int32_t *blk_list) {
     q.abc_pitch = abc_pitch(q.n_tau);
     q.twoF = j.twoF;
     q.part = ws_ptr<tfs::Partial>(j, j.off_part);
+    q.chi = q.f16 ? at.chi16 : at.chi;
+    q.clo = q.f16 ? at.clo16 : at.clo;
+    q.x32 = at.x32;
+    q.kpc = at.kpc;
+    q.K = at.K;
     return q;
 }
 
@@ -1056,7 +1067,11 @@ void ensure_planes(tfstat_ctx *ctx, AtomsSet *at, int32_t prec) {
     const size_t plane = sizeof(unsigned short) * 4 * (size_t)bins16 * kp;
     const size_t plane_b = round_up(plane, 256);
     const size_t exp_b = f16 ? round_up(sizeof(int32_t) * 4 * (size_t)bins16, 256) : 0;
-    void *mem = ctx->arena.alloc(2 * plane_b + exp_b);
+    // the transposed form's column planes (two copies, both parts)
+    const bool cells = tfs::mfma_cells_form(bins16 / 16);
+    const int32_t kpc = tfs::cells_plane_pitch(at->K);
+    const size_t cplane_b = cells ? round_up(sizeof(unsigned short) * 8 * (size_t)at->n_bins * kpc, 256) : 0;
+    void *mem = ctx->arena.alloc(2 * plane_b + exp_b + 2 * cplane_b);
     if (!mem) raise(TFSTAT_E_NOMEM, "arena cannot hold the matrix-core planes");
     try {
         hip_check(hipSetDevice(ctx->device), "hipSetDevice");
@@ -1066,14 +1081,27 @@ void ensure_planes(tfstat_ctx *ctx, AtomsSet *at, int32_t prec) {
         hip_check(tfs::launch_build_planes(at->x32, at->K, at->n_bins, bins16, kp, colexp, xhi, xlo,
                                            ctx->stream),
                   "planes kernel");
+        unsigned short *chi = nullptr, *clo = nullptr;
+        if (cells) {
+            char *base = static_cast<char *>(mem) + 2 * plane_b + exp_b;
+            chi = reinterpret_cast<unsigned short *>(base);
+            clo = reinterpret_cast<unsigned short *>(base + cplane_b);
+            hip_check(tfs::launch_build_cplanes(at->x32, at->K, at->n_bins, bins16, kpc, colexp, chi, clo,
+                                                ctx->stream),
+                      "column planes kernel");
+        }
         hip_check(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
         if (f16) {
             at->xhi16 = xhi;
             at->xlo16 = xlo;
             at->colexp = colexp;
+            at->chi16 = chi;
+            at->clo16 = clo;
         } else {
             at->xhi = xhi;
             at->xlo = xlo;
+            at->chi = chi;
+            at->clo = clo;
         }
     } catch (...) {
         ctx->arena.release(mem);
@@ -1082,7 +1110,8 @@ void ensure_planes(tfstat_ctx *ctx, AtomsSet *at, int32_t prec) {
     (f16 ? at->planes16 : at->planes) = mem;
     at->bins16 = bins16;
     at->kp = kp;
-    at->bytes += 2 * plane_b + exp_b;
+    at->kpc = kpc;
+    at->bytes += 2 * plane_b + exp_b + 2 * cplane_b;
 }
 
 AtomsSet *find_atoms(tfstat_ctx *ctx, tfstat_atoms_id id) {
@@ -1222,7 +1251,8 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             if (j.use_mfma) {
                 // matrix-core work of the long-band blocks
                 midx[i] = n_mfma_maps++;
-                n_mfma_entries += (size_t)j.n_mfma * j.n_row_tiles * tfs::mfma_col_items(j.at->bins16 / 16);
+                n_mfma_entries += (size_t)tfs::mfma_units(j.n_mfma, j.at->bins16 / 16) * j.n_row_tiles *
+                                  tfs::mfma_col_items(j.at->bins16 / 16, j.at->n_bins);
             }
             max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
         } else {
@@ -1400,8 +1430,9 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             if (j.use_mfma) {
                 const int32_t *blk = reinterpret_cast<const int32_t *>(ws_ptr<char>(j, j.off_order)) + j.n_valu;
                 mfp[midx[i]] = mfma_rows_params(j, blk);
-                const int n_ct = tfs::mfma_col_items(j.at->bins16 / 16);
-                for (int q = 0; q < j.n_mfma; ++q)
+                const int n_ct = tfs::mfma_col_items(j.at->bins16 / 16, j.at->n_bins);
+                const int n_u = tfs::mfma_units(j.n_mfma, j.at->bins16 / 16);
+                for (int q = 0; q < n_u; ++q)
                     for (int rt = 0; rt < j.n_row_tiles; ++rt)
                         for (int ct = 0; ct < n_ct; ++ct) {
                             ment[4 * mfe + 0] = midx[i];

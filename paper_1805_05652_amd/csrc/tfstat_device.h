@@ -130,6 +130,13 @@ struct ExpMfmaRowsParams {
     int32_t f16;              // 1: half-precision parts (F16X3), 0: bf16
     float *twoF;
     Partial *part;
+    // transposed form (maps of fewer than kSwMinColTiles column tiles):
+    // column planes [2][4][n_bins][kpc] of the same parts, and the FP32
+    // atoms for the band-end correction
+    const unsigned short *chi, *clo;
+    const float *x32;         // [K + 1][n_bins][4]
+    int32_t kpc;              // column plane pitch, cells_plane_pitch(K)
+    int32_t K;
 };
 
 // XCD-aware task order.  Workgroup b runs on XCD b % 8, and each XCD has its
@@ -154,12 +161,26 @@ __host__ __device__ inline void unit_decode(int bid, int n_units, int per_unit, 
 }
 
 // Maps of at least this many 16-bin column tiles take their matrix-core
-// work items four column tiles at a time (one wave each, weights shared).
+// work items four column tiles at a time (one wave each, weights shared);
+// maps of fewer take the transposed work item: 64 rows x one bin x
+// kCellsBlocks blocks of 8 taus (kCellsNT tiles of 16 taus).
 constexpr int kSwMinColTiles = 4;
-// Column work items of a map with n_col_tiles 16-bin column tiles.
-__host__ __device__ inline int mfma_col_items(int n_col_tiles) {
-    return n_col_tiles >= kSwMinColTiles ? (n_col_tiles + 3) / 4 : n_col_tiles;
+constexpr int kCellsNT = 4;
+constexpr int kCellsBlocks = 2 * kCellsNT;
+__host__ __device__ inline bool mfma_cells_form(int n_col_tiles) { return n_col_tiles < kSwMinColTiles; }
+// Units of a map along its list of matrix-core blocks: one per block, or
+// one per kCellsBlocks blocks in the transposed form.
+__host__ __device__ inline int mfma_units(int n_blocks, int n_col_tiles) {
+    return mfma_cells_form(n_col_tiles) ? (n_blocks + kCellsBlocks - 1) / kCellsBlocks : n_blocks;
 }
+// Column work items per unit and 64-row tile: one per bin in the
+// transposed form, one per four column tiles otherwise.
+__host__ __device__ inline int mfma_col_items(int n_col_tiles, int n_bins) {
+    return mfma_cells_form(n_col_tiles) ? n_bins : (n_col_tiles + 3) / 4;
+}
+// Column planes of the transposed form: slot k of component c, bin b, copy
+// par at element ((par * 4 + c) * n_bins + b) * kpc + k + 8 + par.
+__host__ __device__ inline int32_t cells_plane_pitch(int32_t K) { return (K + 7) / 8 * 8 + 24; }
 
 // Half-precision matrix-core weights are taken as w * 2^kF16WeightExp.
 constexpr int kF16WeightExp = 4;
@@ -423,6 +444,8 @@ inline int32_t shift_table_len(int32_t lblk) { return (kMfmaPad + lblk + kMfmaTW
 hipError_t launch_build_planes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16,
                                int32_t kp, int32_t *colexp, unsigned short *xhi, unsigned short *xlo,
                                hipStream_t s);
+hipError_t launch_build_cplanes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16, int32_t kpc,
+                                const int32_t *colexp, unsigned short *chi, unsigned short *clo, hipStream_t s);
 hipError_t launch_scan(const double *in, int64_t in_row_stride, double *out,
                        int32_t K, int32_t C, hipStream_t s);
 hipError_t launch_rect(const RectParams &p, hipStream_t s);
