@@ -88,7 +88,8 @@ typedef enum {
  *            bits per operand (relative residual up to 2^-17), so 2F can
  *            miss a 1e-4 relative bound on a few cells of badly conditioned
  *            windows; F16X3 meets it.  The first call on an atoms set builds
- *            its bf16 planes (16 bytes per slot and bin of arena).
+ *            its bf16 planes (16 bytes per slot and bin of arena; sets of
+ *            2 to 48 bins 32 more, for the transposed form of their sums).
  *   F16X3  : as BF16X3 with IEEE half-precision hi + lo parts (22
  *            significant bits per operand, relative residual up to 2^-23),
  *            the data columns scaled by powers of two (one per bin and
@@ -98,7 +99,8 @@ typedef enum {
  *            has a block of 8 taus with every band at least 64 slots long,
  *            the blocks whose shortest band is at least 24 slots run on the
  *            matrix cores (shorter windows amplify the parts' rounding).
- *            Builds its own planes on first use (16 bytes per slot and bin).
+ *            Builds its own planes on first use (16 bytes per slot and bin;
+ *            sets of 2 to 48 bins 32 more).
  *   RECUR64: exponential windows on a regular t0 grid whose step is a whole
  *            number of SFT slots (at most 64): every sum in FP64 by the exact
  *            recurrence of the window sums from one t0 to the next, O(1)

@@ -561,11 +561,13 @@ __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t b
 // bin x kCellsBlocks blocks of 8 taus (kCellsNT tiles of 16 taus; the
 // blocks of one item are consecutive in the block list, which runs from
 // the longest band down, and a tile sits out the K steps past its own
-// longest band).  Data planes: [copy 2][component 4][bin][kpc], slot k of
-// copy par at element k + 8 + par, so that the 8 slots from any k are one
-// 16-byte load from a 4-byte aligned address in the copy of k's parity;
-// slots outside [0, K) read as zero (the 8 + par elements in front and the
-// pad behind K are zero, and loads that would start before that pad or at
+// longest band).  Data planes: [copy kCellsCopies][component 4][bin][kpc],
+// slot k of copy r at element k + 16 - r, so that the 8 slots from any k
+// are one 16-byte load from copy k mod kCellsCopies at an address aligned
+// to 2 kCellsCopies bytes (two copies: 4-byte aligned, which the loads
+// need; eight copies, 16-byte aligned, measured no faster); slots outside
+// [0, K) read as zero (the elements in front and the pad behind K are
+// zero, and loads that would start more than 8 slots before the data or at
 // or after K are sent beyond the buffer's end, which reads zero).
 // ---------------------------------------------------------------------------
 struct CellsSmem {
@@ -635,9 +637,9 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
         const int k0 = p.rows[min(m_w + 4 * mt + (lrow >> 2), n_t0 - 1)].k0;
-        const int par = k0 & 1;
+        const int r = k0 & (kCellsCopies - 1);
         a_k0[mt] = k0;
-        a_base[mt] = ((par * 4 + comp) * p.n_bins + bin) * p.kpc + 8 + par + k0;
+        a_base[mt] = ((r * 4 + comp) * p.n_bins + bin) * p.kpc + 16 - r + k0;
         k0lo = min(k0lo, k0);
         k0hi = max(k0hi, k0);
     }
@@ -660,7 +662,7 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
     // lags all lie below every band (no weight mask)
     const int kd_lo = -8 - k0lo, kd_hi = K - 24 - k0hi;
 
-    const uint32_t bytes = (uint32_t)(2 * 4 * p.n_bins) * (uint32_t)p.kpc * 2u;
+    const uint32_t bytes = (uint32_t)(kCellsCopies * 4 * p.n_bins) * (uint32_t)p.kpc * 2u;
     const __amdgpu_buffer_rsrc_t rh = plane_rsrc(p.chi, bytes);
     const __amdgpu_buffer_rsrc_t rl = plane_rsrc(p.clo, bytes);
     auto load_a = [&](int kb, u32x4 *h, u32x4 *l) {
@@ -735,6 +737,9 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
         if (n < 0) continue;
         const int64_t tau = p.tau[n];
         const float cI = (float)(1.4426950408889634 / (double)tau);
+        double v2[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        double fmx = -INFINITY;
+        long long imx = 0x7fffffffffffffffLL;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const int m = m_w + 4 * mt + kg;
@@ -764,7 +769,19 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
             fold_abc(abc, (double)exp2f(-(float)rp.delta * cI));
             const double v = twoF_folded(abc, f[0], f[1], f[2], f[3]);
             if (p.twoF) p.twoF[((size_t)bin * n_t0 + m) * p.n_tau + n] = (float)v;
-            red = red_combine(red, Red{0.5 * v, 1.0, (long long)m * p.n_tau + n});
+            v2[mt] = v;
+            const long long idx = (long long)m * p.n_tau + n;
+            if (v > fmx || (v == fmx && idx < imx)) {
+                fmx = v;
+                imx = idx;
+            }
+        }
+        if (fmx != -INFINITY) {
+            double sum = 0.0;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                if (v2[mt] != -INFINITY) sum += (double)__expf((float)(0.5 * (v2[mt] - fmx)));
+            red = red_combine(red, Red{0.5 * fmx, sum, imx});
         }
     }
 
@@ -1197,21 +1214,22 @@ __global__ __launch_bounds__(256) void build_planes_kernel(const float *x32, int
 }
 
 // Column planes of the transposed form: the parts build_planes_kernel
-// makes, laid out [copy 2][4 components][n_bins][kpc] with slot k of copy
-// par at element k + 8 + par (zero outside [0, K)).
+// makes, laid out [copy kCellsCopies][4 components][n_bins][kpc] with slot
+// k of copy r at element k + 16 - r (zero outside [0, K)).
 template <bool F16>
 __global__ __launch_bounds__(256) void build_cplanes_kernel(const float *x32, int32_t K, int32_t n_bins,
                                                             int32_t bins16, int32_t kpc, const int32_t *colexp,
                                                             unsigned short *chi, unsigned short *clo) {
     const int64_t per_c = (int64_t)n_bins * kpc;
     const int64_t per_copy = 4 * per_c;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 2 * per_copy; i += (int64_t)gridDim.x * 256) {
-        const int par = (int)(i / per_copy);
-        const int64_t r = i - par * per_copy;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < kCellsCopies * per_copy;
+         i += (int64_t)gridDim.x * 256) {
+        const int cp = (int)(i / per_copy);
+        const int64_t r = i - cp * per_copy;
         const int c = (int)(r / per_c);
         const int64_t r2 = r - c * per_c;
         const int bin = (int)(r2 / kpc);
-        const int64_t k = r2 - (int64_t)bin * kpc - 8 - par;
+        const int64_t k = r2 - (int64_t)bin * kpc - 16 + cp;
         float x = 0.f;
         if (k >= 0 && k < K) x = x32[((size_t)k * n_bins + bin) * 4 + c];
         if constexpr (F16) {
@@ -1233,7 +1251,7 @@ __global__ __launch_bounds__(256) void build_cplanes_kernel(const float *x32, in
 
 hipError_t launch_build_cplanes(const float *x32, int32_t K, int32_t n_bins, int32_t bins16, int32_t kpc,
                                 const int32_t *colexp, unsigned short *chi, unsigned short *clo, hipStream_t s) {
-    const int64_t total = (int64_t)8 * n_bins * kpc;
+    const int64_t total = (int64_t)kCellsCopies * 4 * n_bins * kpc;
     int64_t g = (total + 255) / 256;
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;

@@ -403,7 +403,8 @@ void plan_job(Job &j) {
             const int64_t kp = ((int64_t)at.K + 31) / 32 * 32 + 32;
             ok = at.n_bins >= kMfmaMinBins && bins16 * kp * 2 < ((int64_t)1 << 31);
             if (tfs::mfma_cells_form((int)(bins16 / 16)))
-                ok = ok && (int64_t)16 * at.n_bins * tfs::cells_plane_pitch(at.K) < ((int64_t)1 << 31);
+                ok = ok && (int64_t)8 * tfs::kCellsCopies * at.n_bins * tfs::cells_plane_pitch(at.K) <
+                               ((int64_t)1 << 31);
             j.mfma_rows = ok;
         }
         bool long_block = false;
@@ -1067,10 +1068,11 @@ void ensure_planes(tfstat_ctx *ctx, AtomsSet *at, int32_t prec) {
     const size_t plane = sizeof(unsigned short) * 4 * (size_t)bins16 * kp;
     const size_t plane_b = round_up(plane, 256);
     const size_t exp_b = f16 ? round_up(sizeof(int32_t) * 4 * (size_t)bins16, 256) : 0;
-    // the transposed form's column planes (two copies, both parts)
+    // the transposed form's column planes (kCellsCopies copies, both parts)
     const bool cells = tfs::mfma_cells_form(bins16 / 16);
     const int32_t kpc = tfs::cells_plane_pitch(at->K);
-    const size_t cplane_b = cells ? round_up(sizeof(unsigned short) * 8 * (size_t)at->n_bins * kpc, 256) : 0;
+    const size_t cplane_b =
+        cells ? round_up(sizeof(unsigned short) * 4 * tfs::kCellsCopies * (size_t)at->n_bins * kpc, 256) : 0;
     void *mem = ctx->arena.alloc(2 * plane_b + exp_b + 2 * cplane_b);
     if (!mem) raise(TFSTAT_E_NOMEM, "arena cannot hold the matrix-core planes");
     try {

@@ -131,8 +131,8 @@ struct ExpMfmaRowsParams {
     float *twoF;
     Partial *part;
     // transposed form (maps of fewer than kSwMinColTiles column tiles):
-    // column planes [2][4][n_bins][kpc] of the same parts, and the FP32
-    // atoms for the band-end correction
+    // column planes [kCellsCopies][4][n_bins][kpc] of the same parts, and
+    // the FP32 atoms for the band-end correction
     const unsigned short *chi, *clo;
     const float *x32;         // [K + 1][n_bins][4]
     int32_t kpc;              // column plane pitch, cells_plane_pitch(K)
@@ -179,7 +179,10 @@ __host__ __device__ inline int mfma_col_items(int n_col_tiles, int n_bins) {
     return mfma_cells_form(n_col_tiles) ? n_bins : (n_col_tiles + 3) / 4;
 }
 // Column planes of the transposed form: slot k of component c, bin b, copy
-// par at element ((par * 4 + c) * n_bins + b) * kpc + k + 8 + par.
+// r at element ((r * 4 + c) * n_bins + b) * kpc + k + 16 - r, one copy per
+// residue of k mod kCellsCopies (a power of two up to 8).
+constexpr int kCellsCopies = 2;
+static_assert(kCellsCopies == 2 || kCellsCopies == 4 || kCellsCopies == 8, "column plane copies");
 __host__ __device__ inline int32_t cells_plane_pitch(int32_t K) { return (K + 7) / 8 * 8 + 24; }
 
 // Half-precision matrix-core weights are taken as w * 2^kF16WeightExp.

@@ -433,7 +433,7 @@ def _kernel_launches(ctx, fn):
 @pytest.mark.parametrize("prec", ["f16x3", "bf16x3"])
 @pytest.mark.parametrize("case", ["linspace", "stride7", "before_after", "bins5", "bins37", "bins1_valu", "bins3",
                                   "one_row_tile", "long_and_short", "scaled", "bins70", "bins64_stride3",
-                                  "bins150", "bins520"])
+                                  "bins150", "bins520", "bins2", "bins4", "bins48", "bins49"])
 def test_matrix_any_grid(ctx, case, prec):
     """Matrix cores for exponential windows on any t0 grid (weights computed
     per row): linspace rows with their own offsets, rows 7 slots apart, rows
@@ -441,15 +441,17 @@ def test_matrix_any_grid(ctx, case, prec):
     tiles), a one-bin map (FP32 path) and a three-bin one, a single partial row
     tile, tau blocks with short bands beside long ones (FP32 F-only tiles),
     and data far outside the half-precision range with one all-zero bin
-    (the half-precision path's column scaling).  Maps of 64 to 520 bins take
-    the work items of four column tiles with shared weights (70 bins: a
-    last group of one column tile and three waves without one; 70, 150 and
-    520 bins: 2, 3 and 9 column groups, each with its own order of work
-    items over the XCDs).
+    (the half-precision path's column scaling).  Maps of 2 to 48 bins take
+    the transposed work item (one bin per item; 2 and 4 bins: one bin per
+    XCD, 8 or more: bins dealt over the XCDs, others in plain order), maps
+    of 49 to 520 bins the work items of four column tiles with shared
+    weights (49 bins: the smallest such map; 70 bins: a last group of one
+    column tile and three waves without one; 70, 150 and 520 bins: 2, 3 and
+    9 column groups, each with its own order of work items over the XCDs).
     Every cell and the per-bin results against the oracle."""
     _case("%s any grid %s" % (prec, case))
     n_bins = {"bins5": 5, "bins37": 37, "bins1_valu": 1, "bins3": 3, "bins70": 70, "bins64_stride3": 64,
-              "bins150": 150, "bins520": 520}.get(case, 24)
+              "bins150": 150, "bins520": 520, "bins2": 2, "bins4": 4, "bins48": 48, "bins49": 49}.get(case, 24)
     atoms = tfsynth.make_atoms(811, 1400, 0.12, n_bins=n_bins,
                                injections=[tfsynth.Injection(min(4, n_bins - 1), "exp", 300 * T, 60 * T, 1.0)])
     if case == "scaled":
@@ -461,7 +463,8 @@ def test_matrix_any_grid(ctx, case, prec):
         fb[7] = 0.0
         atoms = dataclasses.replace(atoms, fa=fa, fb=fb, a2=atoms.a2 * 2.0 ** 40, b2=atoms.b2 * 2.0 ** 40,
                                     ab=atoms.ab * 2.0 ** 40)
-    if case in ("linspace", "bins5", "bins37", "bins1_valu", "bins3", "scaled", "bins70"):
+    if case in ("linspace", "bins5", "bins37", "bins1_valu", "bins3", "scaled", "bins70", "bins2", "bins4", "bins48",
+                "bins49"):
         win = tfsynth.linspace_grid(atoms, "exp", 260, 110)
     elif case == "bins64_stride3":
         win = tfsynth.regular_window("exp", 50 * T + 3, 3 * T, 150, 2 * T, 4 * T + 9, 75)
