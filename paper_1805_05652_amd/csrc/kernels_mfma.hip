@@ -548,8 +548,11 @@ __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t b
 // data, so that delta_m lies in [0, T_sft)).  The weights g depend on the
 // tau and the lag only, so they are the B operand (32 lags x 16 taus per
 // K step) that a wave shares among all its rows, and the A operand gathers
-// the data: row 4 i + c of a 16-row tile is component c of the tile's cell
-// i, and its 8 lags of a K step are the 8 slots from k0_m + d.  A window
+// the data: row i of 16-row tile c is component c of the wave's cell i
+// (t0 row m = first + i), and its 8 lags of a K step are the 8 slots from
+// k0_m + d; the accumulators then give each lane all four components of
+// its cells, and the rows of one load instruction read one plane, where
+// nearby rows share cache lines.  A window
 // holds the lags below L_m = ceil((3 tau - delta_m) / T_sft), which is
 // L = ceil(3 tau / T_sft) or L - 1; B holds the lags below L, and a cell
 // whose band is L - 1 has the product of lag L - 1 taken off in the
@@ -557,7 +560,7 @@ __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, uint32_t b
 // matrix cores do no work on absent bins, and a weight is made once per
 // 16 cells.
 //
-// Work item: 64 rows (16 per wave, as four 16-row tiles of 4 cells) x one
+// Work item: 64 rows (16 per wave, one 16-row tile per component) x one
 // bin x kCellsBlocks blocks of 8 taus (kCellsNT tiles of 16 taus; the
 // blocks of one item are consecutive in the block list, which runs from
 // the longest band down, and a tile sits out the K steps past its own
@@ -628,21 +631,17 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
         Lt[t] = __builtin_amdgcn_readfirstlane(lt);
     }
 
-    // A side: the lane's cell (lrow >> 2) of each 16-row tile, component
-    // lrow & 3; element of slot k0 in its copy (rows past the grid repeat
-    // the last one; never written)
-    const int comp = lrow & 3;
-    int a_k0[4], a_base[4];
-    int k0lo = 1 << 30, k0hi = -(1 << 30);
+    // A side: 16-row tile c holds component c of the wave's 16 cells, the
+    // lane's cell being row m_w + lrow; element of its slot k0 in its copy
+    // (rows past the grid repeat the last one; never written)
+    const int a_k0 = p.rows[min(m_w + lrow, n_t0 - 1)].k0;
+    int a_base[4];
+    {
+        const int r = a_k0 & (kCellsCopies - 1);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const int k0 = p.rows[min(m_w + 4 * mt + (lrow >> 2), n_t0 - 1)].k0;
-        const int r = k0 & (kCellsCopies - 1);
-        a_k0[mt] = k0;
-        a_base[mt] = ((r * 4 + comp) * p.n_bins + bin) * p.kpc + 16 - r + k0;
-        k0lo = min(k0lo, k0);
-        k0hi = max(k0hi, k0);
+        for (int c = 0; c < 4; ++c) a_base[c] = ((r * 4 + c) * p.n_bins + bin) * p.kpc + 16 - r + a_k0;
     }
+    int k0lo = a_k0, k0hi = a_k0;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         k0lo = min(k0lo, __shfl_xor(k0lo, o, 64));
@@ -668,15 +667,13 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
     auto load_a = [&](int kb, u32x4 *h, u32x4 *l) {
         const int d0 = kb + 8 * kg;
         const bool edge = kb < kd_lo || kb >= kd_hi;
+        const int s = a_k0 + d0;
+        const bool out = edge && (s < -8 || s >= K);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            uint32_t off = (uint32_t)(a_base[mt] + d0) * 2u;
-            if (edge) {
-                const int s = a_k0[mt] + d0;
-                if (s < -8 || s >= K) off = 0x80000000u;
-            }
-            h[mt] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)off, 0, 0));
-            l[mt] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)off, 0, 0));
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t off = out ? 0x80000000u : (uint32_t)(a_base[c] + d0) * 2u;
+            h[c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)off, 0, 0));
+            l[c] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)off, 0, 0));
         }
     };
 
@@ -721,10 +718,10 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
         }
     }
 
-    // finalize: lane holds cell kg of each 16-row tile (row m_w + 4 mt + kg)
-    // for the tau of its column, components r = 0..3 in acc[mt][t][r].  Half
-    // precision sums carry the powers of two of the weights and of their
-    // data column, removed exactly here.
+    // finalize: lane holds cells 4 kg + r (rows m_w + 4 kg + r, r < 4) for
+    // the tau of its column, component c in acc[c][t][r].  Half precision
+    // sums carry the powers of two of the weights and of their data
+    // column, removed exactly here.
     double sc[4] = {1.0, 1.0, 1.0, 1.0};
     if constexpr (F16) {
 #pragma unroll
@@ -742,12 +739,12 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
         long long imx = 0x7fffffffffffffffLL;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            const int m = m_w + 4 * mt + kg;
+            const int m = m_w + 4 * kg + mt;
             if (m >= n_t0) continue;
             const RowPlan rp = p.rows[m];
             double f[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) f[c] = sc[c] * (double)acc[mt][t][c];
+            for (int c = 0; c < 4; ++c) f[c] = sc[c] * (double)acc[c][t][mt];
             // the band of this row: L or L - 1; the last lag's product off
             const int64_t span = 3 * tau - rp.delta;
             const int64_t Lm = span > 0 ? min((span + T - 1) / T, (int64_t)1 << 30) : 0;
