@@ -597,7 +597,7 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
     float cT[kCellsNT], cD[kCellsNT], rho[kCellsNT];
     int L[kCellsNT];
     int Lt[kCellsNT];        // the tile's longest band (wave-uniform; 0: no tau)
-    int Lmin = 1 << 30;      // shortest band of the lane's taus
+    int Ls[kCellsNT];        // the tile's shortest band (wave-uniform)
     // the lane's tau of tile t (-1: none)
     auto tau_of = [&](int t) {
         const int qb = 2 * t + (lrow >> 3);
@@ -618,7 +618,6 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
             cD[t] = F16 ? (float)kF16WeightExp : 0.f;
             rho[t] = exp2f(cT[t]);
             L[t] = (int)min((3 * tau + T - 1) / T, (int64_t)1 << 30);
-            Lmin = min(Lmin, L[t]);
         } else {
             cT[t] = 0.f;
             cD[t] = -INFINITY;
@@ -626,9 +625,14 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
             L[t] = 0;
         }
         int lt = L[t];
+        int ls = n >= 0 ? L[t] : 1 << 30;
 #pragma unroll
-        for (int o = 1; o < 16; o <<= 1) lt = max(lt, __shfl_xor(lt, o, 64));
+        for (int o = 1; o < 16; o <<= 1) {
+            lt = max(lt, __shfl_xor(lt, o, 64));
+            ls = min(ls, __shfl_xor(ls, o, 64));
+        }
         Lt[t] = __builtin_amdgcn_readfirstlane(lt);
+        Ls[t] = __builtin_amdgcn_readfirstlane(ls);
     }
 
     // A side: 16-row tile c holds component c of the wave's 16 cells, the
@@ -646,19 +650,16 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
     for (int o = 1; o < 64; o <<= 1) {
         k0lo = min(k0lo, __shfl_xor(k0lo, o, 64));
         k0hi = max(k0hi, __shfl_xor(k0hi, o, 64));
-        Lmin = min(Lmin, __shfl_xor(Lmin, o, 64));
     }
     k0lo = __builtin_amdgcn_readfirstlane(k0lo);
     k0hi = __builtin_amdgcn_readfirstlane(k0hi);
-    Lmin = __builtin_amdgcn_readfirstlane(Lmin);
     int lmax = 0;
 #pragma unroll
     for (int t = 0; t < kCellsNT; ++t) lmax = max(lmax, Lt[t]);
     // lags with data for some row: below K - k0lo; an even number of steps
     const int kend = min(lmax, K - k0lo);
-    const int kb_end = kend > 0 ? (kend + 63) & ~63 : 0;
-    // steps whose loads all fall in [-8, K) (no per-lane check) and whose
-    // lags all lie below every band (no weight mask)
+    const int kb_end = kend > 0 ? (kend + 31) & ~31 : 0;
+    // steps whose loads all fall in [-8, K) (no per-lane check)
     const int kd_lo = -8 - k0lo, kd_hi = K - 24 - k0hi;
 
     const uint32_t bytes = (uint32_t)(kCellsCopies * 4 * p.n_bins) * (uint32_t)p.kpc * 2u;
@@ -683,15 +684,19 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
 #pragma unroll
         for (int t = 0; t < kCellsNT; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // one K step: per tau tile still inside its band, the lane's weights,
-    // then 12 products (three of each 16-row tile)
-    auto step = [&](auto edge, int kb, const u32x4 *ah, const u32x4 *al) {
+    // one K step: per tau tile still inside its band, the lane's weights
+    // (masked past a band only where one of the tile's bands may end in
+    // the step), then 12 products (three of each 16-row tile)
+    auto step = [&](int kb, const u32x4 *ah, const u32x4 *al) {
         const int d0 = kb + 8 * kg;
 #pragma unroll
         for (int t = 0; t < kCellsNT; ++t) {
             if (kb >= Lt[t]) continue;
             u32x4 bh, bl;
-            rows_weights<decltype(edge)::value, F16>(d0, cT[t], cD[t], rho[t], L[t], bh, bl);
+            if (kb + 32 > Ls[t])
+                rows_weights<true, F16>(d0, cT[t], cD[t], rho[t], L[t], bh, bl);
+            else
+                rows_weights<false, F16>(d0, cT[t], cD[t], rho[t], L[t], bh, bl);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) acc[mt][t] = mfma_part<F16>(ah[mt], bh, acc[mt][t]);
 #pragma unroll
@@ -700,22 +705,13 @@ __device__ __attribute__((always_inline)) inline void mfma_cells_tile(PP &p, Cel
             for (int mt = 0; mt < 4; ++mt) acc[mt][t] = mfma_part<F16>(al[mt], bh, acc[mt][t]);
         }
     };
-    if (kb_end > 0) {
-        u32x4 ah[4], al[4], nh[4], nl[4];
-        load_a(0, ah, al);
-        auto run = [&](int kb, const u32x4 *h, const u32x4 *l) {
-            if (kb + 32 > Lmin)
-                step(std::true_type{}, kb, h, l);
-            else
-                step(std::false_type{}, kb, h, l);
-        };
+    // one step's loads at a time: the registers of a second set would cost
+    // a wave per SIMD, and three waves hide the loads' latency better
 #pragma unroll 1
-        for (int kb = 0; kb < kb_end; kb += 64) {
-            load_a(kb + 32, nh, nl);
-            run(kb, ah, al);
-            load_a(min(kb + 64, kb_end - 32), ah, al);
-            run(kb + 32, nh, nl);
-        }
+    for (int kb = 0; kb < kb_end; kb += 32) {
+        u32x4 ah[4], al[4];
+        load_a(kb, ah, al);
+        step(kb, ah, al);
     }
 
     // finalize: lane holds cells 4 kg + r (rows m_w + 4 kg + r, r < 4) for
@@ -1080,40 +1076,22 @@ __device__ __attribute__((always_inline)) inline void mfma_rows_tile_sw(PP &p, S
     }
 }
 
-union MfmaRowsSmem {
-    CellsSmem cells;
-    SwSmem sw;
-};
-
 #ifndef TFS_ROWS_WAVES
 #define TFS_ROWS_WAVES 2       // waves per SIMD the register budget targets
 #endif
+#ifndef TFS_CELLS_WAVES
+#define TFS_CELLS_WAVES 3      // the same for the transposed form's kernels
+#endif
 
-// Work items of a map: one bin and kCellsBlocks blocks of the transposed
-// form, or four 16-bin column tiles and one block (mfma_rows_tile_sw) when
-// the map has kSwMinColTiles or more (q: the unit, a block or a group of
-// kCellsBlocks blocks).
-template <bool F16, typename PP>
-__device__ __attribute__((always_inline)) inline void mfma_rows_item(PP &p, MfmaRowsSmem &sm, int q, int row_tile,
-                                                                   int col_item) {
-    if (mfma_cells_form(p.n_col_tiles))
-        mfma_cells_tile<F16>(p, sm.cells, q, row_tile, col_item);
-    else
-        mfma_rows_tile_sw<F16>(p, sm.sw, q, row_tile, col_item);
-}
-
-// XCD-aware task order: column items dealt to the XCDs when there are at
-// least 8 of them, one per XCD when there are 2 or 4, otherwise the tau
-// blocks as the units of unit_decode.
-template <bool F16>
-__global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpMfmaRowsParams p) {
-    __shared__ MfmaRowsSmem sm;
-    const int bid = blockIdx.x;
+// Work item of launch block bid of a map, in an XCD-aware order: column
+// items dealt to the XCDs when there are at least 8 of them, one per XCD
+// when there are 2 or 4, otherwise the units (tau blocks, or groups of them
+// in the transposed form) as the units of unit_decode.  False: no item.
+__device__ inline bool rows_task(const ExpMfmaRowsParams &p, int bid, int &q, int &row_tile, int &col_item) {
     const int xcd = bid & 7;
     const int slot = bid >> 3;
     const int n_col = mfma_col_items(p.n_col_tiles, p.n_bins);
     const int n_units = mfma_units(p.n_blocks, p.n_col_tiles);
-    int q, row_tile, col_item;
     if (n_col >= 8) {
         const int cpx = (n_col + 7) / 8;
         const int per_block = p.n_row_tiles * cpx;
@@ -1121,37 +1099,58 @@ __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpM
         const int rem = slot % per_block;
         row_tile = rem / cpx;
         col_item = (rem % cpx) * 8 + xcd;
-        if (q >= n_units || col_item >= n_col) return;
-    } else if (n_col == 2 || n_col == 4) {
+        return q < n_units && col_item < n_col;
+    }
+    if (n_col == 2 || n_col == 4) {
         // each XCD one column item (its share of the data planes stays in
         // the XCD's L2) and every (8 / n_col)-th unit
         const int r = 8 / n_col;
         col_item = xcd % n_col;
         q = (slot / p.n_row_tiles) * r + xcd / n_col;
         row_tile = slot % p.n_row_tiles;
-        if (q >= n_units) return;
-    } else {
-        int rem;
-        unit_decode(bid, n_units, p.n_row_tiles * n_col, q, rem);
-        if (q >= n_units) return;
-        row_tile = rem / n_col;
-        col_item = rem % n_col;
+        return q < n_units;
     }
-    mfma_rows_item<F16>(p, sm, q, row_tile, col_item);
+    int rem;
+    unit_decode(bid, n_units, p.n_row_tiles * n_col, q, rem);
+    row_tile = rem / n_col;
+    col_item = rem % n_col;
+    return q < n_units;
 }
 
-// Matrix-core work items of many maps (one entry per workgroup).
+// Maps of kSwMinColTiles or more column tiles (the shared-weight item).
+template <bool F16>
+__global__ __launch_bounds__(256, TFS_ROWS_WAVES) void exp_mfma_rows_kernel(ExpMfmaRowsParams p) {
+    __shared__ SwSmem sm;
+    int q, row_tile, col_item;
+    if (rows_task(p, blockIdx.x, q, row_tile, col_item)) mfma_rows_tile_sw<F16>(p, sm, q, row_tile, col_item);
+}
+
+// Maps of fewer column tiles (the transposed item).
+template <bool F16>
+__global__ __launch_bounds__(256, TFS_CELLS_WAVES) void exp_mfma_cells_kernel(ExpMfmaRowsParams p) {
+    __shared__ CellsSmem sm;
+    int q, row_tile, col_item;
+    if (rows_task(p, blockIdx.x, q, row_tile, col_item)) mfma_cells_tile<F16>(p, sm, q, row_tile, col_item);
+}
+
+// Matrix-core work items of many maps (one entry per workgroup): the
+// transposed form's entries [0, n_cells), the others after them.
+template <bool F16>
+__global__ __launch_bounds__(256, TFS_CELLS_WAVES) void mfma_cells_batch_kernel(MfmaBatchParams b) {
+    __shared__ CellsSmem sm;
+    const int32_t *en = b.entries + 4 * (size_t)blockIdx.x;
+    mfma_cells_tile<F16>(*reinterpret_cast<const __attribute__((address_space(4))) ExpMfmaRowsParams *>(
+                             reinterpret_cast<uintptr_t>(b.jobs + en[0])),
+                         sm, en[1], en[2], en[3]);
+}
+
 template <bool F16>
 __global__ __launch_bounds__(256, TFS_ROWS_WAVES) void mfma_batch_kernel(MfmaBatchParams b) {
-    __shared__ MfmaRowsSmem sm;
-    const int e = blockIdx.x;
-    const int job = b.entries[4 * e + 0];
-    const int q = b.entries[4 * e + 1];
-    const int row_tile = b.entries[4 * e + 2];
-    const int col_item = b.entries[4 * e + 3];
-    mfma_rows_item<F16>(*reinterpret_cast<const __attribute__((address_space(4))) ExpMfmaRowsParams *>(
-                            reinterpret_cast<uintptr_t>(b.jobs + job)),
-                        sm, q, row_tile, col_item);
+    __shared__ SwSmem sm;
+    const int32_t *en = b.entries + 4 * ((size_t)b.n_cells + blockIdx.x);
+    mfma_rows_tile_sw<F16>(*reinterpret_cast<const __attribute__((address_space(4))) ExpMfmaRowsParams *>(
+                               reinterpret_cast<uintptr_t>(b.jobs + en[0])),
+                           sm, en[1], en[2], en[3]);
 }
 
 // Per data column (component c, bin) of the FP32 atoms x32 [K+1][bins][4],
@@ -1278,8 +1277,8 @@ hipError_t launch_exp_mfma(const ExpMfmaParams &p, hipStream_t s) {
 hipError_t launch_exp_mfma_rows(const ExpMfmaRowsParams &p, hipStream_t s) {
     if (p.n_blocks <= 0) return hipSuccess;
     if (p.kp < p.kp_data + 32) return hipErrorInvalidValue;   // even-step padding reads up to kp_data + 32
-    if (mfma_cells_form(p.n_col_tiles) && (p.chi == nullptr || p.clo == nullptr || p.x32 == nullptr))
-        return hipErrorInvalidValue;
+    const bool cells = mfma_cells_form(p.n_col_tiles);
+    if (cells && (p.chi == nullptr || p.clo == nullptr || p.x32 == nullptr)) return hipErrorInvalidValue;
     unsigned grid;
     const int n_col = mfma_col_items(p.n_col_tiles, p.n_bins);
     const int n_units = mfma_units(p.n_blocks, p.n_col_tiles);
@@ -1292,19 +1291,38 @@ hipError_t launch_exp_mfma_rows(const ExpMfmaRowsParams &p, hipStream_t s) {
     } else {
         grid = (unsigned)unit_grid(n_units, p.n_row_tiles * n_col);
     }
-    if (p.f16)
-        hipLaunchKernelGGL(exp_mfma_rows_kernel<true>, dim3(grid), dim3(256), 0, s, p);
-    else
-        hipLaunchKernelGGL(exp_mfma_rows_kernel<false>, dim3(grid), dim3(256), 0, s, p);
+    if (cells) {
+        if (p.f16)
+            hipLaunchKernelGGL(exp_mfma_cells_kernel<true>, dim3(grid), dim3(256), 0, s, p);
+        else
+            hipLaunchKernelGGL(exp_mfma_cells_kernel<false>, dim3(grid), dim3(256), 0, s, p);
+    } else {
+        if (p.f16)
+            hipLaunchKernelGGL(exp_mfma_rows_kernel<true>, dim3(grid), dim3(256), 0, s, p);
+        else
+            hipLaunchKernelGGL(exp_mfma_rows_kernel<false>, dim3(grid), dim3(256), 0, s, p);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_batch(const MfmaBatchParams &p, hipStream_t s) {
     if (p.n_entries <= 0) return hipSuccess;
-    if (p.f16)
-        hipLaunchKernelGGL(mfma_batch_kernel<true>, dim3((unsigned)p.n_entries), dim3(256), 0, s, p);
-    else
-        hipLaunchKernelGGL(mfma_batch_kernel<false>, dim3((unsigned)p.n_entries), dim3(256), 0, s, p);
+    if (p.n_cells < 0 || p.n_cells > p.n_entries) return hipErrorInvalidValue;
+    if (p.n_cells > 0) {
+        if (p.f16)
+            hipLaunchKernelGGL(mfma_cells_batch_kernel<true>, dim3((unsigned)p.n_cells), dim3(256), 0, s, p);
+        else
+            hipLaunchKernelGGL(mfma_cells_batch_kernel<false>, dim3((unsigned)p.n_cells), dim3(256), 0, s, p);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int n_rest = p.n_entries - p.n_cells;
+    if (n_rest > 0) {
+        if (p.f16)
+            hipLaunchKernelGGL(mfma_batch_kernel<true>, dim3((unsigned)n_rest), dim3(256), 0, s, p);
+        else
+            hipLaunchKernelGGL(mfma_batch_kernel<false>, dim3((unsigned)n_rest), dim3(256), 0, s, p);
+    }
     return hipGetLastError();
 }
 

@@ -1223,7 +1223,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     int n_exp = 0, n_rect = 0, n_went = 0, n_scan = 0, n_abc = 0, n_mfma_maps = 0, n_rabc_maps = 0;
     size_t n_rabc = 0;   // recurrence A/B/C entries (exponential windows)
     std::vector<int> aidx(n, -1);
-    size_t n_mfma_entries = 0;
+    size_t n_mfma_entries = 0, n_cells_entries = 0;   // matrix-core work items (transposed form first)
     int32_t max_chunks = 1;
     b->res_off.assign(n, 0);
     b->n_results = 0;
@@ -1253,8 +1253,10 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
             if (j.use_mfma) {
                 // matrix-core work of the long-band blocks
                 midx[i] = n_mfma_maps++;
-                n_mfma_entries += (size_t)tfs::mfma_units(j.n_mfma, j.at->bins16 / 16) * j.n_row_tiles *
+                const size_t ne = (size_t)tfs::mfma_units(j.n_mfma, j.at->bins16 / 16) * j.n_row_tiles *
                                   tfs::mfma_col_items(j.at->bins16 / 16, j.at->n_bins);
+                n_mfma_entries += ne;
+                if (tfs::mfma_cells_form(j.at->bins16 / 16)) n_cells_entries += ne;
             }
             max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
         } else {
@@ -1399,7 +1401,7 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     auto *rent = reinterpret_cast<int32_t *>(hptr(off_rent));
     size_t re = 0;
     int we = 0, se = 0, me = 0, ae = 0;
-    size_t mfe = 0;
+    size_t mfc = 0, mfe = n_cells_entries;   // next transposed-form and other matrix-core entry
     for (int32_t i = 0; i < n; ++i) {
         Job &j = *b->jobs[i];
         if (eidx[i] >= 0) {
@@ -1434,14 +1436,16 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
                 mfp[midx[i]] = mfma_rows_params(j, blk);
                 const int n_ct = tfs::mfma_col_items(j.at->bins16 / 16, j.at->n_bins);
                 const int n_u = tfs::mfma_units(j.n_mfma, j.at->bins16 / 16);
+                // the transposed form's items first (a launch of their own)
+                size_t &pos = tfs::mfma_cells_form(j.at->bins16 / 16) ? mfc : mfe;
                 for (int q = 0; q < n_u; ++q)
                     for (int rt = 0; rt < j.n_row_tiles; ++rt)
                         for (int ct = 0; ct < n_ct; ++ct) {
-                            ment[4 * mfe + 0] = midx[i];
-                            ment[4 * mfe + 1] = q;
-                            ment[4 * mfe + 2] = rt;
-                            ment[4 * mfe + 3] = ct;
-                            ++mfe;
+                            ment[4 * pos + 0] = midx[i];
+                            ment[4 * pos + 1] = q;
+                            ment[4 * pos + 2] = rt;
+                            ment[4 * pos + 3] = ct;
+                            ++pos;
                         }
             }
         } else {
@@ -1485,7 +1489,9 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
     b->rap.n_entries = (int32_t)n_rabc;
     b->mfp.jobs = reinterpret_cast<const tfs::ExpMfmaRowsParams *>(dptr(off_mfp));
     b->mfp.entries = reinterpret_cast<const int32_t *>(dptr(off_ment));
+    if (mfc != n_cells_entries || mfe != n_mfma_entries) raise(TFSTAT_E_INVAL, "internal: matrix-core entry count");
     b->mfp.n_entries = (int32_t)mfe;
+    b->mfp.n_cells = (int32_t)n_cells_entries;
     b->mfp.f16 = b->prec == TFSTAT_PREC_F16X3;
     b->mbp.jobs = reinterpret_cast<const tfs::MergeParams *>(dptr(off_mp));
     b->mbp.job = reinterpret_cast<const int32_t *>(dptr(off_mjob));

@@ -188,13 +188,17 @@ __host__ __device__ inline int32_t cells_plane_pitch(int32_t K) { return (K + 7)
 // Half-precision matrix-core weights are taken as w * 2^kF16WeightExp.
 constexpr int kF16WeightExp = 4;
 
-// Matrix-core work of many maps in one launch: entry e is {map, position in
-// the map's blk_list, 64-row tile, 16-bin column tile}.
+// Matrix-core work of many maps: entry e is {map, unit (position in the
+// map's blk_list, or group of kCellsBlocks of them), 64-row tile, column
+// item}; the transposed form's entries come first and take a launch of
+// their own.
 struct MfmaBatchParams {
     const ExpMfmaRowsParams *jobs;
     const int32_t *entries;   // [n_entries][4]
     int32_t n_entries;
     int32_t f16;              // every job's parts: 1 half, 0 bf16
+    int32_t n_cells;          // entries [0, n_cells): transposed form
+    int32_t pad0;
 };
 
 struct ShiftTableParams {
