@@ -1234,7 +1234,9 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
                 raise(TFSTAT_E_INVAL, "a batch runs no matrix-core shape windows (use tfstat_fmap)");
             shape[i] = job_shape(j);
             eidx[i] = n_exp++;
-            n_went += j.NB;
+            // weight tables: every block, except the matrix-core blocks of
+            // maps whose matrix-core kernels make their weights in registers
+            n_went += (j.use_mfma && j.mfma_rows) ? j.n_valu : j.NB;
             // A/B/C of every cell of split and matrix-core maps: the
             // recurrence for exponential windows, the VALU pass (every
             // block) for shape windows
@@ -1258,7 +1260,12 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
                 n_mfma_entries += ne;
                 if (tfs::mfma_cells_form(j.at->bins16 / 16)) n_cells_entries += ne;
             }
-            max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((j.max_blk + 255) / 256, 4096));
+            int64_t mb = j.max_blk;   // the largest table this map's entries make
+            if (j.use_mfma && j.mfma_rows) {
+                mb = 0;
+                for (int q = 0; q < j.n_valu; ++q) mb = std::max<int64_t>(mb, (int64_t)j.lblk[j.order[q]] * j.R);
+            }
+            max_chunks = std::max<int32_t>(max_chunks, (int32_t)std::min<int64_t>((mb + 255) / 256, 4096));
         } else {
             ridx[i] = n_rect++;
             n_scan += 1 + (4 * j.at->n_bins + 63) / 64;
@@ -1407,9 +1414,10 @@ bool batch_layout(tfstat_ctx *ctx, tfstat_batch *b, hipStream_t s, bool sync, bo
         if (eidx[i] >= 0) {
             ep[eidx[i]] = exp_params(j);
             wp[eidx[i]] = weight_params(j);
-            for (int nb = 0; nb < j.NB; ++nb) {
+            const bool regs = j.use_mfma && j.mfma_rows;
+            for (int q = 0; q < (regs ? j.n_valu : j.NB); ++q) {
                 wjob[we] = eidx[i];
-                wblk[we] = nb;
+                wblk[we] = regs ? j.order[q] : q;
                 ++we;
             }
             if (aidx[i] >= 0) {
