@@ -803,13 +803,16 @@ tfs::ExpMfmaRowsParams mfma_rows_params(Job &j, const int32_t *blk_list) {
 // Rows per segment of the A/B/C scan: one wave per (tau, segment), which
 // sums the segment's last window directly and scans its rows 64 at a time,
 // one dependent chunk after another.  More segments mean shorter chains
-// and more waves (and repeated direct sums); a map takes about 2048 waves,
-// in segments of whole 64-row chunks.
+// and more waves, and more direct sums; a map takes about 1024 waves, in
+// segments of whole 64-row chunks (on the 64-candidate batch the scan took
+// 0.76, 0.56, 0.49 and 0.45 ms at 8192, 2048, 1024 and 256 waves per map;
+// one map alone needs the waves to fill the GPU, and a map's segments, which
+// set its rounding, are the same alone and in a batch).
 int32_t abc_seg_rows(const Job &j) {
     const int64_t n_t0 = (int64_t)j.win.t0.size();
     const int64_t n_tau = std::max<int64_t>(1, (int64_t)j.win.tau.size());
     const int64_t chunks = std::max<int64_t>(1, (n_t0 + 63) / 64);
-    const int64_t n_seg = std::max<int64_t>(1, std::min<int64_t>((2048 + n_tau - 1) / n_tau, chunks));
+    const int64_t n_seg = std::max<int64_t>(1, std::min<int64_t>((1024 + n_tau - 1) / n_tau, chunks));
     return (int32_t)((chunks + n_seg - 1) / n_seg * 64);
 }
 
