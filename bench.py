@@ -17,7 +17,7 @@ The same JSON line also carries, unless --no-extras:
                  cores against the plain FP32 form, each with its 2F error
                  against the oracle on sampled cells;
   uneven_batch   64 uneven candidates as one batch (one captured graph, one
-                 persistent fused launch, one matrix-core launch) in FP32,
+                 persistent fused launch, the matrix-core launch) in FP32,
                  F16X3 and BF16X3, against one map per call;
   serving        a Poisson request stream (F16X3 requests) with continuous
                  batching, p50/p99, a load ramp and the sequential plain FP32

@@ -293,8 +293,9 @@ int tfstat_cancel(tfstat_ctx *ctx, tfstat_ticket t);
  * Serving admission.  Whenever one of the context's stream slots is free,
  * the requests at the head of the queue are admitted together: up to
  * max_batch of them (default 16), as many as the arena holds, run as one
- * batch with one persistent fused launch over all their tiles, plus one
- * matrix-core launch for BF16X3 / F16X3 requests (requests of one precision
+ * batch with one persistent fused launch over all their tiles, plus the
+ * matrix-core launches for BF16X3 / F16X3 requests (one for maps of 2 to 48
+ * bins, one for wider maps; requests of one precision
  * each, of up to 2e9 window terms -- cells x slots x bins, or cells x bins
  * for rectangular windows; larger requests, matrix-core shape windows and
  * recurrence requests run alone with their own kernels).  max_batch = 1
@@ -381,8 +382,8 @@ typedef struct {
     double tune_ms;           /* host time spent tuning (0 if not tuned here) */
     double last_ms;           /* device time of the last run (HIP events) */
     double last_fused_ms;     /* device time of the fused launch in the last timed run */
-    double last_mfma_ms;      /* device time of the matrix-core launch of BF16X3 maps in the
-                                 last timed run (0 without such maps) */
+    double last_mfma_ms;      /* device time of the matrix-core launches of BF16X3 / F16X3
+                                 maps in the last timed run (0 without such maps) */
 } tfstat_batch_stats;
 
 int tfstat_batch_create(tfstat_ctx *ctx, int32_t n_maps, const tfstat_atoms_id *ids,
