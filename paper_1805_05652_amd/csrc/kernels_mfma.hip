@@ -9,15 +9,20 @@
 // window).  The antenna atoms a^2, b^2, ab are shared by all bins, so the
 // data columns of all bins share one weight matrix: a dense contraction.
 //
-// Both operands are split into bf16 hi + lo parts (x = hi + lo + O(2^-16 x))
-// and three products W_hi X_hi + W_hi X_lo + W_lo X_hi are accumulated in
-// FP32.  A, B, C (FP64) come from the VALU kernel in its A/B/C-only mode.
+// Both operands are split into bf16 (or half-precision) hi + lo parts
+// (x = hi + lo + O(2^-16 x)) and three products W_hi X_hi + W_hi X_lo +
+// W_lo X_hi are accumulated in FP32.
 //
-// Work item: 64 consecutive t0 rows x 16 bins (64 data columns) x 8 taus,
-// in two passes of 4 taus.  Wave w owns rows 16w..16w+15; its four 16x16
-// output tiles per tau are the four data components of the same 16 bins, so
-// every lane ends with all four components of (row, bin) cells and
-// finalizes them in place.
+// Three kernels share this file.  Shape windows whose rows lie on
+// consecutive slots (exp_mfma_kernel) take the work item 64 consecutive t0
+// rows x 16 bins (64 data columns) x 8 taus, in two passes of 4 taus: wave
+// w owns rows 16w..16w+15, its four 16x16 output tiles per tau are the four
+// data components of the same 16 bins, so every lane ends with all four
+// components of (row, bin) cells and finalizes them in place; their A, B, C
+// (FP64) come from the VALU kernel in its A/B/C-only mode.  Exponential
+// windows on any t0 grid take the transposed work item (maps of 2 to 48
+// bins, mfma_cells_tile) or the shared-weight one (49 or more bins,
+// mfma_rows_tile_sw), described below, with A, B, C from the A/B/C scan.
 #include "tfstat_device.h"
 
 #include <hip/hip_runtime.h>
